@@ -106,8 +106,16 @@ def test_related_rhs_example_3(example):
     for j in range(1, 8):
         B[:, j] = B[:, j - 1] + 0.2 ** j * u[:, j]
     k1 = cg(op, B[:, 0], tol=1e-8)[1]
-    X, mv = related_rhs_solve(op, B, k1, 0, 1e-8)
+    X, mv, before = related_rhs_solve(op, B, k1, 0, 1e-8)
+    # the residual carried by step 3 stays the true residual of the carried guess
+    # (up to the converged residual of the system projected over)
+    for j in range(1, 8):
+        xb, rb = before[j]
+        assert np.linalg.norm(rb - (B[:, j] - op(xb))) <= 1e-7 * np.linalg.norm(B[:, j])
     rel = [np.linalg.norm(B[:, j] - op(X[:, j])) / np.linalg.norm(B[:, j]) for j in range(8)]
     assert max(rel) <= 1e-8
-    # later systems start from increasingly small residuals (Example 3)
+    # later systems start from increasingly small residuals (Example 3), and
+    # projecting over the CG corrections beats single seeding alone
     assert mv[-1] < mv[1] < k1
+    plain = seeded_solve(op, B, k1, 0, 1e-8)["iters"]
+    assert mv[-1] < 0.5 * plain[-1]

@@ -5,7 +5,7 @@ import scipy.linalg
 
 from oracle import operators as ops
 from oracle.cg import cg
-from oracle.seed import project, seed_lanczos, seed_x1, tridiag_dense, tridiag_lu_solve
+from oracle.seed import _reorthogonalize, project, seed_lanczos, seed_x1, tridiag_dense, tridiag_lu_solve
 from paper_0810_0330_amd import synth
 
 
@@ -168,3 +168,24 @@ def test_not_pd_detected():
     d = -np.linspace(1, 2, 100)
     res = seed_lanczos(ops.DiagOp(d), np.ones((100, 1)), m=10)
     assert res.status == "not_pd"
+
+
+def test_reorthogonalization_step_semantics():
+    # step 8 on inputs with O(1) overlaps: v_i re-orthonormalised against
+    # v_1..v_{i-1}, f orthogonalised against v_1..v_i (the new v_i included)
+    gen = np.random.default_rng(12)
+    n, i = 40, 6
+    q, _ = np.linalg.qr(gen.standard_normal((n, i - 1)) + 1j * gen.standard_normal((n, i - 1)))
+    V = np.zeros((n, i + 1), dtype=np.complex128)
+    V[:, : i - 1] = q
+    V[:, i - 1] = gen.standard_normal(n) + 1j * gen.standard_normal(n)
+    f = gen.standard_normal(n) + 1j * gen.standard_normal(n)
+    f_out = _reorthogonalize(V, i, f.copy())
+    vi = V[:, i - 1]
+    assert abs(np.linalg.norm(vi) - 1) < 1e-14
+    assert np.abs(q.conj().T @ vi).max() < 1e-14
+    assert np.abs(V[:, :i].conj().T @ f_out).max() < 1e-13
+    # f only lost components inside span(v_1..v_i)
+    resid = f - f_out
+    coef = np.linalg.lstsq(V[:, :i], resid, rcond=None)[0]
+    assert np.linalg.norm(V[:, :i] @ coef - resid) < 1e-12
