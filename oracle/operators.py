@@ -135,17 +135,18 @@ def _shift_bwd(psi, mu, antiperiodic):
 
 
 def _colour(u, chi):
-    # (u chi)_{s,c} = sum_d u_{c,d} chi_{s,d}
-    return np.einsum("...cd,...sd->...sc", u, chi)
+    # (u chi)_{s,c} = sum_d u_{c,d} chi_{s,d}, i.e. chi u^T per site
+    return np.matmul(chi, np.swapaxes(u, -1, -2))
 
 
 def _colour_dag(u, chi):
-    # (u^H chi)_{s,c} = sum_d conj(u_{d,c}) chi_{s,d}
-    return np.einsum("...dc,...sd->...sc", u.conj(), chi)
+    # (u^H chi)_{s,c} = sum_d conj(u_{d,c}) chi_{s,d}, i.e. chi conj(u) per site
+    return np.matmul(chi, u.conj())
 
 
 def _spin(p, chi):
-    return np.einsum("ab,...bc->...ac", p, chi)
+    # (p chi)_{a,c} = sum_b p_{a,b} chi_{b,c}
+    return np.matmul(p, chi)
 
 
 def wilson_hop(psi, U, antiperiodic=True, dagger=False):

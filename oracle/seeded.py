@@ -54,7 +54,8 @@ def related_rhs_solve(apply_a, B, m, freq, tol, maxit=100000):
     Step 2 uses the Lanczos seed (m steps, reorthogonalization frequency freq)
     and finishes system 1 with CG if needed.  After each system j is solved, its
     CG correction x_cg = x^j - x^j_bcg seeds every later system by a Galerkin
-    projection over that single vector.  Returns (X, mvps per RHS).
+    projection over that single vector.  Returns (X, mvps per RHS, before_cg)
+    where before_cg[j] = (x^j_bcg, r^j_bcg), the state each system's CG started from.
     """
     B = np.asarray(B)
     n, nrhs = B.shape
@@ -71,11 +72,13 @@ def related_rhs_solve(apply_a, B, m, freq, tol, maxit=100000):
     # step 1: x_bcg^1 = 0, r_bcg^1 = b^1
     x_bcg = np.zeros(n, dtype=dtype)
     r_bcg = B[:, 0].astype(dtype)
+    before_cg = [(x_bcg.copy(), r_bcg.copy())]
     for j in range(nrhs):
         if j > 0:
             # step 4: the next system starts from its current guess
             x_bcg = X[:, j].copy()
             r_bcg = R[:, j].copy()
+            before_cg.append((x_bcg.copy(), r_bcg.copy()))
             x, it, _ = cg(apply_a, B[:, j], x_bcg, tol, maxit)
             X[:, j] = x
             mvps.append(it)
@@ -88,7 +91,7 @@ def related_rhs_solve(apply_a, B, m, freq, tol, maxit=100000):
             d = np.vdot(x_cg, R[:, i]) / den
             X[:, i] = X[:, i] + d * x_cg
             R[:, i] = R[:, i] - d * r_bcg
-    return X, mvps
+    return X, mvps, before_cg
 
 
 def multiple_seed_solve(apply_a, B, tol, maxit=100000):
