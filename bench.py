@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark of the single-seed Lanczos-CG solver on one MI355X.
+
+One step = one whole seeded solve of a batch of right-hand sides: the seed
+phase on right-hand side 1 (Lanczos-CG run for m steps with reorthogonalization
+every `freq` steps), the projection of the other right-hand sides over the
+stored basis, and the mixed-precision CG that finishes every right-hand side to
+a true FP64 relative residual <= tol.  Inputs are synthetic and already
+resident in HBM when the timed region starts.
+
+Metric: right-hand sides solved per second.  Beside it the same right-hand
+sides are solved by plain per-RHS FP64 CG on the same GPU, the main kernels are
+timed with HIP events inside the timed region (algorithmic bytes / time against
+the 8 TB/s HBM peak), and the FP64 CPU oracle is timed on a bounded sample on
+the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+METRIC = "RHS solved/sec at rel.res 1e-8 (seeded vs plain CG); stencil HBM GB/s"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="wilson_16x3x32", choices=["wilson_16x3x32", "wilson_8x4", "laplace_32x32"])
+    ap.add_argument("--m", type=int, default=None)
+    ap.add_argument("--freq", type=int, default=None)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timer", action="store_true", help="do not record per-kernel events")
+    return ap.parse_args()
+
+
+def workload(args):
+    from paper_0810_0330_amd import synth
+    if args.workload == "wilson_16x3x32":
+        w = synth.wilson_16x3x32()
+    elif args.workload == "wilson_8x4":
+        w = synth.wilson_8x4(m=150)
+        w.precision = "mixed"
+    else:
+        w = synth.laplace_32x32()
+    if args.m is not None:
+        w.m = args.m
+    if args.freq is not None:
+        w.freq = args.freq
+    return w
+
+
+def cpu_baseline(w, inp, counts):
+    """Time the FP64 oracle on a bounded sample and scale it to the whole solve.
+
+    Sample: 4 oracle A-applies and 8 oracle length-n vector updates on the same
+    lattice.  The full oracle solve is priced with this step's own counts: one
+    A-apply per Lanczos step and per CG iteration (+1 per right-hand side for
+    the initial and final residuals), and one vector update per stored basis
+    vector touched by the reorthogonalizations and the projection.
+    """
+    import numpy as np
+
+    from oracle import operators as ops
+    from oracle.cg import cg  # noqa: F401  (the oracle's CG is what the counts price)
+
+    if w.op == "laplace2d":
+        op = ops.Laplace2DOp(*w.dims)
+    else:
+        op = ops.WilsonNormalOp(inp["U"], w.kappa)
+    b = inp["B"][:, 0].copy()
+    t0 = time.perf_counter()
+    napply = 4
+    for _ in range(napply):
+        b = op(b) / np.linalg.norm(b)
+    t_apply = (time.perf_counter() - t0) / napply
+    v = inp["B"][:, 1].astype(np.complex128 if w.op != "laplace2d" else np.float64)
+    y = v.copy()
+    t0 = time.perf_counter()
+    nvec = 8
+    for _ in range(nvec):
+        c = np.vdot(v, y)
+        y = y - (c / (np.vdot(v, v) + 1.0)) * v
+    t_vec = (time.perf_counter() - t0) / nvec
+    t_total = counts["applies"] * t_apply + counts["vector_passes"] * t_vec
+    return {
+        "value": w.nrhs / t_total,
+        "unit": "RHS/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{napply} oracle A-applies ({t_apply * 1e3:.1f} ms each) and {nvec} vector updates "
+                   f"({t_vec * 1e3:.2f} ms each) on the benchmark lattice, scaled by this run's counts: "
+                   f"{counts['applies']} A-applies, {counts['vector_passes']} basis-vector passes "
+                   f"(extrapolated; numpy stencil runs on one thread)"),
+    }
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "bench.py measures one GPU only; the multi-GPU path is design-only "
+                                   "(lattice domain decomposition, see DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0810_0330_amd import api, synth
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    w = workload(args)
+    log(f"[bench] workload {w.name}: dims {w.dims} nrhs {w.nrhs} m {w.m} freq {w.freq} tol {w.tol} {w.precision}")
+    t0 = time.perf_counter()
+    inp = synth.make_inputs(w)
+    if w.op == "laplace2d":
+        op = api.Op.laplace2d(*w.dims)
+        B = torch.from_numpy(np.ascontiguousarray(inp["B"].T)).to(dev)
+    else:
+        op = api.Op.wilson(w.dims, torch.from_numpy(api.pack_links(inp["U"])).to(dev), w.kappa)
+        B = torch.from_numpy(api.pack_field(np.ascontiguousarray(inp["B"].T))).to(dev)
+    torch.cuda.synchronize()
+    log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f} s, n = {op.n}")
+    mixed = w.precision == "mixed"
+
+    def step():
+        return api.seeded_solve(op, B, w.m, w.freq, w.tol, mixed=mixed)
+
+    for i in range(args.warmup):
+        out = step()
+        log(f"[bench] warmup {i}: iters {out['iters']} max relres {max(out['relres']):.2e}")
+    stream = torch.cuda.current_stream()
+    if not args.no_timer:
+        api.timer_enable(True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t_wall = time.perf_counter()
+    outs = []
+    for i in range(args.steps):
+        outs.append(step())
+        log(f"[bench] step {i} done")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t_wall) * 1e3
+    ms = e0.elapsed_time(e1)
+    kern = api.timer_read() if not args.no_timer else {}
+    api.timer_enable(False)
+    ms_per_step = max(ms, wall_ms) / args.steps
+    out = outs[-1]
+    relres = out["relres"]
+    assert max(relres) <= w.tol, f"not converged: {relres}"
+    value = w.nrhs / (ms_per_step / 1e3)
+    log(f"[bench] {ms_per_step:.1f} ms/step -> {value:.1f} RHS/s; iters {out['iters']}")
+
+    # ---- plain per-RHS FP64 CG on the same GPU
+    plain = None
+    if not args.no_plain:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        pits = []
+        for j in range(w.nrhs):
+            _, it, rr = api.solve_cg(op, B[j:j + 1], w.tol, mixed=False)
+            assert rr[0] <= w.tol
+            pits.append(it[0])
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        plain = {"rhs_per_s": w.nrhs / tp, "ms": tp * 1e3, "iters": pits, "dtype": "f64"}
+        log(f"[bench] plain FP64 CG: {tp * 1e3:.1f} ms, {plain['rhs_per_s']:.1f} RHS/s, iters {pits}")
+
+    # ---- roofline of the dominant kernel class
+    roof = None
+    kernels = {}
+    for name, k in kern.items():
+        if k["launches"] == 0:
+            continue
+        avg_ms = k["ms"] / k["launches"]
+        kernels[name] = {"launches": k["launches"], "ms_total": round(k["ms"], 3), "avg_us": round(avg_ms * 1e3, 2),
+                         "GBps": round(k["bytes"] / (k["ms"] * 1e-3) / 1e9, 1),
+                         "TFLOPs": round(k["flops"] / (k["ms"] * 1e-3) / 1e12, 3),
+                         "bytes_per_launch": k["bytes"] / k["launches"]}
+    if kernels:
+        dom = max(kernels, key=lambda n: kernels[n]["ms_total"])
+        kd = kernels[dom]
+        achieved = kd["GBps"]
+        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": kd["avg_us"], "bytes_per_launch": kd["bytes_per_launch"]}
+
+    # ---- oracle on the host
+    cpu = None
+    if not args.no_cpu_baseline:
+        n_seed = out["basis"].m_done
+        cg_its = sum(out["cg_iters"])
+        freq = max(w.freq, 1)
+        reorth_vecs = sum(2 * (i - 1) for i in range(freq, n_seed + 1, freq)) if w.freq > 0 else 0
+        counts = {"applies": n_seed + 1 + cg_its + 2 * w.nrhs,
+                  "vector_passes": reorth_vecs + 2 * n_seed * (w.nrhs - 1) + 8 * n_seed + 6 * cg_its}
+        t = time.perf_counter()
+        cpu = cpu_baseline(w, inp, counts)
+        log(f"[bench] cpu baseline ({time.perf_counter() - t:.1f} s): {cpu['value']:.4f} RHS/s")
+
+    res = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "RHS/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "dims": list(w.dims), "nrhs": w.nrhs, "m": w.m, "freq": w.freq,
+                   "tol": w.tol, "kappa": w.kappa, "precision": w.precision},
+        "iters": out["iters"],
+        "max_relres": max(relres),
+        "plain_cg": plain,
+        "speedup_vs_plain": round(value / plain["rhs_per_s"], 3) if plain else None,
+        "roofline": roof,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * seedcg.h -- C ABI of the single-seed Lanczos-CG library for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The method (Abdel-Rehim, Morgan, Wilcox, "Improved seed methods for
+ * symmetric positive definite linear equations with multiple right-hand
+ * sides", Sections 1-3) solves A x^j = b^j, j = 1..nrhs, for Hermitian positive
+ * definite A in three calls:
+ *
+ *   sc_seed_lanczos  Lanczos version of CG on right-hand side 1, run for a
+ *                    fixed number of steps m (past convergence), with
+ *                    periodic reorthogonalization; keeps the basis V and the
+ *                    tridiagonal T (Section 3 algorithm, steps 1-9).
+ *   sc_project       Galerkin projection of the other right-hand sides over
+ *                    the stored basis, X += V T^{-1} V^H R0 (the seeding of
+ *                    steps 4 and 7, done in one batched pass).
+ *   sc_solve_cg      CG on each seeded system from its projected guess
+ *                    (Section 2.2), batched over right-hand sides.
+ *
+ * Conventions common to every call
+ * --------------------------------
+ *  - Pointers named *_dev are device pointers (HBM of the current HIP device),
+ *    allocated and owned by the caller.  The library never allocates device
+ *    memory; scratch space is the caller's `work` buffer, sized by
+ *    sc_workspace_size().  Host pointers are named explicitly.
+ *  - Vectors are columns: column j of an n-row matrix starts at element j*ld
+ *    (ld >= n, counted in elements of the matrix's dtype).  Complex numbers
+ *    are interleaved (re, im) pairs.
+ *  - Field layout of the Wilson operator (a data format): element
+ *    (spin s, colour c, site x) of a spinor column is at index
+ *    (s*3 + c)*V + x, V = X*Y*Z*T, x = x0 + X*(x1 + Y*(x2 + Z*x3)).
+ *    Links: complex U_mu(x)[a][b] at index ((mu*3 + a)*3 + b)*V + x.
+ *    Gamma matrices are Hermitian in the chiral basis with
+ *    gamma_5 = diag(1, 1, -1, -1).
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *    it; calls that return host results (m_done, iters, relres) synchronise
+ *    the stream before returning.
+ *  - Every call validates its arguments before touching the device; on an
+ *    argument error nothing is written.  Nothing throws or aborts across the
+ *    ABI.  Device-detected conditions are reported after the call's sync.
+ *    sc_last_error() describes the last failure on the calling thread.
+ *  - Calls on one stream are ordered; concurrent calls that share a `work`
+ *    buffer race.
+ */
+#ifndef SEEDCG_H
+#define SEEDCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SC_R64 = 0,   /* real double */
+    SC_C64 = 1,   /* complex float  (2 x float) */
+    SC_C128 = 2,  /* complex double (2 x double) */
+    SC_R32 = 3    /* real float */
+} sc_dtype;
+
+typedef enum {
+    SC_OK = 0,
+    SC_NOT_CONVERGED = 1,   /* result usable; some right-hand side above tol at maxit */
+    SC_BREAKDOWN = 2,       /* Lanczos found an invariant subspace; *m_done < m, results exact on it */
+    SC_ERR_ARG = -1,
+    SC_ERR_HIP = -2,
+    SC_ERR_NOT_PD = -3,     /* a non-positive LU pivot of T: A is not positive definite */
+    SC_ERR_NONFINITE = -4,  /* NaN or Inf met in a norm */
+    SC_ERR_WORKSPACE = -5,  /* work buffer smaller than sc_workspace_size() */
+    SC_ERR_UNSUPPORTED = -6 /* valid request this build does not implement */
+} sc_status;
+
+typedef struct sc_op sc_op;   /* opaque; immutable after creation */
+
+/* ------------------------------------------------------------------ operators
+ * The A-apply that drives every step (Section 1: A is real symmetric or
+ * complex Hermitian and positive definite).
+ */
+
+/* Unscaled 2D five-point Laplacian with zero Dirichlet boundary on an nx-by-ny
+ * grid: (A x)_{i,j} = 4 x_{i,j} - x_{i+-1,j} - x_{i,j+-1}.  Vectors: SC_R64
+ * (or SC_R32 for the single-precision paths), index i + nx*j.
+ * Errors: SC_ERR_ARG if nx or ny < 1 or out is NULL. */
+sc_status sc_op_laplace2d(int nx, int ny, sc_op** out);
+
+/* Diagonal A = diag(d) (the matrices of the paper's Examples 1-5).  d_dev:
+ * n doubles, positive for an HPD A, owned by the caller and kept alive for the
+ * op's lifetime.  Vectors: SC_R64 / SC_R32. */
+sc_status sc_op_diag(const double* d_dev, int64_t n, sc_op** out);
+
+/* A = D^H D with the Wilson-Dirac matrix (Section 4 solves the normal
+ * equations, two products with D per CG iteration):
+ *   (D psi)(x) = psi(x) - kappa sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                                      + (1 + gamma_mu) U_mu(x-mu)^H psi(x-mu) ]
+ * dims = {X, Y, Z, T}; periodic in x, y, z; antiperiodic in t when
+ * t_antiperiodic != 0.  U64_dev: 4*9*V complex doubles in the link layout
+ * above (required).  U32_dev: the same links as complex floats (optional,
+ * NULL allowed; needed by the single-precision paths).  Both are held by
+ * reference.  Vectors: SC_C128 (or SC_C64), length n = 12*V.
+ * Errors: SC_ERR_ARG on a dimension < 1, a NULL U64_dev, or kappa not finite. */
+sc_status sc_op_wilson_normal(const int dims[4], const void* U64_dev, const void* U32_dev,
+                              double kappa, int t_antiperiodic, sc_op** out);
+
+sc_status sc_op_destroy(sc_op* op);
+
+/* Vector length n and the op's full-precision dtype (SC_R64 or SC_C128). */
+sc_status sc_op_info(const sc_op* op, int64_t* n, sc_dtype* dtype);
+
+/* Y = A X for k columns.  dtype is the op's dtype or its single-precision
+ * counterpart (SC_R32 / SC_C64; Wilson needs U32_dev).  Needs
+ * sc_workspace_size(op, SC_CALL_APPLY, k, 0, dtype) bytes of work. */
+sc_status sc_op_apply(const sc_op* op, sc_dtype dtype, const void* X_dev, int64_t ldx,
+                      void* Y_dev, int64_t ldy, int k, void* work_dev, size_t work_bytes,
+                      void* stream);
+
+/* One Wilson stencil pass for k columns (no workspace):
+ * which = 0: Y = D X, 1: Y = D^H X, 2: Y = H X, 3: Y = H^H X,
+ * where D = 1 - kappa H (H, the hopping term, gives dD/dkappa = -H).
+ * Errors: SC_ERR_ARG for a non-Wilson op or which outside 0..3. */
+sc_status sc_wilson_dslash(const sc_op* op, sc_dtype dtype, int which, const void* X_dev,
+                           int64_t ldx, void* Y_dev, int64_t ldy, int k, void* stream);
+
+/* ------------------------------------------------------------------ workspace */
+typedef enum {
+    SC_CALL_APPLY = 0,
+    SC_CALL_SEED = 1,
+    SC_CALL_PROJECT = 2,
+    SC_CALL_CG = 3
+} sc_call;
+
+/* Bytes of `work` needed by a call.  k: right-hand sides per call; m: basis
+ * size (seed, project); dtype: vector dtype of the call (for SC_CALL_CG pass
+ * the op dtype and set k; the mixed-precision solver needs the same query with
+ * the single-precision dtype).  For SC_CALL_PROJECT op may be NULL when n is
+ * passed through *bytes on entry (in: n, out: bytes). */
+sc_status sc_workspace_size(const sc_op* op, int call, int k, int m, sc_dtype dtype, size_t* bytes);
+
+/* ------------------------------------------------------------------ seed phase
+ * Lanczos version of CG on right-hand side 1 (Section 3 algorithm, steps 1-9),
+ * run for exactly m steps, with the readings:
+ *   - alpha_i = Re(v_i^H f); T_m is real symmetric tridiagonal;
+ *   - step 8 (when i is a multiple of reorth_freq, i >= 2; 0 = never,
+ *     1 = every step) is one pass of classical Gram-Schmidt: v_i and f
+ *     against v_1..v_{i-1}, renormalise v_i, then f against the new v_i;
+ *     alpha and beta keep their recurrence values;
+ *   - breakdown when beta_i <= 1e-12 * max_k |alpha_k|.
+ * b1_dev: right-hand side 1 in the op dtype.  x1_dev (op dtype): in, the
+ * initial guess (zeros allowed); out, x0 + V_m T_m^{-1} (beta_0 e_1), the
+ * Lanczos-CG iterate after m_done steps.
+ * V_dev: n x (m+1) basis, column i-1 = v_i, leading dimension ldv >= n, dtype
+ * v_dtype: the op dtype (all-FP64 arithmetic) or its single-precision
+ * counterpart (FP32 vectors and storage; FP64 dot products, recurrences and
+ * reorthogonalization sums).
+ * alpha_dev: m doubles (alpha_1..alpha_m); beta_dev: m+1 doubles
+ * (beta_0..beta_m).  m_done (host): steps completed.
+ * Returns SC_OK, SC_BREAKDOWN (m_done < m), SC_ERR_NOT_PD (m_done = the last
+ * step with a positive pivot), SC_ERR_NONFINITE, or an argument/HIP error.
+ * Synchronises `stream` once, at the end. */
+sc_status sc_seed_lanczos(const sc_op* op, const void* b1_dev, void* x1_dev, int m, int reorth_freq,
+                          void* V_dev, int64_t ldv, sc_dtype v_dtype, double* alpha_dev,
+                          double* beta_dev, int* m_done, void* work_dev, size_t work_bytes,
+                          void* stream);
+
+/* ------------------------------------------------------------------ projection
+ * X += V_m T_m^{-1} V_m^H R0 for k columns: the Galerkin projection over the
+ * stored basis that seeds right-hand sides 2..nrhs (steps 4 and 7 in batched
+ * form).  T_m has diagonal alpha_1..alpha_m and off-diagonal beta_1..beta_{m-1}
+ * and is solved with the LU recurrences of step 6 (no pivoting).
+ * V_dev: n x m, ldv, v_dtype (SC_C128/SC_C64 or SC_R64/SC_R32).
+ * R0_dev, X_dev: n x k in vec_dtype (SC_C128 or SC_R64; the full-precision
+ * type matching V).  Sums are accumulated in FP64.  Asynchronous. */
+sc_status sc_project(int64_t n, const void* V_dev, int64_t ldv, sc_dtype v_dtype, int m,
+                     const double* alpha_dev, const double* beta_dev, sc_dtype vec_dtype,
+                     const void* R0_dev, int64_t ldr, int k, void* X_dev, int64_t ldx,
+                     void* work_dev, size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------ CG
+ * Plain CG (Hestenes-Stiefel) on each of k columns, batched: B_dev and X_dev
+ * (in: guesses, out: solutions) are n x k in the op dtype.  Stops each column
+ * when its recursively updated residual satisfies ||r|| <= tol ||b||, then
+ * recomputes the true residual and restarts from it (at most 5 times) while
+ * it is above tol.  One iteration = one A-apply.
+ * mixed = 0: FP64 throughout.  mixed = 1: FP32 vectors and operator with FP64
+ * reliable updates: x and the true residual b - A x are kept in FP64 and
+ * recomputed whenever the FP32 residual has fallen by 10x since the last
+ * update, and at FP32 convergence; a column is converged only when its FP64
+ * true residual is <= tol.  (Wilson needs U32_dev.)
+ * iters (host, k ints), relres (host, k doubles: true relative residuals).
+ * Returns SC_OK or SC_NOT_CONVERGED.  Synchronises once per chunk of
+ * iterations. */
+sc_status sc_solve_cg(const sc_op* op, int mixed, const void* B_dev, int64_t ldb, void* X_dev,
+                      int64_t ldx, int k, double tol, int maxit, int* iters, double* relres,
+                      void* work_dev, size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------ timing
+ * Optional event timing of the library's main kernels, for benchmarks (not
+ * part of the method).  sc_timer_enable(1) clears earlier records and, from
+ * then on, brackets every launch of the classes below with two HIP events on
+ * the launch's own stream, recording the launch's algorithmic bytes and flops;
+ * sc_timer_enable(0) stops recording.  sc_timer_read(cls, ...) waits for the
+ * recorded events and returns, for class cls, the summed kernel time (ms),
+ * the number of launches and the summed algorithmic bytes and flops:
+ *   0  Wilson stencil pass, FP32: (48k + 72)*4 bytes and 1368k (D, D^H) or
+ *      1320k (H, H^H) flops per site for k columns;
+ *   1  Wilson stencil pass, FP64: (48k + 72)*8 bytes per site, same flops;
+ *   2  G = V^H W: V, W read once, G written; 8 n M N flops (complex);
+ *   3  X += V Y:  V read once, X read and written; 8 n M N flops (complex).
+ * Errors: SC_ERR_ARG for an unknown class or a NULL pointer. */
+sc_status sc_timer_enable(int on);
+sc_status sc_timer_read(int cls, double* ms, int64_t* launches, double* bytes, double* flops);
+
+/* Description of the last failure on the calling thread (valid until the next
+ * call on that thread); "" when the last call succeeded. */
+const char* sc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEEDCG_H */

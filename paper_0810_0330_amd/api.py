@@ -1,0 +1,334 @@
+"""Python binding of the C ABI in include/seedcg.h (argument marshalling only).
+
+Every step of the solver runs in the HIP library ``libseedcg.so``; this module
+only turns torch tensors into device pointers, sizes workspaces and converts
+status codes into exceptions.  It fails loudly when the library is missing or
+no GPU is present: there is no CPU fallback.
+
+Vectors are rows of 2-D tensors: a batch of k vectors of length n is a
+contiguous (k, n) tensor, i.e. the column-major n x k matrix of the C ABI with
+ld = n.  Wilson vectors use the library field layout (``pack_field``).
+
+The method (Abdel-Rehim, Morgan, Wilcox): ``seed_lanczos`` runs the Lanczos
+version of CG on right-hand side 1 past convergence with periodic
+reorthogonalization (Section 3 algorithm), ``project`` seeds the other
+right-hand sides by a Galerkin projection over the stored basis, and
+``solve_cg`` finishes them with CG (Section 2.2).  ``seeded_solve`` chains the
+three.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libseedcg.so")
+
+SC_R64, SC_C64, SC_C128, SC_R32 = 0, 1, 2, 3
+SC_CALL_APPLY, SC_CALL_SEED, SC_CALL_PROJECT, SC_CALL_CG = 0, 1, 2, 3
+STATUS = {0: "SC_OK", 1: "SC_NOT_CONVERGED", 2: "SC_BREAKDOWN", -1: "SC_ERR_ARG", -2: "SC_ERR_HIP",
+          -3: "SC_ERR_NOT_PD", -4: "SC_ERR_NONFINITE", -5: "SC_ERR_WORKSPACE", -6: "SC_ERR_UNSUPPORTED"}
+
+_TORCH_DT = {SC_R64: torch.float64, SC_R32: torch.float32, SC_C128: torch.complex128, SC_C64: torch.complex64}
+_DT_OF = {v: k for k, v in _TORCH_DT.items()}
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_INT = ctypes.c_int
+_DBL = ctypes.c_double
+_SZ = ctypes.c_size_t
+
+_PROTOS = {
+    "sc_op_laplace2d": [_INT, _INT, ctypes.POINTER(_P)],
+    "sc_op_diag": [_P, _I64, ctypes.POINTER(_P)],
+    "sc_op_wilson_normal": [ctypes.POINTER(_INT), _P, _P, _DBL, _INT, ctypes.POINTER(_P)],
+    "sc_op_destroy": [_P],
+    "sc_op_info": [_P, ctypes.POINTER(_I64), ctypes.POINTER(_INT)],
+    "sc_op_apply": [_P, _INT, _P, _I64, _P, _I64, _INT, _P, _SZ, _P],
+    "sc_wilson_dslash": [_P, _INT, _INT, _P, _I64, _P, _I64, _INT, _P],
+    "sc_workspace_size": [_P, _INT, _INT, _INT, _INT, ctypes.POINTER(_SZ)],
+    "sc_seed_lanczos": [_P, _P, _P, _INT, _INT, _P, _I64, _INT, _P, _P, ctypes.POINTER(_INT), _P, _SZ, _P],
+    "sc_project": [_I64, _P, _I64, _INT, _INT, _P, _P, _INT, _P, _I64, _INT, _P, _I64, _P, _SZ, _P],
+    "sc_solve_cg": [_P, _INT, _P, _I64, _P, _I64, _INT, _DBL, _INT, ctypes.POINTER(_INT), ctypes.POINTER(_DBL),
+                    _P, _SZ, _P],
+    "sc_timer_enable": [_INT],
+    "sc_timer_read": [_INT, ctypes.POINTER(_DBL), ctypes.POINTER(_I64), ctypes.POINTER(_DBL), ctypes.POINTER(_DBL)],
+    "sc_last_error": [],
+}
+
+_lib = None
+
+
+class SeedCGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libseedcg.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_0810_0330_amd.build`")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, args in _PROTOS.items():
+            f = getattr(l, name)
+            f.argtypes = args
+            f.restype = ctypes.c_char_p if name == "sc_last_error" else ctypes.c_int
+        _lib = l
+    return _lib
+
+
+def _check(status, ok=(0,)):
+    if status not in ok:
+        raise SeedCGError(status, lib().sc_last_error().decode())
+    return status
+
+
+def _require_gpu(t=None):
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_0810_0330_amd needs a ROCm GPU: no device is visible")
+    if t is not None and not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+_work_cache = {}
+
+
+def _work(nbytes, device):
+    key = (str(device),)
+    buf = _work_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        _work_cache[key] = buf
+    return buf
+
+
+def release_workspace():
+    _work_cache.clear()
+
+
+# ----------------------------------------------------------------------------- timing
+TIMER_CLASSES = {0: "wilson_f32", 1: "wilson_f64", 2: "gemm_cn", 3: "gemm_nn"}
+
+
+def timer_enable(on=True):
+    _check(lib().sc_timer_enable(1 if on else 0))
+
+
+def timer_read():
+    """{class name: dict(ms, launches, bytes, flops)} for the launches recorded since timer_enable(True)."""
+    out = {}
+    for cls, name in TIMER_CLASSES.items():
+        ms, nl, by, fl = _DBL(), _I64(), _DBL(), _DBL()
+        _check(lib().sc_timer_read(cls, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(by), ctypes.byref(fl)))
+        out[name] = {"ms": ms.value, "launches": nl.value, "bytes": by.value, "flops": fl.value}
+    return out
+
+
+# ----------------------------------------------------------------------------- layouts
+def pack_field(psi):
+    """Natural spinor layout (..., V*12) site-major -> library layout (s*3+c)*V + x."""
+    shp = psi.shape
+    v = shp[-1] // 12
+    if isinstance(psi, np.ndarray):
+        return np.ascontiguousarray(np.swapaxes(psi.reshape(shp[:-1] + (v, 12)), -1, -2)).reshape(shp)
+    return psi.reshape(shp[:-1] + (v, 12)).transpose(-1, -2).contiguous().reshape(shp)
+
+
+def unpack_field(psi):
+    """Library layout -> natural site-major layout."""
+    shp = psi.shape
+    v = shp[-1] // 12
+    if isinstance(psi, np.ndarray):
+        return np.ascontiguousarray(np.swapaxes(psi.reshape(shp[:-1] + (12, v)), -1, -2)).reshape(shp)
+    return psi.reshape(shp[:-1] + (12, v)).transpose(-1, -2).contiguous().reshape(shp)
+
+
+def pack_links(U):
+    """Links (4, T, Z, Y, X, 3, 3) -> library layout ((mu*3+a)*3+b)*V + x, flat."""
+    if isinstance(U, np.ndarray):
+        return np.ascontiguousarray(np.moveaxis(U, (5, 6), (1, 2))).reshape(-1)
+    return U.permute(0, 5, 6, 1, 2, 3, 4).contiguous().reshape(-1)
+
+
+# ----------------------------------------------------------------------------- operators
+class Op:
+    """An HPD operator A held by the library (keeps its device arrays alive)."""
+
+    def __init__(self, handle, keep, device, kind, dims=None, kappa=None, antiperiodic=True):
+        self._h = handle
+        self._keep = keep
+        self.device = device
+        self.kind = kind
+        self.dims = dims
+        self.kappa = kappa
+        self.antiperiodic = antiperiodic
+        n = _I64()
+        dt = _INT()
+        _check(lib().sc_op_info(self._h, ctypes.byref(n), ctypes.byref(dt)))
+        self.n = n.value
+        self.sc_dtype = dt.value
+        self.dtype = _TORCH_DT[dt.value]
+        self.single_dtype = torch.complex64 if dt.value == SC_C128 else torch.float32
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().sc_op_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    @classmethod
+    def laplace2d(cls, nx, ny, device="cuda"):
+        _require_gpu()
+        h = _P()
+        _check(lib().sc_op_laplace2d(int(nx), int(ny), ctypes.byref(h)))
+        return cls(h, [], torch.device(device), "laplace2d", dims=(nx, ny))
+
+    @classmethod
+    def diag(cls, d):
+        _require_gpu(d)
+        d = d.to(torch.float64).contiguous()
+        h = _P()
+        _check(lib().sc_op_diag(_ptr(d), d.numel(), ctypes.byref(h)))
+        return cls(h, [d], d.device, "diag")
+
+    @classmethod
+    def wilson(cls, dims, U, kappa, antiperiodic=True, single=True):
+        """A = D^H D.  dims = (X, Y, Z, T); U: links in the library layout (pack_links), complex128 on the GPU."""
+        _require_gpu(U)
+        U64 = U.to(torch.complex128).contiguous()
+        U32 = U64.to(torch.complex64) if single else None
+        d = (ctypes.c_int * 4)(*[int(v) for v in dims])
+        h = _P()
+        _check(lib().sc_op_wilson_normal(d, _ptr(U64), _ptr(U32) if U32 is not None else None, float(kappa),
+                                         1 if antiperiodic else 0, ctypes.byref(h)))
+        return cls(h, [U64, U32], U64.device, "wilson", dims=tuple(dims), kappa=float(kappa),
+                   antiperiodic=antiperiodic)
+
+    def _vec(self, X, dtype):
+        if X.dim() == 1:
+            X = X.reshape(1, -1)
+        if X.shape[-1] != self.n:
+            raise ValueError(f"vector length {X.shape[-1]} != n = {self.n}")
+        return X.to(device=self.device, dtype=dtype).contiguous()
+
+    def apply(self, X, single=False):
+        """Y = A X for the rows of X."""
+        dt = self.single_dtype if single else self.dtype
+        X = self._vec(X, dt)
+        Y = torch.empty_like(X)
+        sdt = _DT_OF[dt]
+        nb = _SZ()
+        _check(lib().sc_workspace_size(self._h, SC_CALL_APPLY, X.shape[0], 0, sdt, ctypes.byref(nb)))
+        w = _work(nb.value, self.device)
+        _check(lib().sc_op_apply(self._h, sdt, _ptr(X), self.n, _ptr(Y), self.n, X.shape[0], _ptr(w), w.numel(),
+                                 _stream()))
+        return Y
+
+    def dslash(self, X, which=0, single=False):
+        """Wilson pass: which 0 = D, 1 = D^H, 2 = H, 3 = H^H (D = 1 - kappa H)."""
+        dt = self.single_dtype if single else self.dtype
+        X = self._vec(X, dt)
+        Y = torch.empty_like(X)
+        _check(lib().sc_wilson_dslash(self._h, _DT_OF[dt], int(which), _ptr(X), self.n, _ptr(Y), self.n,
+                                      X.shape[0], _stream()))
+        return Y
+
+
+# ----------------------------------------------------------------------------- the method
+@dataclass
+class Basis:
+    V: torch.Tensor        # (m+1, n): rows v_1 .. v_{m+1}
+    alpha: torch.Tensor    # (m,) FP64
+    beta: torch.Tensor     # (m+1,) FP64, beta_0 .. beta_m
+    x1: torch.Tensor       # (n,) Lanczos-CG approximation of right-hand side 1
+    m_done: int
+    status: int
+    n: int
+
+
+def seed_lanczos(op, b1, m, freq, x0=None, v_dtype=None):
+    """Seed phase on right-hand side b1 (Section 3 algorithm): returns a Basis."""
+    b1 = op._vec(b1, op.dtype)
+    x1 = torch.zeros_like(b1) if x0 is None else op._vec(x0, op.dtype).clone()
+    vdt = op.dtype if v_dtype is None else v_dtype
+    V = torch.empty((m + 1, op.n), dtype=vdt, device=op.device)
+    alpha = torch.empty(m, dtype=torch.float64, device=op.device)
+    beta = torch.empty(m + 1, dtype=torch.float64, device=op.device)
+    nb = _SZ()
+    _check(lib().sc_workspace_size(op.handle, SC_CALL_SEED, 1, int(m), _DT_OF[vdt], ctypes.byref(nb)))
+    w = _work(nb.value, op.device)
+    md = _INT()
+    st = lib().sc_seed_lanczos(op.handle, _ptr(b1), _ptr(x1), int(m), int(freq), _ptr(V), op.n, _DT_OF[vdt],
+                               _ptr(alpha), _ptr(beta), ctypes.byref(md), _ptr(w), w.numel(), _stream())
+    _check(st, ok=(0, 2))
+    return Basis(V, alpha, beta, x1.reshape(-1), md.value, st, op.n)
+
+
+def project(basis, R0, X0=None, m=None):
+    """X0 + V_m T_m^{-1} V_m^H R0 for the rows of R0 (the seeding of the other right-hand sides)."""
+    m = basis.m_done if m is None else int(m)
+    full = torch.complex128 if basis.V.dtype in (torch.complex64, torch.complex128) else torch.float64
+    R0 = R0.reshape(-1, basis.n).to(device=basis.V.device, dtype=full).contiguous()
+    X = torch.zeros_like(R0) if X0 is None else X0.reshape(-1, basis.n).to(R0.device, full).clone().contiguous()
+    k = R0.shape[0]
+    if m < 1 or k == 0:
+        return X
+    nb = _SZ(basis.n)
+    _check(lib().sc_workspace_size(None, SC_CALL_PROJECT, k, m, _DT_OF[full], ctypes.byref(nb)))
+    w = _work(nb.value, R0.device)
+    _check(lib().sc_project(basis.n, _ptr(basis.V), basis.n, _DT_OF[basis.V.dtype], m, _ptr(basis.alpha),
+                            _ptr(basis.beta), _DT_OF[full], _ptr(R0), basis.n, k, _ptr(X), basis.n, _ptr(w),
+                            w.numel(), _stream()))
+    return X
+
+
+def solve_cg(op, B, tol, X0=None, mixed=False, maxit=100000):
+    """CG on the rows of B from X0; returns (X, iters list, true relative residuals list)."""
+    B = op._vec(B, op.dtype)
+    X = torch.zeros_like(B) if X0 is None else op._vec(X0, op.dtype).clone()
+    k = B.shape[0]
+    nb = _SZ()
+    dt = op.sc_dtype if not mixed else _DT_OF[op.single_dtype]
+    _check(lib().sc_workspace_size(op.handle, SC_CALL_CG, k, 0, dt, ctypes.byref(nb)))
+    w = _work(nb.value, op.device)
+    iters = (ctypes.c_int * k)()
+    rel = (ctypes.c_double * k)()
+    _check(lib().sc_solve_cg(op.handle, 1 if mixed else 0, _ptr(B), op.n, _ptr(X), op.n, k, float(tol), int(maxit),
+                             iters, rel, _ptr(w), w.numel(), _stream()), ok=(0, 1))
+    return X, list(iters), list(rel)
+
+
+def seeded_solve(op, B, m, freq, tol, mixed=False, maxit=100000):
+    """Single seed: seed on row 0 of B, project rows 1.., finish every row with CG.
+
+    Returns dict(X, iters (RHS 1 counts the seed steps), cg_iters, relres, basis, X_seeded).
+    """
+    B = op._vec(B, op.dtype)
+    vdt = op.single_dtype if mixed else op.dtype
+    basis = seed_lanczos(op, B[0], m, freq, v_dtype=vdt)
+    Xs = torch.empty_like(B)
+    Xs[0] = basis.x1
+    if B.shape[0] > 1:
+        Xs[1:] = project(basis, B[1:])
+    X, its, rel = solve_cg(op, B, tol, X0=Xs, mixed=mixed, maxit=maxit)
+    iters = [its[0] + basis.m_done] + its[1:]
+    return {"X": X, "X_seeded": Xs, "iters": iters, "cg_iters": its, "relres": rel, "basis": basis}

@@ -1,0 +1,310 @@
+// Tall-skinny contractions with the stored Lanczos basis and the solve with the
+// Lanczos tridiagonal matrix.
+//
+//   gemm_cn:  G = V^H W   (V: n x M basis, W: N <= 32 columns, G: M x N FP64)
+//             used by step 8 (coefficients of v_i and f on v_1..v_{i-1}) and by
+//             the projection (V^H R0).  Split over row chunks; each block
+//             stages a KT x TM tile of V and a KT x N tile of W in LDS and
+//             accumulates in FP64; the chunk partials are then added in chunk
+//             order by a second kernel, so the result is deterministic.
+//   gemm_nn:  X_j += scale * V Y_j  (thread per row, Y staged in LDS).
+//   tridiag:  Y <- T^{-1} Y with T = L U, the factorization of the seed
+//             algorithm's step 6 (pivots delta_i, multipliers gamma_{i-1}).
+#include "sc_internal.h"
+#include "sc_timer.h"
+
+namespace sc {
+
+template <typename R, bool CPLX>
+__device__ __forceinline__ cplx<double> ld_elem(const R* p, int64_t idx) {
+    if constexpr (CPLX) {
+        cplx<R> c = ld2(p, idx);
+        return {(double)c.re, (double)c.im};
+    } else {
+        return {(double)p[idx], 0.0};
+    }
+}
+
+// ---------------------------------------------------------------- G = V^H W
+// TM basis columns per block, G_ = 256/TM thread groups, QN W-columns per thread.
+template <typename VR, typename WR, bool CPLX, int TM, int QN, int KT>
+__global__ __launch_bounds__(kBlock) void k_cn_partial(const VR* __restrict__ V, int64_t ldv, int64_t n, int M,
+                                                       ColPtrs<const void> W, int N, double* __restrict__ part,
+                                                       int64_t rows_per_chunk, const int* halt) {
+    if (halt && *halt) return;
+    constexpr int GR = kBlock / TM;
+    constexpr int NT = GR * QN;
+    __shared__ cplx<double> Vs[KT][TM + 1];
+    __shared__ cplx<double> Ws[KT][NT];
+    const int a0 = blockIdx.y * TM;
+    const int64_t r0 = blockIdx.x * rows_per_chunk;
+    const int64_t r1 = min(n, r0 + rows_per_chunk);
+    const int ta = threadIdx.x % TM;
+    const int tg = threadIdx.x / TM;
+    cplx<double> acc[QN];
+#pragma unroll
+    for (int q = 0; q < QN; ++q) acc[q] = {0.0, 0.0};
+    for (int64_t rb = r0; rb < r1; rb += KT) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < KT * TM; e += kBlock) {
+            const int rr = e % KT, aa = e / KT;
+            const int64_t r = rb + rr;
+            const int a = a0 + aa;
+            Vs[rr][aa] = (r < r1 && a < M) ? ld_elem<VR, CPLX>(V, (int64_t)a * ldv + r) : cplx<double>{0.0, 0.0};
+        }
+        for (int e = threadIdx.x; e < KT * NT; e += kBlock) {
+            const int rr = e % KT, jj = e / KT;
+            const int64_t r = rb + rr;
+            Ws[rr][jj] = (r < r1 && jj < N) ? ld_elem<WR, CPLX>((const WR*)W.p[jj], r) : cplx<double>{0.0, 0.0};
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int rr = 0; rr < KT; ++rr) {
+            const cplx<double> v = Vs[rr][ta];
+#pragma unroll
+            for (int q = 0; q < QN; ++q) {
+                const cplx<double> w = Ws[rr][tg + GR * q];
+                acc[q].re += v.re * w.re + v.im * w.im;
+                acc[q].im += v.re * w.im - v.im * w.re;
+            }
+        }
+    }
+    const int a = a0 + ta;
+    if (a < M) {
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const int j = tg + GR * q;
+            if (j < N) {
+                const int64_t o = ((int64_t)blockIdx.x * M + a) * N + j;
+                part[2 * o] = acc[q].re;
+                part[2 * o + 1] = acc[q].im;
+            }
+        }
+    }
+}
+
+__global__ void k_cn_reduce(const double* __restrict__ part, int nchunk, int64_t nout /* doubles */,
+                            double* __restrict__ G, bool cplx, const int* halt) {
+    if (halt && *halt) return;
+    const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (o >= nout) return;
+    double s = 0.0;
+    if (cplx) {
+        for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * nout + o];
+    } else {  // partials keep (re, im) pairs; the real result is the re part
+        for (int c = 0; c < nchunk; ++c) s += part[2 * ((int64_t)c * nout + o)];
+    }
+    G[o] = s;
+}
+
+struct CnPlan {
+    int tm, kt, nchunk;
+    int64_t rows;
+};
+
+static CnPlan cn_plan(int64_t n, int M, int N) {
+    CnPlan p;
+    p.tm = N <= 2 ? 128 : 32;
+    p.kt = N <= 2 ? 16 : 64;
+    const int mt = (M + p.tm - 1) / p.tm;
+    int64_t want = std::max<int64_t>(1, (2048 + mt - 1) / mt);
+    const int64_t maxchunk = std::max<int64_t>(1, (n + p.kt - 1) / p.kt);
+    want = std::min(want, maxchunk);
+    int64_t rows = (n + want - 1) / want;
+    rows = (rows + p.kt - 1) / p.kt * p.kt;
+    p.rows = std::max<int64_t>(rows, p.kt);
+    p.nchunk = (int)std::max<int64_t>(1, (n + p.rows - 1) / p.rows);
+    return p;
+}
+
+// Partials needed by any call with M' <= M basis columns and N' <= N columns:
+// the split plan gives smaller M more row chunks, so the maximum is not at M.
+size_t gemm_cn_part_doubles(int64_t n, int M, int N, bool) {
+    size_t best = 0;
+    for (int nq = 1; nq <= N; ++nq)
+        for (int mm = 1; mm <= M; ++mm) {
+            const CnPlan p = cn_plan(n, mm, nq);
+            best = std::max(best, (size_t)p.nchunk * mm * nq * 2);
+        }
+    return best;
+}
+
+template <typename VR, typename WR, bool CPLX>
+static void cn_launch(const CnPlan& p, const VR* V, int64_t ldv, int64_t n, int M, const ColPtrs<const void>& W, int N,
+                      double* part, const int* halt, hipStream_t s) {
+    dim3 grid((unsigned)p.nchunk, (unsigned)((M + p.tm - 1) / p.tm));
+    if (N <= 2)
+        hipLaunchKernelGGL((k_cn_partial<VR, WR, CPLX, 128, 1, 16>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
+    else if (N <= 8)
+        hipLaunchKernelGGL((k_cn_partial<VR, WR, CPLX, 32, 1, 64>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
+    else
+        hipLaunchKernelGGL((k_cn_partial<VR, WR, CPLX, 32, 4, 64>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
+}
+
+sc_status gemm_cn(bool cplx, bool vsingle, const void* V, int64_t ldv, int64_t n, int M, bool wsingle,
+                  const ColPtrs<const void>& W, int N, double* G, double* part, const int* halt, hipStream_t s) {
+    if (M <= 0 || N <= 0) return SC_OK;
+    if (N > kMaxCols) {
+        set_error("gemm_cn: too many columns");
+        return SC_ERR_ARG;
+    }
+    CnPlan p = cn_plan(n, M, N);
+    const double eb = (cplx ? 2.0 : 1.0);
+    TimerScope ts_(TC_GEMM_CN, s,
+                   (double)n * M * eb * (vsingle ? 4 : 8) + (double)n * N * eb * (wsingle ? 4 : 8) + (double)M * N * eb * 8,
+                   (cplx ? 8.0 : 2.0) * n * M * N);
+#define SC_CN(VR, WR, C) cn_launch<VR, WR, C>(p, (const VR*)V, ldv, n, M, W, N, part, halt, s)
+    if (cplx) {
+        if (vsingle) { if (wsingle) SC_CN(float, float, true); else SC_CN(float, double, true); }
+        else { if (wsingle) SC_CN(double, float, true); else SC_CN(double, double, true); }
+    } else {
+        if (vsingle) { if (wsingle) SC_CN(float, float, false); else SC_CN(float, double, false); }
+        else { if (wsingle) SC_CN(double, float, false); else SC_CN(double, double, false); }
+    }
+#undef SC_CN
+    SC_LAUNCH_CHECK();
+    const int64_t nout = (int64_t)M * N * (cplx ? 2 : 1);
+    hipLaunchKernelGGL(k_cn_reduce, dim3((unsigned)((nout + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, part,
+                       p.nchunk, cplx ? nout : (int64_t)M * N, G, cplx, halt);
+    SC_LAUNCH_CHECK();
+    return SC_OK;
+}
+
+// ---------------------------------------------------------------- X += scale V Y
+template <typename VR, typename XR, bool CPLX, int NT>
+__global__ __launch_bounds__(kBlock) void k_nn(const VR* __restrict__ V, int64_t ldv, int64_t n, int M,
+                                               const double* __restrict__ Y, int N, ColPtrs<void> X, double scale,
+                                               const int* halt) {
+    if (halt && *halt) return;
+    constexpr int AC = 64;
+    constexpr int W = CPLX ? 2 : 1;
+    __shared__ double Ys[AC * NT * W];
+    const int64_t r = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    double ar[NT], ai[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) ar[j] = ai[j] = 0.0;
+    for (int a0 = 0; a0 < M; a0 += AC) {
+        const int na = min(AC, M - a0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < AC * NT * W; e += kBlock) {
+            const int aa = e / (NT * W);
+            const int j = (e / W) % NT;
+            const int pp = e % W;
+            Ys[e] = (aa < na && j < N) ? Y[((int64_t)(a0 + aa) * N + j) * W + pp] : 0.0;
+        }
+        __syncthreads();
+        if (r < n) {
+            for (int aa = 0; aa < na; ++aa) {
+                const cplx<double> v = ld_elem<VR, CPLX>(V, (int64_t)(a0 + aa) * ldv + r);
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    if constexpr (CPLX) {
+                        const double yr = Ys[(aa * NT + j) * 2], yi = Ys[(aa * NT + j) * 2 + 1];
+                        ar[j] += v.re * yr - v.im * yi;
+                        ai[j] += v.re * yi + v.im * yr;
+                    } else {
+                        ar[j] += v.re * Ys[aa * NT + j];
+                    }
+                }
+            }
+        }
+    }
+    if (r >= n) return;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        if (j < N) {
+            XR* x = (XR*)X.p[j];
+            if constexpr (CPLX) {
+                cplx<XR> c = ld2(x, r);
+                c.re = (XR)((double)c.re + scale * ar[j]);
+                c.im = (XR)((double)c.im + scale * ai[j]);
+                st2(x, r, c);
+            } else {
+                x[r] = (XR)((double)x[r] + scale * ar[j]);
+            }
+        }
+    }
+}
+
+template <typename VR, typename XR, bool CPLX>
+static void nn_launch(const VR* V, int64_t ldv, int64_t n, int M, const double* Y, int N, const ColPtrs<void>& X,
+                      double scale, const int* halt, hipStream_t s) {
+    dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
+    if (N <= 2)
+        hipLaunchKernelGGL((k_nn<VR, XR, CPLX, 2>), grid, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
+    else if (N <= 8)
+        hipLaunchKernelGGL((k_nn<VR, XR, CPLX, 8>), grid, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
+    else
+        hipLaunchKernelGGL((k_nn<VR, XR, CPLX, 32>), grid, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
+}
+
+sc_status gemm_nn(bool cplx, bool vsingle, const void* V, int64_t ldv, int64_t n, int M, const double* Y, int N,
+                  bool xsingle, const ColPtrs<void>& X, double scale, const int* halt, hipStream_t s) {
+    if (M <= 0 || N <= 0 || n <= 0) return SC_OK;
+    if (N > kMaxCols) {
+        set_error("gemm_nn: too many columns");
+        return SC_ERR_ARG;
+    }
+    const double eb = (cplx ? 2.0 : 1.0);
+    TimerScope ts_(TC_GEMM_NN, s, (double)n * M * eb * (vsingle ? 4 : 8) + 2.0 * n * N * eb * (xsingle ? 4 : 8),
+                   (cplx ? 8.0 : 2.0) * n * M * N);
+#define SC_NN(VR, XR, C) nn_launch<VR, XR, C>((const VR*)V, ldv, n, M, Y, N, X, scale, halt, s)
+    if (cplx) {
+        if (vsingle) { if (xsingle) SC_NN(float, float, true); else SC_NN(float, double, true); }
+        else { if (xsingle) SC_NN(double, float, true); else SC_NN(double, double, true); }
+    } else {
+        if (vsingle) { if (xsingle) SC_NN(float, float, false); else SC_NN(float, double, false); }
+        else { if (xsingle) SC_NN(double, float, false); else SC_NN(double, double, false); }
+    }
+#undef SC_NN
+    SC_LAUNCH_CHECK();
+    return SC_OK;
+}
+
+// ---------------------------------------------------------------- T^{-1}
+// T is real, so a complex right-hand side is two real ones: Y is an M x nc
+// row-major real matrix (nc = N or 2N) and thread t sweeps column t.
+__global__ void k_tridiag(const double* __restrict__ alpha, const double* __restrict__ beta, int M,
+                          double* __restrict__ Y, int nc, const double* e1_beta0, double* __restrict__ work,
+                          const int* halt) {
+    if (halt && *halt) return;
+    double* gam = work;
+    double* del = work + M;
+    if (threadIdx.x == 0) {
+        del[0] = alpha[0];
+        for (int i = 1; i < M; ++i) {
+            gam[i] = beta[i] / del[i - 1];
+            del[i] = alpha[i] - gam[i] * beta[i];
+        }
+    }
+    if (e1_beta0) {
+        for (int64_t e = threadIdx.x; e < (int64_t)M * nc; e += blockDim.x) Y[e] = (e == 0) ? *e1_beta0 : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+        double prev = Y[t];
+        for (int a = 1; a < M; ++a) {
+            const double y = Y[(int64_t)a * nc + t] - gam[a] * prev;
+            Y[(int64_t)a * nc + t] = y;
+            prev = y;
+        }
+        double next = Y[(int64_t)(M - 1) * nc + t] / del[M - 1];
+        Y[(int64_t)(M - 1) * nc + t] = next;
+        for (int a = M - 2; a >= 0; --a) {
+            const double y = (Y[(int64_t)a * nc + t] - beta[a + 1] * next) / del[a];
+            Y[(int64_t)a * nc + t] = y;
+            next = y;
+        }
+    }
+}
+
+sc_status tridiag_solve(const double* alpha, const double* beta, int M, double* Y, int N, bool cplx,
+                        const double* e1_beta0, double* work, const int* halt, hipStream_t s) {
+    if (M <= 0 || N <= 0) return SC_OK;
+    const int nc = N * (cplx ? 2 : 1);
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, s, alpha, beta, M, Y, nc, e1_beta0, work, halt);
+    SC_LAUNCH_CHECK();
+    return SC_OK;
+}
+
+}  // namespace sc

@@ -1,0 +1,159 @@
+// Internal helpers shared by the library's translation units: complex
+// arithmetic, wave/block reductions, deterministic split reductions, error
+// plumbing and workspace carving.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/seedcg.h"
+
+namespace sc {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+void clear_error();
+
+#define SC_HIP(expr)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            ::sc::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));       \
+            return SC_ERR_HIP;                                                        \
+        }                                                                             \
+    } while (0)
+
+#define SC_LAUNCH_CHECK() SC_HIP(hipGetLastError())
+
+#define SC_ARG(cond, msg)                                                             \
+    do {                                                                              \
+        if (!(cond)) {                                                                \
+            ::sc::set_error(std::string("argument error: ") + (msg));                 \
+            return SC_ERR_ARG;                                                        \
+        }                                                                             \
+    } while (0)
+
+#define SC_TRY(expr)                                                                  \
+    do {                                                                              \
+        sc_status s_ = (expr);                                                        \
+        if (s_ != SC_OK) return s_;                                                   \
+    } while (0)
+
+// ---------------------------------------------------------------- complex
+template <typename R>
+struct cplx {
+    R re, im;
+};
+
+template <typename R> struct vec2;
+template <> struct vec2<float> { using type = float2; };
+template <> struct vec2<double> { using type = double2; };
+
+template <typename R>
+__device__ __forceinline__ cplx<R> ld2(const R* p, int64_t idx) {
+    auto v = reinterpret_cast<const typename vec2<R>::type*>(p)[idx];
+    return {v.x, v.y};
+}
+template <typename R>
+__device__ __forceinline__ void st2(R* p, int64_t idx, cplx<R> c) {
+    typename vec2<R>::type v;
+    v.x = c.re;
+    v.y = c.im;
+    reinterpret_cast<typename vec2<R>::type*>(p)[idx] = v;
+}
+
+// ---------------------------------------------------------------- reductions
+constexpr int kBlock = 256;          // threads per block of the streaming kernels
+constexpr int kWaves = kBlock / 64;  // 64-wide wavefronts
+constexpr int kMaxRedBlocks = 1024;  // split-reduction width cap
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the block; every thread gets the total.  Deterministic: fixed tree.
+__device__ __forceinline__ double block_sum(double v, double* sh /* kWaves doubles */) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) t += sh[i];
+    return t;
+}
+
+// Split reduction across the blocks of one grid row: every block deposits its
+// partial in part[blockIdx.x]; the last block to arrive (counted in *ctr)
+// adds them in index order, so the result depends only on the data and the
+// grid width, never on scheduling.  Returns true in the last block, where
+// *total holds the sum (valid in every thread of that block).  The counter is
+// reset by the last block, ready for the next launch.
+__device__ __forceinline__ bool split_reduce(double v, double* part, unsigned* ctr, double* total,
+                                            double* sh) {
+    __shared__ int am_last;
+    double b = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = b;
+        __threadfence();
+        unsigned prev = atomicAdd(ctr, 1u);
+        am_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!am_last) return false;
+    __threadfence();
+    double s = 0.0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) s += part[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) *ctr = 0u;
+    *total = s;
+    return true;
+}
+
+inline int red_grid(int64_t n_items, int per_thread = 4) {
+    int64_t g = (n_items + (int64_t)kBlock * per_thread - 1) / ((int64_t)kBlock * per_thread);
+    if (g < 1) g = 1;
+    if (g > kMaxRedBlocks) g = kMaxRedBlocks;
+    return (int)g;
+}
+
+// ---------------------------------------------------------------- workspace
+struct Carver {
+    char* base;
+    size_t cap;
+    size_t off = 0;
+    bool dry;  // size query only
+    Carver(void* b, size_t c) : base((char*)b), cap(c), dry(b == nullptr) {}
+    // 256-byte aligned carving (absolute addresses; a dry run assumes an aligned base)
+    template <typename T>
+    T* take(size_t count) {
+        const uintptr_t addr = ((uintptr_t)base + off + 255) & ~uintptr_t(255);
+        off = addr - (uintptr_t)base;
+        T* p = dry ? nullptr : reinterpret_cast<T*>(base + off);
+        off += count * sizeof(T);
+        return p;
+    }
+    bool ok() const { return dry || off <= cap; }
+};
+
+inline bool is_complex(sc_dtype d) { return d == SC_C64 || d == SC_C128; }
+inline bool is_single(sc_dtype d) { return d == SC_C64 || d == SC_R32; }
+inline size_t dtype_bytes(sc_dtype d) {
+    switch (d) {
+        case SC_R64: return 8;
+        case SC_C64: return 8;
+        case SC_C128: return 16;
+        case SC_R32: return 4;
+    }
+    return 0;
+}
+inline sc_dtype single_of(sc_dtype d) { return d == SC_C128 ? SC_C64 : (d == SC_R64 ? SC_R32 : d); }
+inline sc_dtype double_of(sc_dtype d) { return d == SC_C64 ? SC_C128 : (d == SC_R32 ? SC_R64 : d); }
+
+}  // namespace sc

@@ -1,0 +1,72 @@
+// Internal declarations: the operator object and the launchers shared by the
+// host drivers.
+#pragma once
+
+#include "sc_common.h"
+
+enum sc_op_kind { SC_OPK_LAPLACE2D = 0, SC_OPK_DIAG = 1, SC_OPK_WILSON = 2 };
+
+struct sc_op {
+    int kind;
+    int64_t n;          // vector length in elements of `dtype`
+    sc_dtype dtype;     // SC_R64 or SC_C128
+    // Laplacian
+    int nx = 0, ny = 0;
+    // diagonal
+    const double* d = nullptr;
+    // Wilson
+    int dims[4] = {0, 0, 0, 0};  // X, Y, Z, T
+    int64_t vol = 0;
+    const void* U64 = nullptr;
+    const void* U32 = nullptr;
+    double kappa = 0.0;
+    int antiperiodic = 1;
+};
+
+namespace sc {
+
+// Column pointer list for the tall-skinny kernels (up to kMaxCols columns).
+constexpr int kMaxCols = 32;
+template <typename T>
+struct ColPtrs {
+    T* p[kMaxCols];
+};
+
+// ---------------------------------------------------------------- stencils (k_stencil.hip)
+// Y = A X for k columns, all arrays in the precision selected by `single`
+// (ld in elements of that dtype).  tmp: k*n elements (Wilson only).
+sc_status op_apply(const sc_op* op, bool single, const void* X, int64_t ldx, void* Y, int64_t ldy, int k,
+                   void* tmp, hipStream_t s);
+// elements of scratch op_apply needs per column
+int64_t op_apply_tmp_elems(const sc_op* op);
+// one Wilson pass: which 0 = D, 1 = D^H, 2 = H, 3 = H^H
+sc_status wilson_pass(const sc_op* op, bool single, int which, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                      int k, hipStream_t s);
+
+// ---------------------------------------------------------------- streaming kernels (k_blas.hip)
+// All act on "real views": a complex column of n elements is 2n reals.
+// z = a*x + b*y  (y may be null when b == 0); types: 0 = double, 1 = float
+sc_status lincomb(int zt, void* z, int64_t ldz, int xt, const void* x, int64_t ldx, int yt, const void* y,
+                  int64_t ldy, int64_t N, int k, double a, double b, hipStream_t s);
+// res[j] = sum_i x[i,j]*y[i,j] (FP64 accumulation), deterministic split reduction.
+// part: k*kMaxRedBlocks doubles, ctr: k zeroed counters.
+sc_status dot(int xt, const void* x, int64_t ldx, int yt, const void* y, int64_t ldy, int64_t N, int k,
+              double* res, double* part, unsigned* ctr, hipStream_t s);
+template <typename T>
+sc_status fill(T* p, int64_t n, T v, hipStream_t s);
+
+// ---------------------------------------------------------------- tall-skinny (k_tsgemm.hip)
+// G[a*N + j] = sum_r conj(V[r,a]) W_j[r]  (a < M, j < N <= kMaxCols); G complex or real FP64.
+// part: gemm_cn_part_elems(n, M, N) doubles.
+size_t gemm_cn_part_doubles(int64_t n, int M, int N, bool cplx);
+sc_status gemm_cn(bool cplx, bool vsingle, const void* V, int64_t ldv, int64_t n, int M, bool wsingle,
+                  const ColPtrs<const void>& W, int N, double* G, double* part, const int* halt, hipStream_t s);
+// X_j[r] += scale * sum_a V[r,a] Y[a*N + j]
+sc_status gemm_nn(bool cplx, bool vsingle, const void* V, int64_t ldv, int64_t n, int M, const double* Y, int N,
+                  bool xsingle, const ColPtrs<void>& X, double scale, const int* halt, hipStream_t s);
+// Y (M x N, complex or real, row-major [a*N+j]) <- T_M^{-1} Y by the LU recurrences.
+// If e1_beta0 != null, Y is first set to beta0 e_1 (N = 1).  work: 2*M doubles.
+sc_status tridiag_solve(const double* alpha, const double* beta, int M, double* Y, int N, bool cplx,
+                        const double* e1_beta0, double* work, const int* halt, hipStream_t s);
+
+}  // namespace sc

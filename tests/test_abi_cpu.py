@@ -1,0 +1,91 @@
+"""CPU checks of the boundary: the library loads and exports every symbol the
+header declares, and host-side argument validation rejects bad calls without
+touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "seedcg.h")
+LIB = os.path.join(ROOT, "paper_0810_0330_amd", "libseedcg.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sc_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_0810_0330_amd import build
+        build.build()
+    l = ctypes.CDLL(LIB)
+    l.sc_last_error.restype = ctypes.c_char_p
+    return l
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "sc_seed_lanczos" in names and "sc_project" in names and "sc_solve_cg" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_header():
+    from paper_0810_0330_amd import api
+    assert set(declared_functions()) == set(api._PROTOS)
+
+
+def test_op_argument_errors(lib):
+    out = ctypes.c_void_p()
+    assert lib.sc_op_laplace2d(0, 4, ctypes.byref(out)) == -1
+    assert b"nx and ny" in lib.sc_last_error()
+    assert lib.sc_op_laplace2d(4, 4, None) == -1
+    dims = (ctypes.c_int * 4)(4, 4, 0, 4)
+    assert lib.sc_op_wilson_normal(dims, ctypes.c_void_p(256), None, ctypes.c_double(0.12), 1, ctypes.byref(out)) == -1
+    dims = (ctypes.c_int * 4)(4, 4, 4, 4)
+    assert lib.sc_op_wilson_normal(dims, None, None, ctypes.c_double(0.12), 1, ctypes.byref(out)) == -1
+    assert lib.sc_op_wilson_normal(dims, ctypes.c_void_p(264), None, ctypes.c_double(0.12), 1, ctypes.byref(out)) == -1
+    assert b"aligned" in lib.sc_last_error()
+    assert lib.sc_op_wilson_normal(dims, ctypes.c_void_p(256), None, ctypes.c_double(float("nan")), 1,
+                                   ctypes.byref(out)) == -1
+
+
+def test_op_create_info_destroy_on_host(lib):
+    # creating an op only records pointers: no device access, so it works without a GPU
+    out = ctypes.c_void_p()
+    assert lib.sc_op_laplace2d(32, 16, ctypes.byref(out)) == 0
+    n = ctypes.c_int64()
+    dt = ctypes.c_int()
+    assert lib.sc_op_info(out, ctypes.byref(n), ctypes.byref(dt)) == 0
+    assert n.value == 512 and dt.value == 0
+    nb = ctypes.c_size_t()
+    assert lib.sc_workspace_size(out, 3, 4, 0, 0, ctypes.byref(nb)) == 0 and nb.value > 4 * 3 * 512 * 8
+    assert lib.sc_workspace_size(out, 1, 1, 50, 0, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert lib.sc_workspace_size(out, 9, 1, 50, 0, ctypes.byref(nb)) == -1
+    # seed: m < 1 and a NULL m_done are argument errors, caught before any launch
+    md = ctypes.c_int()
+    p = ctypes.c_void_p(4096)
+    assert lib.sc_seed_lanczos(out, p, p, 0, 1, p, ctypes.c_int64(512), 0, p, p, ctypes.byref(md), p,
+                               ctypes.c_size_t(1 << 30), None) == -1
+    assert lib.sc_seed_lanczos(out, p, p, 10, 1, p, ctypes.c_int64(511), 0, p, p, ctypes.byref(md), p,
+                               ctypes.c_size_t(1 << 30), None) == -1
+    assert b"ldv" in lib.sc_last_error()
+    # too small a workspace is reported as such
+    assert lib.sc_seed_lanczos(out, p, p, 10, 1, p, ctypes.c_int64(512), 0, p, p, ctypes.byref(md), p,
+                               ctypes.c_size_t(16), None) == -5
+    # CG: tol <= 0 and k < 1
+    it = (ctypes.c_int * 1)()
+    rr = (ctypes.c_double * 1)()
+    assert lib.sc_solve_cg(out, 0, p, ctypes.c_int64(512), p, ctypes.c_int64(512), 1, ctypes.c_double(0.0), 10, it, rr,
+                           p, ctypes.c_size_t(1 << 30), None) == -1
+    assert lib.sc_solve_cg(out, 0, p, ctypes.c_int64(512), p, ctypes.c_int64(512), 0, ctypes.c_double(1e-8), 10, it,
+                           rr, p, ctypes.c_size_t(1 << 30), None) == -1
+    # projection: mismatched real/complex dtypes
+    assert lib.sc_project(ctypes.c_int64(512), p, ctypes.c_int64(512), 1, 10, p, p, 0, p, ctypes.c_int64(512), 1, p,
+                          ctypes.c_int64(512), p, ctypes.c_size_t(1 << 30), None) == -1
+    assert lib.sc_op_destroy(out) == 0
