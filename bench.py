@@ -45,7 +45,60 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timer", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--micro", default=None, choices=["wilson_f32", "wilson_f64", "copy", "gemm_cn", "gemm_nn"],
+                    help="time one kernel in isolation on the workload's lattice (for profilers)")
+    ap.add_argument("--k", type=int, default=1, help="columns per launch in --micro mode")
+    ap.add_argument("--reps", type=int, default=20, help="launches in --micro mode")
     return ap.parse_args()
+
+
+def micro(args, w):
+    """One kernel, `reps` launches, on the workload's lattice: for rocprofv3 counter runs."""
+    import numpy as np
+    import torch
+
+    from paper_0810_0330_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    inp = synth.make_inputs(w)
+    op = api.Op.wilson(w.dims, torch.from_numpy(api.pack_links(inp["U"])).to(dev), w.kappa)
+    k = args.k
+    single = args.micro != "wilson_f64"
+    dt = torch.complex64 if single else torch.complex128
+    g = torch.Generator(device=dev).manual_seed(1)
+    X = torch.randn((k, op.n), dtype=dt, device=dev, generator=g)
+    res = {"micro": args.micro, "k": k, "reps": args.reps, "n": op.n}
+    if args.micro.startswith("wilson"):
+        Y = torch.empty_like(X)
+        fn = lambda: op.dslash(X, 0, single=single)  # noqa: E731
+        bytes_per = (48.0 * k + 72.0) * (4 if single else 8) * (op.n // 12)
+    elif args.micro == "copy":
+        Y = torch.empty_like(X)
+        fn = lambda: Y.copy_(X)  # noqa: E731
+        bytes_per = 2.0 * X.numel() * X.element_size()
+    else:
+        m = 1000
+        V = torch.randn((m, op.n), dtype=torch.complex64, device=dev, generator=g)
+        basis = api.Basis(V, torch.ones(m, dtype=torch.float64, device=dev) * 4,
+                          torch.ones(m + 1, dtype=torch.float64, device=dev) * 0.1, None, m, 0, op.n)
+        R = X.to(torch.complex128)
+        fn = lambda: api.project(basis, R)  # noqa: E731
+        bytes_per = 2.0 * m * op.n * 8
+    fn()
+    torch.cuda.synchronize()
+    api.timer_enable(True)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(args.reps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    res["avg_us"] = e0.elapsed_time(e1) * 1e3 / args.reps
+    res["GBps"] = bytes_per / (res["avg_us"] * 1e-6) / 1e9
+    res["kernels"] = {k2: v for k2, v in api.timer_read().items() if v["launches"]}
+    api.timer_enable(False)
+    print(json.dumps(res), flush=True)
 
 
 def workload(args):
@@ -125,6 +178,8 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda:0")
     w = workload(args)
+    if args.micro:
+        return micro(args, w)
     log(f"[bench] workload {w.name}: dims {w.dims} nrhs {w.nrhs} m {w.m} freq {w.freq} tol {w.tol} {w.precision}")
     t0 = time.perf_counter()
     inp = synth.make_inputs(w)
@@ -203,6 +258,12 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "avg_launch_us": kd["avg_us"], "bytes_per_launch": kd["bytes_per_launch"]}
 
+    tuning = {}
+    if w.op == "wilson":
+        for kk, single in [(1, True), (w.nrhs, True), (1, False), (w.nrhs, False)]:
+            v, us = op.tune_info(kk, single=single)
+            tuning[f"{'f32' if single else 'f64'}_k{kk}"] = {"variant": v, "us": us}
+
     # ---- oracle on the host
     cpu = None
     if not args.no_cpu_baseline:
@@ -237,6 +298,7 @@ def main():
         "speedup_vs_plain": round(value / plain["rhs_per_s"], 3) if plain else None,
         "roofline": roof,
         "kernels": kernels,
+        "stencil_tuning": tuning,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

@@ -121,6 +121,23 @@ sc_status sc_op_apply(const sc_op* op, sc_dtype dtype, const void* X_dev, int64_
 sc_status sc_wilson_dslash(const sc_op* op, sc_dtype dtype, int which, const void* X_dev,
                            int64_t ldx, void* Y_dev, int64_t ldy, int k, void* stream);
 
+/* Launch shape of the Wilson stencil chosen by the library's autotuner for
+ * this lattice, precision and column count k (not part of the method).  The
+ * first pass with a new (lattice, dtype, k) times each candidate shape on the
+ * caller's buffers, which adds one host synchronisation to that call, and
+ * keeps the fastest; SEEDCG_TUNE=0 in the environment selects fixed defaults,
+ * and no tuning happens while the stream is being captured.  variant (host):
+ * 0 = unrolled hops, 1 column per thread; 1, 2, 3 = rolled hop loop with 1, 2,
+ * 4 columns per thread (-1: not tuned yet).  us (host, 4 floats): measured
+ * microseconds per pass of each candidate (-1 if not run). */
+sc_status sc_wilson_tune_info(const sc_op* op, sc_dtype dtype, int k, int* variant, float* us);
+
+/* Pin the stencil launch shape for (this op's lattice, dtype, k) instead of
+ * tuning it (variant 0..3 as above); variant -1 forgets the choice so the next
+ * pass tunes again.  Errors: SC_ERR_ARG for a non-Wilson op, k < 1 or a
+ * variant outside -1..3. */
+sc_status sc_wilson_tune_set(const sc_op* op, sc_dtype dtype, int k, int variant);
+
 /* ------------------------------------------------------------------ workspace */
 typedef enum {
     SC_CALL_APPLY = 0,

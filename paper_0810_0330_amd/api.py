@@ -53,6 +53,8 @@ _PROTOS = {
     "sc_project": [_I64, _P, _I64, _INT, _INT, _P, _P, _INT, _P, _I64, _INT, _P, _I64, _P, _SZ, _P],
     "sc_solve_cg": [_P, _INT, _P, _I64, _P, _I64, _INT, _DBL, _INT, ctypes.POINTER(_INT), ctypes.POINTER(_DBL),
                     _P, _SZ, _P],
+    "sc_wilson_tune_info": [_P, _INT, _INT, ctypes.POINTER(_INT), ctypes.POINTER(ctypes.c_float)],
+    "sc_wilson_tune_set": [_P, _INT, _INT, _INT],
     "sc_timer_enable": [_INT],
     "sc_timer_read": [_INT, ctypes.POINTER(_DBL), ctypes.POINTER(_I64), ctypes.POINTER(_DBL), ctypes.POINTER(_DBL)],
     "sc_last_error": [],
@@ -242,6 +244,18 @@ class Op:
         _check(lib().sc_op_apply(self._h, sdt, _ptr(X), self.n, _ptr(Y), self.n, X.shape[0], _ptr(w), w.numel(),
                                  _stream()))
         return Y
+
+    def tune_info(self, k, single=True):
+        """(variant, [us per candidate]) chosen by the stencil autotuner for k columns."""
+        v = _INT()
+        us = (ctypes.c_float * 4)()
+        dt = SC_C64 if single else SC_C128
+        _check(lib().sc_wilson_tune_info(self._h, dt, int(k), ctypes.byref(v), us))
+        return v.value, [round(float(u), 2) for u in us]
+
+    def tune_set(self, k, variant, single=True):
+        """Pin the stencil launch shape for k columns (variant -1: tune again)."""
+        _check(lib().sc_wilson_tune_set(self._h, SC_C64 if single else SC_C128, int(k), int(variant)))
 
     def dslash(self, X, which=0, single=False):
         """Wilson pass: which 0 = D, 1 = D^H, 2 = H, 3 = H^H (D = 1 - kappa H)."""

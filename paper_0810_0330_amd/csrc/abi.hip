@@ -128,7 +128,7 @@ sc_status sc_op_wilson_normal(const int dims[4], const void* U64_dev, const void
     SC_ARG(!U32_dev || aligned(U32_dev, 8), "U32_dev is not 8-byte aligned");
     SC_ARG(std::isfinite(kappa), "kappa must be finite");
     const int64_t vol = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
-    SC_ARG(vol <= (int64_t(1) << 40) / 12, "lattice too large");
+    SC_ARG(vol * 36 < (int64_t(1) << 31), "lattice too large: 32-bit site indexing needs 36 * volume < 2^31");
     sc_op* op = new sc_op();
     op->kind = SC_OPK_WILSON;
     for (int i = 0; i < 4; ++i) op->dims[i] = dims[i];
@@ -293,6 +293,24 @@ sc_status sc_solve_cg(const sc_op* op, int mixed, const void* B_dev, int64_t ldb
     }
     return solve_cg(op, mixed, B_dev, ldb, X_dev, ldx, k, tol, maxit, iters, relres, work_dev, work_bytes,
                     (hipStream_t)stream);
+    SC_GUARD_END
+}
+
+sc_status sc_wilson_tune_info(const sc_op* op, sc_dtype dtype, int k, int* variant, float* us) {
+    SC_GUARD_BEGIN
+    SC_ARG(op && op->kind == SC_OPK_WILSON, "not a Wilson op");
+    SC_ARG(dtype == SC_C128 || dtype == SC_C64, "dtype must be SC_C128 or SC_C64");
+    SC_ARG(variant && us, "NULL argument");
+    return wilson_tune_query(op, dtype == SC_C64, k, variant, us);
+    SC_GUARD_END
+}
+
+sc_status sc_wilson_tune_set(const sc_op* op, sc_dtype dtype, int k, int variant) {
+    SC_GUARD_BEGIN
+    SC_ARG(op && op->kind == SC_OPK_WILSON, "not a Wilson op");
+    SC_ARG(dtype == SC_C128 || dtype == SC_C64, "dtype must be SC_C128 or SC_C64");
+    SC_ARG(k >= 1 && variant >= -1 && variant <= 3, "k must be >= 1 and variant in -1..3");
+    return wilson_tune_pin(op, dtype == SC_C64, k, variant);
     SC_GUARD_END
 }
 

@@ -5,10 +5,19 @@
 // still active, then verifies the true residual b - A x of every column and
 // restarts the ones still above tol.
 //
+// One iteration is four kernels: q = A p (the operator), partials of <p, q>,
+// x += alpha p and r -= alpha q with partials of ||r||^2, and p = r + beta p.
+// Each consumer block re-adds the producer's per-block partials in a fixed
+// order, so every block derives the same scalars.  The per-column state is
+// double-buffered: the last kernel of an iteration reads one copy and writes
+// the other, so no kernel reads a field that another of its blocks writes.
+//
 // mixed = 1: the vectors and the operator run in FP32; x and the true
 // residual are FP64.  A reliable update (x64 += x32, r = b - A64 x64, r32 =
-// r, x32 = 0, p kept) is made when a column's FP32 residual has fallen by 10x
-// since its last update, and whenever it reaches tol.
+// r, x32 = 0) is made when a column's FP32 residual norm has fallen by 10x
+// since its last update (p is kept and CG continues with the true residual),
+// and when the FP32 residual reaches tol (then CG restarts from the true
+// residual if it is still above tol).
 #include "sc_internal.h"
 
 #include <vector>
@@ -17,16 +26,15 @@ namespace sc {
 
 struct CGCol {
     double rho;      // ||r||^2 of the current recurrence
-    double alpha;    // rho / <p, A p>
-    double beta;     // rho_new / rho
+    double rho_prev; // rho of the previous iteration
+    double beta;     // rho / rho_prev
     double bnorm2;   // ||b||^2
     double tol2;     // tol^2 ||b||^2
     double rmax2;    // largest ||r||^2 since the last reliable update
-    double rho_prev; // rho of the previous iteration
     int active;      // iterating
     int iters;       // A-applies inside the loop so far
     int maxit;
-    int flag;        // 1: FP32 residual fell below tol (mixed: wants a reliable update)
+    int flag;        // 1: recursive residual at tol; 2: mixed, reliable update due
 };
 
 __global__ void k_cg_setup(CGCol* st, const double* rho, const double* bn, int k, double tol, int maxit, int first) {
@@ -42,81 +50,124 @@ __global__ void k_cg_setup(CGCol* st, const double* rho, const double* bn, int k
     c.rho = rho[j];
     c.rho_prev = rho[j];
     c.rmax2 = rho[j];
-    c.alpha = c.beta = 0.0;
+    c.beta = 0.0;
     c.flag = 0;
     c.active = (c.bnorm2 > 0.0) && (c.rho > c.tol2) && (c.iters < c.maxit) && isfinite(c.rho);
     st[j] = c;
 }
 
-// alpha = rho / Re<p, q>
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_cg_alpha(const R* __restrict__ p, const R* __restrict__ q, int64_t ld,
-                                                     int64_t N, CGCol* st, double* part, unsigned* ctr) {
+// partials of Re<p, q>
+template <typename R, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_cg_pq(const R* __restrict__ p, const R* __restrict__ q, int64_t ld,
+                                                  int64_t N, const CGCol* st, double* part) {
     __shared__ double sh[kWaves];
     const int col = blockIdx.y;
     if (!st[col].active) return;
+    constexpr int W = Pack<R>::W;
     const R* pc = p + col * ld;
     const R* qc = q + col * ld;
     double acc = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock)
-        acc += (double)pc[i] * (double)qc[i];
-    double tot;
-    if (split_reduce(acc, part + (int64_t)col * gridDim.x, ctr + col, &tot, sh) && threadIdx.x == 0)
-        st[col].alpha = st[col].rho / tot;
+    const int64_t stride = (int64_t)gridDim.x * kBlock * W;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W; i0 < N; i0 += stride) {
+        if (VEC && i0 + W <= N) {
+            const Pack<R> a = ldp(pc, i0), b = ldp(qc, i0);
+#pragma unroll
+            for (int e = 0; e < W; ++e) acc += (double)a.v[e] * (double)b.v[e];
+        } else {
+            for (int64_t j = i0; j < min(N, i0 + W); ++j) acc += (double)pc[j] * (double)qc[j];
+        }
+    }
+    block_partial(acc, part + (int64_t)col * gridDim.x, sh);
 }
 
-// x += alpha p; r -= alpha q; rho_new = ||r||^2; convergence and beta
-template <typename XT, typename R>
+// alpha = rho / <p, q>; x += alpha p; r -= alpha q; partials of ||r||^2
+template <typename XT, typename R, bool VEC>
 __global__ __launch_bounds__(kBlock) void k_cg_xr(XT* __restrict__ x, int64_t ldx, R* __restrict__ r,
                                                   const R* __restrict__ p, const R* __restrict__ q, int64_t ld,
-                                                  int64_t N, CGCol* st, int mixed, double* part, unsigned* ctr) {
+                                                  int64_t N, const CGCol* st, const double* part_pq, int G,
+                                                  double* part_rr) {
     __shared__ double sh[kWaves];
     const int col = blockIdx.y;
     if (!st[col].active) return;
-    const double a = st[col].alpha;
+    constexpr int W = Pack<R>::W;
+    const double a = st[col].rho / sum_partials(part_pq + (int64_t)col * G, G, sh);
     const R aR = (R)a;
     XT* xc = x + col * ldx;
     R* rc = r + col * ld;
     const R* pc = p + col * ld;
     const R* qc = q + col * ld;
     double acc = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock) {
-        xc[i] = (XT)(xc[i] + (XT)aR * (XT)pc[i]);
-        const R rv = rc[i] - aR * qc[i];
-        rc[i] = rv;
-        acc += (double)rv * (double)rv;
-    }
-    double tot;
-    if (split_reduce(acc, part + (int64_t)col * gridDim.x, ctr + col, &tot, sh) && threadIdx.x == 0) {
-        CGCol c = st[col];
-        c.iters += 1;
-        c.rho_prev = c.rho;
-        c.rho = tot;
-        c.beta = tot / c.rho_prev;
-        c.rmax2 = fmax(c.rmax2, tot);
-        if (!(tot > c.tol2) || !isfinite(tot)) {
-            c.flag = 1;          // recursive residual at tol (mixed: verify with an update)
-            c.active = 0;
-        } else if (mixed && tot < 0.01 * c.rmax2) {
-            c.flag = 2;          // FP32 residual fell 10x: pause for a reliable update
-            c.active = 0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock * W;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W; i0 < N; i0 += stride) {
+        if (VEC && sizeof(XT) == sizeof(R) && i0 + W <= N) {
+            Pack<R> xv = ldp((R*)xc, i0), rv = ldp(rc, i0);
+            const Pack<R> pv = ldp(pc, i0), qv = ldp(qc, i0);
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                xv.v[e] = xv.v[e] + aR * pv.v[e];
+                rv.v[e] = rv.v[e] - aR * qv.v[e];
+                acc += (double)rv.v[e] * (double)rv.v[e];
+            }
+            stp((R*)xc, i0, xv);
+            stp(rc, i0, rv);
+        } else {
+            for (int64_t j = i0; j < min(N, i0 + W); ++j) {
+                xc[j] = (XT)(xc[j] + (XT)aR * (XT)pc[j]);
+                const R rv = rc[j] - aR * qc[j];
+                rc[j] = rv;
+                acc += (double)rv * (double)rv;
+            }
         }
-        if (c.iters >= c.maxit) c.active = 0;
-        st[col] = c;
     }
+    block_partial(acc, part_rr + (int64_t)col * gridDim.x, sh);
 }
 
-// p = r + beta p
-template <typename R>
+// rho_new from the partials, convergence / reliable-update decisions (the
+// same in every block); p = r + beta p unless the column stops.  Block 0
+// writes the next state copy.
+template <typename R, bool VEC>
 __global__ __launch_bounds__(kBlock) void k_cg_p(R* __restrict__ p, const R* __restrict__ r, int64_t ld, int64_t N,
-                                                 const CGCol* st) {
+                                                 const CGCol* st, CGCol* st_next, const double* part_rr, int G,
+                                                 int mixed) {
+    __shared__ double sh[kWaves];
     const int col = blockIdx.y;
-    if (!st[col].active) return;
-    const R b = (R)st[col].beta;
+    CGCol c = st[col];
+    if (!c.active) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st_next[col] = c;
+        return;
+    }
+    constexpr int W = Pack<R>::W;
+    const double rr = sum_partials(part_rr + (int64_t)col * G, G, sh);
+    c.iters += 1;
+    c.rho_prev = c.rho;
+    c.rho = rr;
+    c.beta = rr / c.rho_prev;
+    c.rmax2 = fmax(c.rmax2, rr);
+    if (!(rr > c.tol2) || !isfinite(rr)) {
+        c.flag = 1;
+        c.active = 0;
+    } else if (mixed && rr < 0.01 * c.rmax2) {
+        c.flag = 2;
+        c.active = 0;
+    }
+    if (c.iters >= c.maxit) c.active = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st_next[col] = c;
+    if (!c.active) return;
+    const R b = (R)c.beta;
     R* pc = p + col * ld;
     const R* rc = r + col * ld;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock)
-        pc[i] = rc[i] + b * pc[i];
+    const int64_t stride = (int64_t)gridDim.x * kBlock * W;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W; i0 < N; i0 += stride) {
+        if (VEC && i0 + W <= N) {
+            Pack<R> pv = ldp(pc, i0);
+            const Pack<R> rv = ldp(rc, i0);
+#pragma unroll
+            for (int e = 0; e < W; ++e) pv.v[e] = rv.v[e] + b * pv.v[e];
+            stp(pc, i0, pv);
+        } else {
+            for (int64_t j = i0; j < min(N, i0 + W); ++j) pc[j] = rc[j] + b * pc[j];
+        }
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -128,10 +179,12 @@ struct CGWork {
     void* xs;      // mixed: FP32 increment of x (k x N2)
     double* r64;   // mixed: FP64 true residual (k x N2)
     double* ax64;  // A x in FP64 (k x N2)
+    double* xg;    // gathered FP64 columns for partial true residuals (k x N2)
     void* tmp64;   // FP64 op scratch (k columns)
+    double* part_pq;
+    double* part_rr;
     double* part;
-    unsigned* ctr;
-    CGCol* st;
+    CGCol* st[2];
     double* rho;
     double* bn;
 };
@@ -149,12 +202,15 @@ static CGWork carve_cg(Carver& c, const sc_op* op, int k, bool mixed) {
     if (mixed) {
         w.xs = c.take<float>(N2 * k);
         w.r64 = c.take<double>(N2 * k);
+        w.xg = c.take<double>(N2 * k);
     }
     w.ax64 = c.take<double>(N2 * k);
     w.tmp64 = c.take<double>(tmpn * k);
+    w.part_pq = c.take<double>((size_t)kMaxRedBlocks * k);
+    w.part_rr = c.take<double>((size_t)kMaxRedBlocks * k);
     w.part = c.take<double>((size_t)kMaxRedBlocks * k);
-    w.ctr = c.take<unsigned>(k);
-    w.st = c.take<CGCol>(k);
+    w.st[0] = c.take<CGCol>(k);
+    w.st[1] = c.take<CGCol>(k);
     w.rho = c.take<double>(k);
     w.bn = c.take<double>(k);
     return w;
@@ -166,19 +222,19 @@ size_t cg_workspace(const sc_op* op, int k, bool mixed) {
     return c.off + 256;
 }
 
-// r64 = b - A x (FP64), rr[j] = ||r64_j||^2
-static sc_status true_residual(const sc_op* op, const double* B, int64_t ldb2, const double* X, int64_t ldx2,
-                               int k, const CGWork& w, double* r64, double* rr, hipStream_t s) {
+// r64 = b - A x (FP64) for k columns, rr[j] = ||r64_j||^2
+static sc_status true_residual(const sc_op* op, const double* B, int64_t ldb2, const double* X, int64_t ldx2, int k,
+                               const CGWork& w, double* r64, int64_t ldr2, double* rr, hipStream_t s) {
     const bool cpl = is_complex(op->dtype);
     const int64_t N2 = op->n * (cpl ? 2 : 1);
     const int64_t div = cpl ? 2 : 1;
     SC_TRY(op_apply(op, false, X, ldx2 / div, w.ax64, op->n, k, w.tmp64, s));
-    SC_TRY(lincomb(0, r64, N2, 0, B, ldb2, 0, w.ax64, N2, N2, k, 1.0, -1.0, s));
-    SC_TRY(dot(0, r64, N2, 0, r64, N2, N2, k, rr, w.part, w.ctr, s));
+    SC_TRY(lincomb(0, r64, ldr2, 0, B, ldb2, 0, w.ax64, N2, N2, k, 1.0, -1.0, s));
+    SC_TRY(dot(0, r64, ldr2, 0, r64, ldr2, N2, k, rr, w.part, nullptr, s));
     return SC_OK;
 }
 
-template <typename R>
+template <typename R, bool VEC>
 static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ldb, double* X, int64_t ldx, int k,
                         double tol, int maxit, int* iters, double* relres, const CGWork& w, hipStream_t s,
                         sc_status* result) {
@@ -196,22 +252,22 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
     std::vector<CGCol> hst(k);
     std::vector<double> hrr(k);
     const int chunk = 8;
+    int cur = 0;  // index of the state copy the next iteration reads
 
-    SC_TRY(fill<unsigned>(w.ctr, k, 0u, s));
-    SC_TRY(dot(0, B, ldb2, 0, B, ldb2, N2, k, w.bn, w.part, w.ctr, s));
+    SC_TRY(dot(0, B, ldb2, 0, B, ldb2, N2, k, w.bn, w.part, nullptr, s));
     // r = b - A x; rho = ||r||^2
     double* r64 = mixed ? w.r64 : (double*)r;
-    SC_TRY(true_residual(op, B, ldb2, X, ldx2, k, w, r64, w.rho, s));
+    SC_TRY(true_residual(op, B, ldb2, X, ldx2, k, w, r64, N2, w.rho, s));
     if (mixed) {
         SC_TRY(lincomb(1, r, N2, 0, r64, N2, 0, nullptr, 0, N2, k, 1.0, 0.0, s));
         SC_TRY(fill<float>((float*)w.xs, N2 * k, 0.0f, s));
     }
     SC_TRY(lincomb(vt, p, N2, vt, r, N2, 0, nullptr, 0, N2, k, 1.0, 0.0, s));
-    hipLaunchKernelGGL(k_cg_setup, dim3((k + 63) / 64), dim3(64), 0, s, w.st, w.rho, w.bn, k, tol, maxit, 1);
+    hipLaunchKernelGGL(k_cg_setup, dim3((k + 63) / 64), dim3(64), 0, s, w.st[cur], w.rho, w.bn, k, tol, maxit, 1);
     SC_LAUNCH_CHECK();
 
     // columns with b = 0 are solved by x = 0
-    SC_HIP(hipMemcpyAsync(hst.data(), w.st, sizeof(CGCol) * k, hipMemcpyDeviceToHost, s));
+    SC_HIP(hipMemcpyAsync(hst.data(), w.st[cur], sizeof(CGCol) * k, hipMemcpyDeviceToHost, s));
     SC_HIP(hipStreamSynchronize(s));
     for (int j = 0; j < k; ++j)
         if (!(hst[j].bnorm2 > 0.0)) SC_TRY(lincomb(0, X + j * ldx2, N2, 0, X + j * ldx2, N2, 0, nullptr, 0, N2, 1, 0.0, 0.0, s));
@@ -223,40 +279,49 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
         while (any) {
             for (int it = 0; it < chunk; ++it) {
                 SC_TRY(op_apply(op, mixed, p, op->n, q, op->n, k, w.tmp, s));
-                hipLaunchKernelGGL(k_cg_alpha<R>, grid, blk, 0, s, p, q, N2, N2, w.st, w.part, w.ctr);
+                hipLaunchKernelGGL((k_cg_pq<R, VEC>), grid, blk, 0, s, p, q, N2, N2, w.st[cur], w.part_pq);
                 SC_LAUNCH_CHECK();
                 if (mixed)
-                    hipLaunchKernelGGL((k_cg_xr<float, R>), grid, blk, 0, s, (float*)w.xs, N2, r, p, q, N2, N2, w.st, 1,
-                                       w.part, w.ctr);
+                    hipLaunchKernelGGL((k_cg_xr<float, R, VEC>), grid, blk, 0, s, (float*)w.xs, N2, r, p, q, N2, N2,
+                                       w.st[cur], w.part_pq, g, w.part_rr);
                 else
-                    hipLaunchKernelGGL((k_cg_xr<double, R>), grid, blk, 0, s, X, ldx2, r, p, q, N2, N2, w.st, 0,
-                                       w.part, w.ctr);
+                    hipLaunchKernelGGL((k_cg_xr<double, R, VEC>), grid, blk, 0, s, X, ldx2, r, p, q, N2, N2,
+                                       w.st[cur], w.part_pq, g, w.part_rr);
                 SC_LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_cg_p<R>, grid, blk, 0, s, p, r, N2, N2, w.st);
+                hipLaunchKernelGGL((k_cg_p<R, VEC>), grid, blk, 0, s, p, r, N2, N2, w.st[cur], w.st[1 - cur],
+                                   w.part_rr, g, mixed ? 1 : 0);
                 SC_LAUNCH_CHECK();
+                cur = 1 - cur;
             }
-            SC_HIP(hipMemcpyAsync(hst.data(), w.st, sizeof(CGCol) * k, hipMemcpyDeviceToHost, s));
+            SC_HIP(hipMemcpyAsync(hst.data(), w.st[cur], sizeof(CGCol) * k, hipMemcpyDeviceToHost, s));
             SC_HIP(hipStreamSynchronize(s));
             any = false;
-            bool upd = false;
+            std::vector<int> upd;
             for (int j = 0; j < k; ++j) {
                 any |= hst[j].active != 0;
-                upd |= mixed && hst[j].flag != 0 && hst[j].iters < hst[j].maxit;
+                if (mixed && hst[j].flag != 0 && hst[j].iters < hst[j].maxit) upd.push_back(j);
             }
-            if (mixed && upd) {
+            if (!upd.empty()) {
                 // reliable update of the paused columns: x64 += xs; r64 = b - A x64; r = r64; xs = 0
-                for (int j = 0; j < k; ++j) {
-                    if (!hst[j].flag || hst[j].iters >= hst[j].maxit) continue;
+                const int nu = (int)upd.size();
+                for (int c = 0; c < nu; ++c) {
+                    const int j = upd[c];
                     float* xs = (float*)w.xs + j * N2;
                     SC_TRY(lincomb(0, X + j * ldx2, N2, 0, X + j * ldx2, N2, 1, xs, N2, N2, 1, 1.0, 1.0, s));
                     SC_TRY(fill<float>(xs, N2, 0.0f, s));
+                    SC_TRY(lincomb(0, w.xg + c * N2, N2, 0, X + j * ldx2, N2, 0, nullptr, 0, N2, 1, 1.0, 0.0, s));
                 }
-                SC_TRY(true_residual(op, B, ldb2, X, ldx2, k, w, w.r64, w.rho, s));
+                SC_TRY(op_apply(op, false, w.xg, op->n, w.ax64, op->n, nu, w.tmp64, s));
+                for (int c = 0; c < nu; ++c) {
+                    const int j = upd[c];
+                    SC_TRY(lincomb(0, w.r64 + j * N2, N2, 0, B + j * ldb2, N2, 0, w.ax64 + c * N2, N2, N2, 1, 1.0,
+                                   -1.0, s));
+                    SC_TRY(dot(0, w.r64 + j * N2, N2, 0, w.r64 + j * N2, N2, N2, 1, w.rho + j, w.part, nullptr, s));
+                }
                 SC_HIP(hipMemcpyAsync(hrr.data(), w.rho, sizeof(double) * k, hipMemcpyDeviceToHost, s));
                 SC_HIP(hipStreamSynchronize(s));
-                for (int j = 0; j < k; ++j) {
+                for (int j : upd) {
                     CGCol& c = hst[j];
-                    if (!c.flag || c.iters >= c.maxit) continue;
                     R* rj = r + j * N2;
                     R* pj = p + j * N2;
                     SC_TRY(lincomb(1, rj, N2, 0, w.r64 + j * N2, N2, 0, nullptr, 0, N2, 1, 1.0, 0.0, s));
@@ -274,7 +339,7 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
                     c.flag = 0;
                     any |= c.active != 0;
                 }
-                SC_HIP(hipMemcpyAsync(w.st, hst.data(), sizeof(CGCol) * k, hipMemcpyHostToDevice, s));
+                SC_HIP(hipMemcpyAsync(w.st[cur], hst.data(), sizeof(CGCol) * k, hipMemcpyHostToDevice, s));
                 SC_HIP(hipStreamSynchronize(s));
             }
         }
@@ -284,7 +349,7 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
             SC_TRY(fill<float>((float*)w.xs, N2 * k, 0.0f, s));
         }
         // verify on the true residual
-        SC_TRY(true_residual(op, B, ldb2, X, ldx2, k, w, mixed ? w.r64 : (double*)r, w.rho, s));
+        SC_TRY(true_residual(op, B, ldb2, X, ldx2, k, w, r64, N2, w.rho, s));
         SC_HIP(hipMemcpyAsync(hrr.data(), w.rho, sizeof(double) * k, hipMemcpyDeviceToHost, s));
         SC_HIP(hipStreamSynchronize(s));
         bool again = false;
@@ -297,13 +362,11 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
         if (!again || restarts >= 5) break;
         ++restarts;
         // restart every column from its true residual (converged ones stay inactive)
-        if (mixed) {
-            SC_TRY(lincomb(1, r, N2, 0, w.r64, N2, 0, nullptr, 0, N2, k, 1.0, 0.0, s));
-        }
+        if (mixed) SC_TRY(lincomb(1, r, N2, 0, w.r64, N2, 0, nullptr, 0, N2, k, 1.0, 0.0, s));
         SC_TRY(lincomb(vt, p, N2, vt, r, N2, 0, nullptr, 0, N2, k, 1.0, 0.0, s));
-        hipLaunchKernelGGL(k_cg_setup, dim3((k + 63) / 64), dim3(64), 0, s, w.st, w.rho, w.bn, k, tol, maxit, 0);
+        hipLaunchKernelGGL(k_cg_setup, dim3((k + 63) / 64), dim3(64), 0, s, w.st[cur], w.rho, w.bn, k, tol, maxit, 0);
         SC_LAUNCH_CHECK();
-        SC_HIP(hipMemcpyAsync(hst.data(), w.st, sizeof(CGCol) * k, hipMemcpyDeviceToHost, s));
+        SC_HIP(hipMemcpyAsync(hst.data(), w.st[cur], sizeof(CGCol) * k, hipMemcpyDeviceToHost, s));
         SC_HIP(hipStreamSynchronize(s));
     }
     *result = SC_OK;
@@ -321,10 +384,19 @@ sc_status solve_cg(const sc_op* op, int mixed, const void* B, int64_t ldb, void*
         return SC_ERR_WORKSPACE;
     }
     sc_status result = SC_OK;
-    if (mixed)
-        SC_TRY(cg_run<float>(op, true, (const double*)B, ldb, (double*)X, ldx, k, tol, maxit, iters, relres, w, s, &result));
-    else
-        SC_TRY(cg_run<double>(op, false, (const double*)B, ldb, (double*)X, ldx, k, tol, maxit, iters, relres, w, s, &result));
+    const bool cpl = is_complex(op->dtype);
+    const int64_t N2 = op->n * (cpl ? 2 : 1);
+    const int64_t mul = cpl ? 2 : 1;
+    if (mixed) {
+        // packs of 4 floats: columns of r, p, q, xs are N2 floats apart
+        const bool vec = (N2 % 4) == 0;
+        if (vec) SC_TRY((cg_run<float, true>(op, true, (const double*)B, ldb, (double*)X, ldx, k, tol, maxit, iters, relres, w, s, &result)));
+        else SC_TRY((cg_run<float, false>(op, true, (const double*)B, ldb, (double*)X, ldx, k, tol, maxit, iters, relres, w, s, &result)));
+    } else {
+        const bool vec = (N2 % 2) == 0 && ((uintptr_t)X % 16) == 0 && ((ldx * mul) % 2) == 0;
+        if (vec) SC_TRY((cg_run<double, true>(op, false, (const double*)B, ldb, (double*)X, ldx, k, tol, maxit, iters, relres, w, s, &result)));
+        else SC_TRY((cg_run<double, false>(op, false, (const double*)B, ldb, (double*)X, ldx, k, tol, maxit, iters, relres, w, s, &result)));
+    }
     if (result == SC_NOT_CONVERGED) set_error("solve_cg: some right-hand side is above tol at maxit");
     return result;
 }

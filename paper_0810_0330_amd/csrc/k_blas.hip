@@ -1,6 +1,6 @@
 // Streaming vector kernels on real views (a complex column of n elements is
 // 2n reals): linear combinations with precision conversion, and dot products
-// accumulated in FP64 with a deterministic split reduction.
+// accumulated in FP64 (per-block partials, then a fixed-order finish).
 #include "sc_internal.h"
 
 namespace sc {
@@ -24,7 +24,7 @@ template sc_status fill<unsigned>(unsigned*, int64_t, unsigned, hipStream_t);
 template sc_status fill<int>(int*, int64_t, int, hipStream_t);
 template sc_status fill<float>(float*, int64_t, float, hipStream_t);
 
-// z = a x + b y
+// z = a x + b y (4 elements per thread-iteration)
 template <typename ZT, typename XT, typename YT>
 __global__ __launch_bounds__(kBlock) void k_lincomb(ZT* __restrict__ z, int64_t ldz, const XT* __restrict__ x,
                                                     int64_t ldx, const YT* __restrict__ y, int64_t ldy, int64_t N,
@@ -33,17 +33,24 @@ __global__ __launch_bounds__(kBlock) void k_lincomb(ZT* __restrict__ z, int64_t 
     ZT* zc = z + col * ldz;
     const XT* xc = x + col * ldx;
     const YT* yc = y ? y + col * ldy : nullptr;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock) {
-        double v = a * (double)xc[i];
-        if (yc) v += b * (double)yc[i];
-        zc[i] = (ZT)v;
+    const int64_t stride = (int64_t)gridDim.x * kBlock * 4;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 4; i0 < N; i0 += stride) {
+        const int64_t i1 = min(N, i0 + 4);
+#pragma unroll
+        for (int64_t i = i0; i < i0 + 4; ++i) {
+            if (i < i1) {
+                double v = a * (double)xc[i];
+                if (yc) v += b * (double)yc[i];
+                zc[i] = (ZT)v;
+            }
+        }
     }
 }
 
 template <typename ZT, typename XT>
 static void lincomb_y(int yt, ZT* z, int64_t ldz, const XT* x, int64_t ldx, const void* y, int64_t ldy, int64_t N,
                       int k, double a, double b, hipStream_t s) {
-    dim3 grid((unsigned)std::min<int64_t>((N + kBlock - 1) / kBlock, 2048), (unsigned)k);
+    dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((N + 4 * kBlock - 1) / (4 * kBlock), 2048)), (unsigned)k);
     if (yt == 0)
         hipLaunchKernelGGL((k_lincomb<ZT, XT, double>), grid, dim3(kBlock), 0, s, z, ldz, x, ldx, (const double*)y, ldy, N, a, b);
     else
@@ -66,10 +73,10 @@ sc_status lincomb(int zt, void* z, int64_t ldz, int xt, const void* x, int64_t l
     return SC_OK;
 }
 
-// res[col] = sum x*y
+// partial sums of x*y per block and column
 template <typename XT, typename YT>
-__global__ __launch_bounds__(kBlock) void k_dot(const XT* __restrict__ x, int64_t ldx, const YT* __restrict__ y,
-                                                int64_t ldy, int64_t N, double* res, double* part, unsigned* ctr) {
+__global__ __launch_bounds__(kBlock) void k_dot_part(const XT* __restrict__ x, int64_t ldx, const YT* __restrict__ y,
+                                                     int64_t ldy, int64_t N, double* part) {
     __shared__ double sh[kWaves];
     const int col = blockIdx.y;
     const XT* xc = x + col * ldx;
@@ -77,27 +84,32 @@ __global__ __launch_bounds__(kBlock) void k_dot(const XT* __restrict__ x, int64_
     double acc = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock)
         acc += (double)xc[i] * (double)yc[i];
-    double tot;
-    if (split_reduce(acc, part + (int64_t)col * gridDim.x, ctr + col, &tot, sh)) {
-        if (threadIdx.x == 0) res[col] = tot;
-    }
+    block_partial(acc, part + (int64_t)col * gridDim.x, sh);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot_finish(const double* part, int G, double* res) {
+    __shared__ double sh[kWaves];
+    const double s = sum_partials(part + (int64_t)blockIdx.x * G, G, sh);
+    if (threadIdx.x == 0) res[blockIdx.x] = s;
 }
 
 template <typename XT>
 static void dot_y(int yt, const XT* x, int64_t ldx, const void* y, int64_t ldy, int64_t N, int k, double* res,
-                  double* part, unsigned* ctr, hipStream_t s) {
-    dim3 grid((unsigned)red_grid(N), (unsigned)k);
+                  double* part, hipStream_t s) {
+    const int g = red_grid(N, 4);
+    dim3 grid((unsigned)g, (unsigned)k);
     if (yt == 0)
-        hipLaunchKernelGGL((k_dot<XT, double>), grid, dim3(kBlock), 0, s, x, ldx, (const double*)y, ldy, N, res, part, ctr);
+        hipLaunchKernelGGL((k_dot_part<XT, double>), grid, dim3(kBlock), 0, s, x, ldx, (const double*)y, ldy, N, part);
     else
-        hipLaunchKernelGGL((k_dot<XT, float>), grid, dim3(kBlock), 0, s, x, ldx, (const float*)y, ldy, N, res, part, ctr);
+        hipLaunchKernelGGL((k_dot_part<XT, float>), grid, dim3(kBlock), 0, s, x, ldx, (const float*)y, ldy, N, part);
+    hipLaunchKernelGGL(k_dot_finish, dim3(k), dim3(kBlock), 0, s, part, g, res);
 }
 
 sc_status dot(int xt, const void* x, int64_t ldx, int yt, const void* y, int64_t ldy, int64_t N, int k, double* res,
-              double* part, unsigned* ctr, hipStream_t s) {
+              double* part, unsigned* /*unused*/, hipStream_t s) {
     if (k <= 0) return SC_OK;
-    if (xt == 0) dot_y<double>(yt, (const double*)x, ldx, y, ldy, N, k, res, part, ctr, s);
-    else dot_y<float>(yt, (const float*)x, ldx, y, ldy, N, k, res, part, ctr, s);
+    if (xt == 0) dot_y<double>(yt, (const double*)x, ldx, y, ldy, N, k, res, part, s);
+    else dot_y<float>(yt, (const float*)x, ldx, y, ldy, N, k, res, part, s);
     SC_LAUNCH_CHECK();
     return SC_OK;
 }

@@ -68,7 +68,7 @@ __device__ __forceinline__ void st2(R* p, int64_t idx, cplx<R> c) {
 // ---------------------------------------------------------------- reductions
 constexpr int kBlock = 256;          // threads per block of the streaming kernels
 constexpr int kWaves = kBlock / 64;  // 64-wide wavefronts
-constexpr int kMaxRedBlocks = 1024;  // split-reduction width cap
+constexpr int kMaxRedBlocks = 512;   // split-reduction width cap
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -89,34 +89,39 @@ __device__ __forceinline__ double block_sum(double v, double* sh /* kWaves doubl
     return t;
 }
 
-// Split reduction across the blocks of one grid row: every block deposits its
-// partial in part[blockIdx.x]; the last block to arrive (counted in *ctr)
-// adds them in index order, so the result depends only on the data and the
-// grid width, never on scheduling.  Returns true in the last block, where
-// *total holds the sum (valid in every thread of that block).  The counter is
-// reset by the last block, ready for the next launch.
-__device__ __forceinline__ bool split_reduce(double v, double* part, unsigned* ctr, double* total,
-                                            double* sh) {
-    __shared__ int am_last;
-    double b = block_sum(v, sh);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = b;
-        __threadfence();
-        unsigned prev = atomicAdd(ctr, 1u);
-        am_last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!am_last) return false;
-    __threadfence();
-    double s = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) s += part[i];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) *ctr = 0u;
-    *total = s;
-    return true;
+// Cross-block reductions without device-scope fences: a producer kernel
+// leaves one partial per block (block_partial); every block of a consumer
+// kernel adds all of them in index order (sum_partials), so each block gets the
+// same, deterministic value.  Kernel boundaries order the two.  (An in-kernel
+// last-block scheme needs an agent-scope release per block, which on a
+// multi-XCD part writes back the L2 and costs more than the re-summation.)
+__device__ __forceinline__ void block_partial(double v, double* part, double* sh) {
+    const double b = block_sum(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = b;
 }
 
-inline int red_grid(int64_t n_items, int per_thread = 4) {
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int G, double* sh) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < G; i += blockDim.x) s += part[i];
+    return block_sum(s, sh);
+}
+
+// 16-byte packs for the streaming kernels (dwordx4 loads and stores)
+template <typename R>
+struct alignas(16) Pack {
+    static constexpr int W = 16 / sizeof(R);
+    R v[W];
+};
+template <typename R>
+__device__ __forceinline__ Pack<R> ldp(const R* p, int64_t i) {
+    return *reinterpret_cast<const Pack<R>*>(p + i);
+}
+template <typename R>
+__device__ __forceinline__ void stp(R* p, int64_t i, const Pack<R>& v) {
+    *reinterpret_cast<Pack<R>*>(p + i) = v;
+}
+
+inline int red_grid(int64_t n_items, int per_thread = 16) {
     int64_t g = (n_items + (int64_t)kBlock * per_thread - 1) / ((int64_t)kBlock * per_thread);
     if (g < 1) g = 1;
     if (g > kMaxRedBlocks) g = kMaxRedBlocks;

@@ -43,6 +43,12 @@ int64_t op_apply_tmp_elems(const sc_op* op);
 sc_status wilson_pass(const sc_op* op, bool single, int which, const void* X, int64_t ldx, void* Y, int64_t ldy,
                       int k, hipStream_t s);
 
+// autotuned stencil launch shape for (op lattice, precision, k): variant id
+// (-1 if not tuned yet) and the measured microseconds of each candidate
+sc_status wilson_tune_query(const sc_op* op, bool single, int k, int* variant, float* us);
+// pin a variant for (lattice, precision, k); variant < 0 forgets the choice
+sc_status wilson_tune_pin(const sc_op* op, bool single, int k, int variant);
+
 // ---------------------------------------------------------------- streaming kernels (k_blas.hip)
 // All act on "real views": a complex column of n elements is 2n reals.
 // z = a*x + b*y  (y may be null when b == 0); types: 0 = double, 1 = float

@@ -15,11 +15,12 @@ namespace sc {
 
 constexpr double kBreakdownTol = 1e-12;  // beta_i <= kBreakdownTol * max |alpha_k|: invariant subspace
 
+// Device state of the phase.  Fields are written by block 0 of one kernel and
+// read by later kernels only, except `halt`, which a kernel may set while its
+// other blocks run: a block that already sees it skips work whose results the
+// halt makes unused.
 struct SeedState {
-    double bsq;      // ||f||^2 of the current step
     double amax;     // max_k |alpha_k|
-    double delta;    // LU pivot delta_i of T
-    double vnorm2;   // ||v_i||^2 during reorthogonalization
     int halt;        // nonzero: stop every later kernel of the phase
     int halt_step;   // step at which halt was decided
     int status;      // sc_status of the halt
@@ -27,126 +28,156 @@ struct SeedState {
 };
 
 __global__ void k_seed_init(SeedState* st) {
-    st->bsq = 0.0;
     st->amax = 0.0;
-    st->delta = 0.0;
-    st->vnorm2 = 0.0;
     st->halt = 0;
     st->halt_step = 0;
     st->status = SC_OK;
     st->m_done = 0;
 }
 
-// beta_i = ||f|| after step 8 (step 9), with the breakdown and finiteness checks
-__device__ void finish_beta(SeedState* st, double* beta, int i, double bsq) {
-    const double b = sqrt(bsq);
-    beta[i] = b;
-    if (!isfinite(b)) {
-        st->status = SC_ERR_NONFINITE;
-        st->halt_step = i;
-        st->m_done = i > 0 ? i - 1 : 0;
-        st->halt = 1;
-    } else if (i == 0 ? !(b > 0.0) : !(b > kBreakdownTol * st->amax)) {
-        st->status = SC_BREAKDOWN;
-        st->halt_step = i;
-        st->m_done = i;
-        st->halt = 1;
-    } else {
-        st->m_done = i;
-    }
-}
-
-// ||x||^2 with the beta_i epilogue (i = 0: beta_0 of step 2)
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_lz_norm(const R* __restrict__ x, int64_t N, double* beta, int i,
-                                                    SeedState* st, double* part, unsigned* ctr) {
+// partials of ||x||^2
+template <typename R, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_norm_part(const R* __restrict__ x, int64_t N, double* part,
+                                                      const int* halt) {
     __shared__ double sh[kWaves];
-    if (st->halt) return;
+    if (halt && *halt) return;
+    constexpr int W = Pack<R>::W;
     double acc = 0.0;
-    for (int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x; j < N; j += (int64_t)gridDim.x * kBlock) {
-        const double v = (double)x[j];
-        acc += v * v;
+    const int64_t stride = (int64_t)gridDim.x * kBlock * W;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W; i0 < N; i0 += stride) {
+        if (VEC && i0 + W <= N) {
+            const Pack<R> a = ldp(x, i0);
+#pragma unroll
+            for (int e = 0; e < W; ++e) acc += (double)a.v[e] * (double)a.v[e];
+        } else {
+            for (int64_t j = i0; j < min(N, i0 + W); ++j) acc += (double)x[j] * (double)x[j];
+        }
     }
-    double tot;
-    if (split_reduce(acc, part, ctr, &tot, sh) && threadIdx.x == 0) finish_beta(st, beta, i, tot);
+    block_partial(acc, part, sh);
 }
 
-// v_{i+1} = f / beta_i, stored as column i of V.  Runs after the halt decision of
-// step i was taken by an earlier kernel, so it only reads the flags.
+// step 9 (and step 2 for i = 0): beta_i = ||f|| from the partials, breakdown
+// and finiteness checks, v_{i+1} = f / beta_i stored as column i of V
 template <typename VT, typename FT>
 __global__ __launch_bounds__(kBlock) void k_lz_next(VT* __restrict__ vnext, const FT* __restrict__ f, int64_t N,
-                                                    const double* beta, int i, const SeedState* st) {
-    const bool brk_here = st->halt && st->status == SC_BREAKDOWN && st->halt_step == i;
-    if (st->halt && !brk_here) return;
-    const FT b = (FT)beta[i];
-    for (int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x; j < N; j += (int64_t)gridDim.x * kBlock)
-        vnext[j] = brk_here ? VT(0) : (VT)(f[j] / b);
-}
-
-// step 5, first half: f = A v_i - beta_{i-1} v_{i-1}; alpha_i = Re(v_i^H f)
-// (+ the pivot delta_i = alpha_i - beta_{i-1}^2 / delta_{i-1} of step 6)
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_lz_alpha(R* __restrict__ f, const R* __restrict__ Av,
-                                                     const R* __restrict__ vi, const R* __restrict__ vprev,
-                                                     int64_t N, const double* beta, double* alpha, int i,
-                                                     SeedState* st, double* part, unsigned* ctr) {
+                                                    double* beta, int i, SeedState* st, const double* part, int G) {
     __shared__ double sh[kWaves];
     if (st->halt) return;
-    const double bprev = i > 1 ? beta[i - 1] : 0.0;
-    const R bp = (R)bprev;
-    double acc = 0.0;
-    for (int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x; j < N; j += (int64_t)gridDim.x * kBlock) {
-        const R fv = i > 1 ? Av[j] - bp * vprev[j] : Av[j];
-        f[j] = fv;
-        acc += (double)vi[j] * (double)fv;
-    }
-    double tot;
-    if (split_reduce(acc, part, ctr, &tot, sh) && threadIdx.x == 0) {
-        alpha[i - 1] = tot;
-        const double d = (i == 1) ? tot : tot - bprev * bprev / st->delta;
-        if (!isfinite(tot)) {
+    const double b = sqrt(sum_partials(part, G, sh));
+    const bool fin = isfinite(b);
+    const bool brk = fin && (i == 0 ? !(b > 0.0) : !(b > kBreakdownTol * st->amax));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        beta[i] = b;
+        if (!fin) {
             st->status = SC_ERR_NONFINITE;
             st->halt_step = i;
-            st->m_done = i - 1;
+            st->m_done = i > 0 ? i - 1 : 0;
             st->halt = 1;
-        } else if (!(d > 0.0)) {
-            st->status = SC_ERR_NOT_PD;
+        } else if (brk) {
+            st->status = SC_BREAKDOWN;
+            st->halt_step = i;
+            st->m_done = i;
+            st->halt = 1;
+        } else {
+            st->m_done = i;
+        }
+    }
+    const FT bf = (FT)b;
+    const bool zero = brk || !fin;
+    for (int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x; j < N; j += (int64_t)gridDim.x * kBlock)
+        vnext[j] = zero ? VT(0) : (VT)(f[j] / bf);
+}
+
+// step 5, first half: f = A v_i - beta_{i-1} v_{i-1}; partials of Re(v_i^H f)
+template <typename R, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_lz_alpha(R* __restrict__ f, const R* __restrict__ Av,
+                                                     const R* __restrict__ vi, const R* __restrict__ vprev,
+                                                     int64_t N, const double* beta, int i, const SeedState* st,
+                                                     double* part) {
+    __shared__ double sh[kWaves];
+    if (st->halt) return;
+    constexpr int W = Pack<R>::W;
+    const R bp = (R)(i > 1 ? beta[i - 1] : 0.0);
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock * W;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W; i0 < N; i0 += stride) {
+        if (VEC && i0 + W <= N) {
+            const Pack<R> a = ldp(Av, i0), pv = ldp(vprev, i0), v = ldp(vi, i0);
+            Pack<R> o;
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                o.v[e] = a.v[e] - bp * pv.v[e];
+                acc += (double)v.v[e] * (double)o.v[e];
+            }
+            stp(f, i0, o);
+        } else {
+            for (int64_t j = i0; j < min(N, i0 + W); ++j) {
+                const R fv = Av[j] - bp * vprev[j];
+                f[j] = fv;
+                acc += (double)vi[j] * (double)fv;
+            }
+        }
+    }
+    block_partial(acc, part, sh);
+}
+
+// step 5, second half: alpha_i from the partials (+ the LU pivot
+// delta_i = alpha_i - beta_{i-1}^2 / delta_{i-1} of step 6, which must stay
+// positive for an HPD A); f -= alpha_i v_i; partials of ||f||^2
+template <typename R, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_lz_f(R* __restrict__ f, const R* __restrict__ vi, int64_t N,
+                                                 double* alpha, const double* beta, double* delta, int i,
+                                                 SeedState* st, const double* part_a, int G, double* part_f) {
+    __shared__ double sh[kWaves];
+    if (st->halt) return;
+    constexpr int W = Pack<R>::W;
+    const double a = sum_partials(part_a, G, sh);
+    const double d = (i == 1) ? a : a - beta[i - 1] * beta[i - 1] / delta[i - 1];
+    const bool bad = !isfinite(a) || !(d > 0.0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        alpha[i - 1] = a;
+        delta[i] = d;
+        if (bad) {
+            st->status = isfinite(a) ? SC_ERR_NOT_PD : SC_ERR_NONFINITE;
             st->halt_step = i;
             st->m_done = i - 1;
             st->halt = 1;
         } else {
-            st->delta = d;
-            st->amax = fmax(st->amax, fabs(tot));
+            st->amax = fmax(st->amax, fabs(a));
         }
     }
-}
-
-// step 5, second half: f -= alpha_i v_i (+ ||f||^2 and the beta_i epilogue
-// when no reorthogonalization follows at this step)
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_lz_f(R* __restrict__ f, const R* __restrict__ vi, int64_t N,
-                                                 const double* alpha, double* beta, int i, int with_norm,
-                                                 SeedState* st, double* part, unsigned* ctr) {
-    __shared__ double sh[kWaves];
-    if (st->halt) return;
-    const R a = (R)alpha[i - 1];
+    if (bad) return;
+    const R aR = (R)a;
     double acc = 0.0;
-    for (int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x; j < N; j += (int64_t)gridDim.x * kBlock) {
-        const R fv = f[j] - a * vi[j];
-        f[j] = fv;
-        acc += (double)fv * (double)fv;
+    const int64_t stride = (int64_t)gridDim.x * kBlock * W;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W; i0 < N; i0 += stride) {
+        if (VEC && i0 + W <= N) {
+            Pack<R> o = ldp(f, i0);
+            const Pack<R> v = ldp(vi, i0);
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                o.v[e] = o.v[e] - aR * v.v[e];
+                acc += (double)o.v[e] * (double)o.v[e];
+            }
+            stp(f, i0, o);
+        } else {
+            for (int64_t j = i0; j < min(N, i0 + W); ++j) {
+                const R fv = f[j] - aR * vi[j];
+                f[j] = fv;
+                acc += (double)fv * (double)fv;
+            }
+        }
     }
-    if (!with_norm) return;
-    double tot;
-    if (split_reduce(acc, part, ctr, &tot, sh) && threadIdx.x == 0) finish_beta(st, beta, i, tot);
+    block_partial(acc, part_f, sh);
 }
 
-// v /= sqrt(nrm2)
+// v /= ||v|| (norm from partials)
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_scale_norm(R* __restrict__ v, int64_t N, const double* nrm2,
+__global__ __launch_bounds__(kBlock) void k_scale_norm(R* __restrict__ v, int64_t N, const double* part, int G,
                                                        const int* halt) {
+    __shared__ double sh[kWaves];
     if (*halt) return;
-    const R nr = (R)sqrt(*nrm2);
+    const R nr = (R)sqrt(sum_partials(part, G, sh));
     for (int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x; j < N; j += (int64_t)gridDim.x * kBlock)
         v[j] = v[j] / nr;
 }
@@ -159,8 +190,10 @@ struct SeedWork {
     double* r64;     // r0^1           (FP64)
     double* ax64;    // A x0           (FP64)
     void* tmp64;     // op scratch     (FP64)
-    double* part;    // split-reduction partials
-    unsigned* ctr;   // split-reduction counters (2)
+    double* part_a;  // partials of alpha_i
+    double* part_f;  // partials of ||f||^2
+    double* part_v;  // partials of ||v_i||^2 (reorthogonalization)
+    double* delta;   // LU pivots delta_1..delta_m (index i)
     SeedState* st;
     double* G;       // reorthogonalization coefficients, (m) x 2 complex
     double* G2;      // one complex coefficient
@@ -181,8 +214,10 @@ static SeedWork carve_seed(Carver& c, const sc_op* op, int m, bool single) {
     w.r64 = c.take<double>(N2);
     w.ax64 = c.take<double>(N2);
     w.tmp64 = c.take<double>(std::max<int64_t>(tmpn, 1));
-    w.part = c.take<double>(kMaxRedBlocks);
-    w.ctr = c.take<unsigned>(2);
+    w.part_a = c.take<double>(kMaxRedBlocks);
+    w.part_f = c.take<double>(kMaxRedBlocks);
+    w.part_v = c.take<double>(kMaxRedBlocks);
+    w.delta = c.take<double>((size_t)m + 2);
     w.st = c.take<SeedState>(1);
     w.G = c.take<double>((size_t)std::max(m, 1) * 4);
     w.G2 = c.take<double>(4);
@@ -198,7 +233,7 @@ size_t seed_workspace(const sc_op* op, int m, bool single) {
     return c.off + 256;
 }
 
-template <typename R>
+template <typename R, bool VEC>
 static sc_status seed_run(const sc_op* op, const void* b1, void* x1, int m, int freq, R* V, int64_t ldv,
                           double* alpha, double* beta, int* m_done, const SeedWork& w, hipStream_t s,
                           sc_status* result) {
@@ -206,7 +241,6 @@ static sc_status seed_run(const sc_op* op, const void* b1, void* x1, int m, int 
     const bool cpl = is_complex(op->dtype);
     const int64_t N2 = op->n * (cpl ? 2 : 1);
     const int64_t ldv2 = ldv * (cpl ? 2 : 1);  // in reals
-    const int rt = single ? 1 : 0;
     const int g = red_grid(N2);
     const dim3 blk(kBlock);
     R* f = (R*)w.f;
@@ -215,15 +249,14 @@ static sc_status seed_run(const sc_op* op, const void* b1, void* x1, int m, int 
 
     hipLaunchKernelGGL(k_seed_init, dim3(1), dim3(1), 0, s, w.st);
     SC_LAUNCH_CHECK();
-    SC_TRY(fill<unsigned>(w.ctr, 2, 0u, s));
 
     // step 1: r0 = b1 - A x0 (FP64)
     SC_TRY(op_apply(op, false, x1, op->n, w.ax64, op->n, 1, w.tmp64, s));
     SC_TRY(lincomb(0, w.r64, N2, 0, b1, N2, 0, w.ax64, N2, N2, 1, 1.0, -1.0, s));
     // step 2: beta_0 = ||r0||, v_1 = r0 / beta_0
-    hipLaunchKernelGGL(k_lz_norm<double>, dim3(g), blk, 0, s, w.r64, N2, beta, 0, w.st, w.part, w.ctr);
+    hipLaunchKernelGGL((k_norm_part<double, VEC>), dim3(g), blk, 0, s, w.r64, N2, w.part_f, nullptr);
     SC_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_lz_next<R, double>), dim3(g), blk, 0, s, V, w.r64, N2, beta, 0, w.st);
+    hipLaunchKernelGGL((k_lz_next<R, double>), dim3(g), blk, 0, s, V, w.r64, N2, beta, 0, w.st, w.part_f, g);
     SC_LAUNCH_CHECK();
 
     for (int i = 1; i <= m; ++i) {
@@ -232,14 +265,12 @@ static sc_status seed_run(const sc_op* op, const void* b1, void* x1, int m, int 
         R* vnext = V + (int64_t)i * ldv2;
         // step 5: f = A v_i - beta_{i-1} v_{i-1}; alpha_i; f -= alpha_i v_i
         SC_TRY(op_apply(op, single, vi, ldv, av, op->n, 1, w.tmp, s));
-        hipLaunchKernelGGL(k_lz_alpha<R>, dim3(g), blk, 0, s, f, av, vi, vprev, N2, beta, alpha, i, w.st, w.part,
-                           w.ctr);
+        hipLaunchKernelGGL((k_lz_alpha<R, VEC>), dim3(g), blk, 0, s, f, av, vi, vprev, N2, beta, i, w.st, w.part_a);
         SC_LAUNCH_CHECK();
-        const bool due = freq > 0 && i >= 2 && i % freq == 0;
-        hipLaunchKernelGGL(k_lz_f<R>, dim3(g), blk, 0, s, f, vi, N2, alpha, beta, i, due ? 0 : 1, w.st, w.part,
-                           w.ctr);
+        hipLaunchKernelGGL((k_lz_f<R, VEC>), dim3(g), blk, 0, s, f, vi, N2, alpha, beta, w.delta, i, w.st, w.part_a,
+                           g, w.part_f);
         SC_LAUNCH_CHECK();
-        if (due) {
+        if (freq > 0 && i >= 2 && i % freq == 0) {
             // step 8: [v_i, f] -= V_{i-1} (V_{i-1}^H [v_i, f]); v_i /= ||v_i||; f -= v_i (v_i^H f)
             ColPtrs<const void> wc{};
             wc.p[0] = vi;
@@ -249,8 +280,9 @@ static sc_status seed_run(const sc_op* op, const void* b1, void* x1, int m, int 
             xc.p[1] = f;
             SC_TRY(gemm_cn(cpl, single, V, ldv, op->n, i - 1, single, wc, 2, w.G, w.gpart, halt, s));
             SC_TRY(gemm_nn(cpl, single, V, ldv, op->n, i - 1, w.G, 2, single, xc, -1.0, halt, s));
-            SC_TRY(dot(rt, vi, N2, rt, vi, N2, N2, 1, &w.st->vnorm2, w.part, w.ctr + 1, s));
-            hipLaunchKernelGGL(k_scale_norm<R>, dim3(g), blk, 0, s, vi, N2, &w.st->vnorm2, halt);
+            hipLaunchKernelGGL((k_norm_part<R, VEC>), dim3(g), blk, 0, s, vi, N2, w.part_v, halt);
+            SC_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_scale_norm<R>, dim3(g), blk, 0, s, vi, N2, w.part_v, g, halt);
             SC_LAUNCH_CHECK();
             ColPtrs<const void> fc{};
             fc.p[0] = f;
@@ -258,11 +290,11 @@ static sc_status seed_run(const sc_op* op, const void* b1, void* x1, int m, int 
             fo.p[0] = f;
             SC_TRY(gemm_cn(cpl, single, vi, ldv, op->n, 1, single, fc, 1, w.G2, w.gpart, halt, s));
             SC_TRY(gemm_nn(cpl, single, vi, ldv, op->n, 1, w.G2, 1, single, fo, -1.0, halt, s));
-            hipLaunchKernelGGL(k_lz_norm<R>, dim3(g), blk, 0, s, f, N2, beta, i, w.st, w.part, w.ctr);
+            hipLaunchKernelGGL((k_norm_part<R, VEC>), dim3(g), blk, 0, s, f, N2, w.part_f, halt);
             SC_LAUNCH_CHECK();
         }
         // step 9: beta_i = ||f||, v_{i+1} = f / beta_i
-        hipLaunchKernelGGL((k_lz_next<R, R>), dim3(g), blk, 0, s, vnext, f, N2, beta, i, w.st);
+        hipLaunchKernelGGL((k_lz_next<R, R>), dim3(g), blk, 0, s, vnext, f, N2, beta, i, w.st, w.part_f, g);
         SC_LAUNCH_CHECK();
     }
 
@@ -292,8 +324,18 @@ sc_status seed_lanczos(const sc_op* op, const void* b1, void* x1, int m, int fre
         return SC_ERR_WORKSPACE;
     }
     sc_status result = SC_OK;
-    if (single) SC_TRY(seed_run<float>(op, b1, x1, m, freq, (float*)V, ldv, alpha, beta, m_done, w, s, &result));
-    else SC_TRY(seed_run<double>(op, b1, x1, m, freq, (double*)V, ldv, alpha, beta, m_done, w, s, &result));
+    // 16-byte packs need 16-byte aligned columns
+    const int64_t N2 = op->n * (is_complex(op->dtype) ? 2 : 1);
+    const size_t rb = single ? 4 : 8;
+    const bool vec = ((uintptr_t)V % 16 == 0) && ((ldv * (is_complex(vdt) ? 2 : 1) * rb) % 16 == 0) &&
+                     ((N2 * rb) % 16 == 0);
+    if (single) {
+        if (vec) SC_TRY((seed_run<float, true>(op, b1, x1, m, freq, (float*)V, ldv, alpha, beta, m_done, w, s, &result)));
+        else SC_TRY((seed_run<float, false>(op, b1, x1, m, freq, (float*)V, ldv, alpha, beta, m_done, w, s, &result)));
+    } else {
+        if (vec) SC_TRY((seed_run<double, true>(op, b1, x1, m, freq, (double*)V, ldv, alpha, beta, m_done, w, s, &result)));
+        else SC_TRY((seed_run<double, false>(op, b1, x1, m, freq, (double*)V, ldv, alpha, beta, m_done, w, s, &result)));
+    }
     if (result == SC_ERR_NOT_PD) set_error("seed_lanczos: non-positive pivot, A is not positive definite");
     if (result == SC_ERR_NONFINITE) set_error("seed_lanczos: non-finite value in the Lanczos recurrence");
     return result;
