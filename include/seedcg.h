@@ -143,7 +143,8 @@ typedef enum {
     SC_CALL_APPLY = 0,
     SC_CALL_SEED = 1,
     SC_CALL_PROJECT = 2,
-    SC_CALL_CG = 3
+    SC_CALL_CG = 3,
+    SC_CALL_KAPPA_GRAD = 4
 } sc_call;
 
 /* Bytes of `work` needed by a call.  k: right-hand sides per call; m: basis
@@ -226,6 +227,22 @@ sc_status sc_solve_cg(const sc_op* op, int mixed, const void* B_dev, int64_t ldb
  * Errors: SC_ERR_ARG for an unknown class or a NULL pointer. */
 sc_status sc_timer_enable(int on);
 sc_status sc_timer_read(int cls, double* ms, int64_t* launches, double* bytes, double* flops);
+
+/* ------------------------------------------------------------------ gradient
+ * Derivative with respect to kappa of L = sum_j Re<eta_j, x_j>, where
+ * x_j = A^{-1} b_j solves the Wilson normal equations (not part of the paper's
+ * method: it lets the seeded solve sit inside a differentiable program).  Given
+ * the solutions X and the adjoint solutions L (lambda_j = A^{-1} eta_j, which
+ * the caller obtains with sc_project / sc_solve_cg seeded from the forward
+ * basis), writes to *grad (host)
+ *   sum_j Re[(H lambda_j)^H (D x_j) + (D lambda_j)^H (H x_j)],
+ * since dA/dkappa = -(H^H D + D^H H) for D = 1 - kappa H.  X_dev, L_dev: n x k
+ * complex doubles.  Needs sc_workspace_size(op, SC_CALL_KAPPA_GRAD, k, 0, ...)
+ * bytes of work.  Synchronises the stream.  Errors: SC_ERR_ARG for a
+ * non-Wilson op or bad pointers, SC_ERR_WORKSPACE. */
+sc_status sc_wilson_kappa_grad(const sc_op* op, const void* X_dev, int64_t ldx, const void* L_dev,
+                               int64_t ldl, int k, double* grad, void* work_dev, size_t work_bytes,
+                               void* stream);
 
 /* Description of the last failure on the calling thread (valid until the next
  * call on that thread); "" when the last call succeeded. */

@@ -27,7 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libseedcg.so")
 
 SC_R64, SC_C64, SC_C128, SC_R32 = 0, 1, 2, 3
-SC_CALL_APPLY, SC_CALL_SEED, SC_CALL_PROJECT, SC_CALL_CG = 0, 1, 2, 3
+SC_CALL_APPLY, SC_CALL_SEED, SC_CALL_PROJECT, SC_CALL_CG, SC_CALL_KAPPA_GRAD = 0, 1, 2, 3, 4
 STATUS = {0: "SC_OK", 1: "SC_NOT_CONVERGED", 2: "SC_BREAKDOWN", -1: "SC_ERR_ARG", -2: "SC_ERR_HIP",
           -3: "SC_ERR_NOT_PD", -4: "SC_ERR_NONFINITE", -5: "SC_ERR_WORKSPACE", -6: "SC_ERR_UNSUPPORTED"}
 
@@ -53,6 +53,7 @@ _PROTOS = {
     "sc_project": [_I64, _P, _I64, _INT, _INT, _P, _P, _INT, _P, _I64, _INT, _P, _I64, _P, _SZ, _P],
     "sc_solve_cg": [_P, _INT, _P, _I64, _P, _I64, _INT, _DBL, _INT, ctypes.POINTER(_INT), ctypes.POINTER(_DBL),
                     _P, _SZ, _P],
+    "sc_wilson_kappa_grad": [_P, _P, _I64, _P, _I64, _INT, ctypes.POINTER(_DBL), _P, _SZ, _P],
     "sc_wilson_tune_info": [_P, _INT, _INT, ctypes.POINTER(_INT), ctypes.POINTER(ctypes.c_float)],
     "sc_wilson_tune_set": [_P, _INT, _INT, _INT],
     "sc_timer_enable": [_INT],
@@ -244,6 +245,19 @@ class Op:
         _check(lib().sc_op_apply(self._h, sdt, _ptr(X), self.n, _ptr(Y), self.n, X.shape[0], _ptr(w), w.numel(),
                                  _stream()))
         return Y
+
+    def kappa_grad(self, X, Lam):
+        """sum_j Re[(H lam_j)^H D x_j + (D lam_j)^H H x_j] (the dL/dkappa contraction)."""
+        X = self._vec(X, torch.complex128)
+        Lam = self._vec(Lam, torch.complex128)
+        k = X.shape[0]
+        nb = _SZ()
+        _check(lib().sc_workspace_size(self._h, SC_CALL_KAPPA_GRAD, k, 0, SC_C128, ctypes.byref(nb)))
+        w = _work(nb.value, self.device)
+        g = _DBL()
+        _check(lib().sc_wilson_kappa_grad(self._h, _ptr(X), self.n, _ptr(Lam), self.n, k, ctypes.byref(g), _ptr(w),
+                                          w.numel(), _stream()))
+        return g.value
 
     def tune_info(self, k, single=True):
         """(variant, [us per candidate]) chosen by the stencil autotuner for k columns."""

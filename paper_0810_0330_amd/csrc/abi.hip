@@ -20,6 +20,10 @@ size_t cg_workspace(const sc_op* op, int k, bool mixed);
 sc_status solve_cg(const sc_op* op, int mixed, const void* B, int64_t ldb, void* X, int64_t ldx, int k, double tol,
                    int maxit, int* iters, double* relres, void* work, size_t work_bytes, hipStream_t s);
 
+size_t kappa_grad_workspace(const sc_op* op, int k);
+sc_status kappa_grad(const sc_op* op, const void* X, int64_t ldx, const void* L, int64_t ldl, int k, double* out,
+                     void* work, size_t work_bytes, hipStream_t s);
+
 static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 // the op's precision or its single counterpart
@@ -183,6 +187,10 @@ sc_status sc_workspace_size(const sc_op* op, int call, int k, int m, sc_dtype dt
             SC_ARG(op && dtype_ok_for(op, dtype), "op NULL or dtype not valid for the op");
             *bytes = cg_workspace(op, std::max(k, 1), is_single(dtype));
             return SC_OK;
+        case SC_CALL_KAPPA_GRAD:
+            SC_ARG(op && op->kind == SC_OPK_WILSON, "kappa gradient needs a Wilson op");
+            *bytes = kappa_grad_workspace(op, std::max(k, 1));
+            return SC_OK;
         default:
             SC_ARG(false, "unknown call id");
     }
@@ -293,6 +301,23 @@ sc_status sc_solve_cg(const sc_op* op, int mixed, const void* B_dev, int64_t ldb
     }
     return solve_cg(op, mixed, B_dev, ldb, X_dev, ldx, k, tol, maxit, iters, relres, work_dev, work_bytes,
                     (hipStream_t)stream);
+    SC_GUARD_END
+}
+
+sc_status sc_wilson_kappa_grad(const sc_op* op, const void* X_dev, int64_t ldx, const void* L_dev, int64_t ldl,
+                                int k, double* grad, void* work_dev, size_t work_bytes, void* stream) {
+    SC_GUARD_BEGIN
+    SC_ARG(op && op->kind == SC_OPK_WILSON, "not a Wilson op");
+    SC_ARG(grad, "grad is NULL");
+    SC_ARG(k >= 1, "k must be >= 1");
+    SC_ARG(X_dev && L_dev && work_dev, "NULL device pointer");
+    SC_ARG(aligned(X_dev, 16) && aligned(L_dev, 16), "misaligned device pointer");
+    SC_ARG(ldx >= op->n && ldl >= op->n, "leading dimension smaller than n");
+    if (work_bytes < kappa_grad_workspace(op, k) - 256) {
+        set_error("kappa_grad: work buffer too small");
+        return SC_ERR_WORKSPACE;
+    }
+    return kappa_grad(op, X_dev, ldx, L_dev, ldl, k, grad, work_dev, work_bytes, (hipStream_t)stream);
     SC_GUARD_END
 }
 
