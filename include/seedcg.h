@@ -228,6 +228,42 @@ sc_status sc_solve_cg(const sc_op* op, int mixed, const void* B_dev, int64_t ldb
 sc_status sc_timer_enable(int on);
 sc_status sc_timer_read(int cls, double* ms, int64_t* launches, double* bytes, double* flops);
 
+/* ------------------------------------------------------------------ batches
+ * Several independent systems, each single-seeded, advanced together: the
+ * seed phases of all systems (static control flow) are captured in one HIP
+ * graph on forked streams and launched once, so every lattice's Lanczos steps
+ * run concurrently; the graph is cached and replayed when the same argument
+ * set is solved again.  Then each system is projected and finished with CG on
+ * its own stream, concurrently.  Per system: X = 0 initially, RHS 1 seeds
+ * (m steps, reorthogonalization every reorth_freq), columns 2..k are projected
+ * over its basis, all k columns finish with CG to tol (mixed = 1: complex64
+ * basis, FP32 bulk, FP64 reliable updates and scalars).  The library fills
+ * m_done and status (an sc_status) of each system; iters and relres are host
+ * arrays of k entries.  All device buffers, including `work`
+ * (sc_batch_workspace_size bytes), are the caller's.  The call synchronises
+ * `stream` and returns SC_OK, SC_NOT_CONVERGED or SC_BREAKDOWN if every system
+ * did, else the first error. */
+typedef struct {
+    const sc_op* op;
+    const void* B_dev;   /* n x k, op dtype */
+    int64_t ldb;
+    void* X_dev;         /* n x k, op dtype (output) */
+    int64_t ldx;
+    int k;
+    int m;
+    int reorth_freq;
+    double tol;
+    int maxit;
+    int mixed;
+    int* iters;          /* host, k */
+    double* relres;      /* host, k */
+    int m_done;          /* out */
+    int status;          /* out */
+} sc_batch_system;
+
+sc_status sc_batch_workspace_size(int nsys, const sc_batch_system* systems, size_t* bytes);
+sc_status sc_batch_solve(int nsys, sc_batch_system* systems, void* work_dev, size_t work_bytes, void* stream);
+
 /* ------------------------------------------------------------------ gradient
  * Derivative with respect to kappa of L = sum_j Re<eta_j, x_j>, where
  * x_j = A^{-1} b_j solves the Wilson normal equations (not part of the paper's

@@ -58,10 +58,18 @@ _PROTOS = {
     "sc_wilson_tune_set": [_P, _INT, _INT, _INT],
     "sc_timer_enable": [_INT],
     "sc_timer_read": [_INT, ctypes.POINTER(_DBL), ctypes.POINTER(_I64), ctypes.POINTER(_DBL), ctypes.POINTER(_DBL)],
+    "sc_batch_workspace_size": [_INT, _P, ctypes.POINTER(_SZ)],
+    "sc_batch_solve": [_INT, _P, _P, _SZ, _P],
     "sc_last_error": [],
 }
 
 _lib = None
+
+
+class BatchSystem(ctypes.Structure):
+    _fields_ = [("op", _P), ("B_dev", _P), ("ldb", _I64), ("X_dev", _P), ("ldx", _I64), ("k", _INT), ("m", _INT),
+                ("reorth_freq", _INT), ("tol", _DBL), ("maxit", _INT), ("mixed", _INT),
+                ("iters", ctypes.POINTER(_INT)), ("relres", ctypes.POINTER(_DBL)), ("m_done", _INT), ("status", _INT)]
 
 
 class SeedCGError(RuntimeError):
@@ -360,3 +368,38 @@ def seeded_solve(op, B, m, freq, tol, mixed=False, maxit=100000):
     X, its, rel = solve_cg(op, B, tol, X0=Xs, mixed=mixed, maxit=maxit)
     iters = [its[0] + basis.m_done] + its[1:]
     return {"X": X, "X_seeded": Xs, "iters": iters, "cg_iters": its, "relres": rel, "basis": basis}
+
+
+def batch_solve(systems, maxit=100000):
+    """Solve several independent systems, each single-seeded, in one batched call.
+
+    systems: list of dicts with keys op, B ((k, n) in the op dtype), m, freq, tol and optional mixed.
+    The seed phases of all systems run as one HIP graph; projection and CG of each
+    system then run on its own stream.  Returns a list of dicts (X, iters, relres,
+    m_done, status) in the input order.
+    """
+    n = len(systems)
+    arr = (BatchSystem * n)()
+    keep = []
+    for i, sd in enumerate(systems):
+        op = sd["op"]
+        B = op._vec(sd["B"], op.dtype)
+        k = B.shape[0]
+        X = torch.empty_like(B)
+        its = (ctypes.c_int * k)()
+        rel = (ctypes.c_double * k)()
+        keep.append((B, X, its, rel))
+        arr[i] = BatchSystem(op.handle, _ptr(B), op.n, _ptr(X), op.n, k, int(sd["m"]), int(sd["freq"]),
+                             float(sd["tol"]), int(sd.get("maxit", maxit)), 1 if sd.get("mixed", False) else 0,
+                             ctypes.cast(its, ctypes.POINTER(_INT)), ctypes.cast(rel, ctypes.POINTER(_DBL)), 0, 0)
+    nb = _SZ()
+    _check(lib().sc_batch_workspace_size(n, ctypes.cast(arr, _P), ctypes.byref(nb)))
+    w = _work(nb.value, systems[0]["op"].device)
+    _check(lib().sc_batch_solve(n, ctypes.cast(arr, _P), _ptr(w), w.numel(), _stream()), ok=(0, 1, 2))
+    out = []
+    for i, (B, X, its, rel) in enumerate(keep):
+        cg_its = list(its)
+        md = arr[i].m_done
+        out.append({"X": X, "iters": [cg_its[0] + md] + cg_its[1:], "cg_iters": cg_its, "relres": list(rel),
+                    "m_done": md, "status": arr[i].status})
+    return out

@@ -13,16 +13,14 @@ thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 void clear_error() { g_last_error.clear(); }
 
-size_t seed_workspace(const sc_op* op, int m, bool single);
 sc_status seed_lanczos(const sc_op* op, const void* b1, void* x1, int m, int freq, void* V, int64_t ldv, sc_dtype vdt,
                        double* alpha, double* beta, int* m_done, void* work, size_t work_bytes, hipStream_t s);
-size_t cg_workspace(const sc_op* op, int k, bool mixed);
-sc_status solve_cg(const sc_op* op, int mixed, const void* B, int64_t ldb, void* X, int64_t ldx, int k, double tol,
-                   int maxit, int* iters, double* relres, void* work, size_t work_bytes, hipStream_t s);
 
 size_t kappa_grad_workspace(const sc_op* op, int k);
 sc_status kappa_grad(const sc_op* op, const void* X, int64_t ldx, const void* L, int64_t ldl, int k, double* out,
                      void* work, size_t work_bytes, hipStream_t s);
+size_t batch_workspace(int nsys, const sc_batch_system* sys);
+sc_status batch_solve(int nsys, sc_batch_system* sys, void* work, size_t work_bytes, hipStream_t s);
 
 static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
@@ -33,7 +31,7 @@ static size_t apply_workspace(const sc_op* op, int k, sc_dtype d) {
     return (size_t)std::max<int64_t>(op_apply_tmp_elems(op), 0) * dtype_bytes(d) * (size_t)std::max(k, 1) + 256;
 }
 
-static size_t project_workspace(int64_t n, int m, bool cpl) {
+size_t project_workspace(int64_t n, int m, bool cpl) {
     Carver c(nullptr, 0);
     c.take<double>((size_t)m * kMaxCols * 2);
     c.take<double>(gemm_cn_part_doubles(n, m, kMaxCols, cpl));
@@ -41,7 +39,7 @@ static size_t project_workspace(int64_t n, int m, bool cpl) {
     return c.off + 256;
 }
 
-static sc_status project_impl(int64_t n, const void* V, int64_t ldv, sc_dtype vdt, int m, const double* alpha,
+sc_status project_impl(int64_t n, const void* V, int64_t ldv, sc_dtype vdt, int m, const double* alpha,
                               const double* beta, sc_dtype xdt, const void* R0, int64_t ldr, int k, void* X,
                               int64_t ldx, void* work, size_t work_bytes, hipStream_t s) {
     const bool cpl = is_complex(vdt);
@@ -318,6 +316,43 @@ sc_status sc_wilson_kappa_grad(const sc_op* op, const void* X_dev, int64_t ldx, 
         return SC_ERR_WORKSPACE;
     }
     return kappa_grad(op, X_dev, ldx, L_dev, ldl, k, grad, work_dev, work_bytes, (hipStream_t)stream);
+    SC_GUARD_END
+}
+
+static sc_status check_batch(int nsys, const sc_batch_system* sys) {
+    SC_ARG(nsys >= 1 && nsys <= 64 && sys, "nsys must be 1..64 and systems non-NULL");
+    for (int i = 0; i < nsys; ++i) {
+        const sc_batch_system& b = sys[i];
+        SC_ARG(b.op, "system op is NULL");
+        SC_ARG(b.k >= 1 && b.m >= 1 && b.reorth_freq >= 0 && b.maxit >= 0, "system k, m >= 1, freq, maxit >= 0");
+        SC_ARG(std::isfinite(b.tol) && b.tol > 0.0, "system tol must be finite and > 0");
+        SC_ARG(b.B_dev && b.X_dev && b.iters && b.relres, "system pointer is NULL");
+        SC_ARG(aligned(b.B_dev, dtype_bytes(b.op->dtype)) && aligned(b.X_dev, dtype_bytes(b.op->dtype)),
+               "system B or X misaligned");
+        SC_ARG(b.ldb >= b.op->n && b.ldx >= b.op->n, "system leading dimension smaller than n");
+        SC_ARG(!(b.mixed && b.op->kind == SC_OPK_WILSON && !b.op->U32), "mixed precision needs U32 links");
+    }
+    return SC_OK;
+}
+
+sc_status sc_batch_workspace_size(int nsys, const sc_batch_system* systems, size_t* bytes) {
+    SC_GUARD_BEGIN
+    SC_ARG(bytes, "bytes is NULL");
+    SC_TRY(check_batch(nsys, systems));
+    *bytes = batch_workspace(nsys, systems);
+    return SC_OK;
+    SC_GUARD_END
+}
+
+sc_status sc_batch_solve(int nsys, sc_batch_system* systems, void* work_dev, size_t work_bytes, void* stream) {
+    SC_GUARD_BEGIN
+    SC_TRY(check_batch(nsys, systems));
+    SC_ARG(work_dev, "work is NULL");
+    if (work_bytes < batch_workspace(nsys, systems) - 256) {
+        set_error("batch_solve: work buffer too small");
+        return SC_ERR_WORKSPACE;
+    }
+    return batch_solve(nsys, systems, work_dev, work_bytes, (hipStream_t)stream);
     SC_GUARD_END
 }
 

@@ -1,0 +1,267 @@
+// Uneven batches of independent systems, each single-seeded.
+//
+// The seed phase of every system has static control flow (exactly m steps,
+// reorthogonalization at known steps), so all of them are captured into one
+// HIP graph: the caller's stream forks into one stream per system, each
+// system's Lanczos kernels are enqueued on its own branch, and the branches
+// join back.  One graph launch then advances every lattice concurrently: the
+// small lattices, which cannot fill the GPU alone, overlap with the large
+// ones.  The instantiated graph is cached and replayed when the same argument
+// set is solved again (a graph bakes in its pointers and sizes).
+//
+// The rest is data dependent: each system's final seed state is read, x^1
+// formed, the other right-hand sides projected, and every column finished
+// with CG, one host thread and one stream per system.
+#include <cstring>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "sc_internal.h"
+
+namespace sc {
+
+namespace {
+
+struct SysPlan {
+    size_t v_off, a_off, b_off, seed_off, seed_bytes, proj_off, proj_bytes, cg_off, cg_bytes;
+    sc_dtype vdt;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+std::vector<SysPlan> plan_batch(int nsys, const sc_batch_system* sys, size_t* total) {
+    std::vector<SysPlan> p(nsys);
+    size_t off = 0;
+    for (int i = 0; i < nsys; ++i) {
+        const sc_op* op = sys[i].op;
+        const bool single = sys[i].mixed != 0;
+        const bool cpl = is_complex(op->dtype);
+        SysPlan& q = p[i];
+        q.vdt = single ? single_of(op->dtype) : op->dtype;
+        q.v_off = off;
+        off = align256(off + (size_t)(sys[i].m + 1) * op->n * dtype_bytes(q.vdt));
+        q.a_off = off;
+        off = align256(off + (size_t)sys[i].m * 8);
+        q.b_off = off;
+        off = align256(off + (size_t)(sys[i].m + 1) * 8);
+        q.seed_off = off;
+        q.seed_bytes = seed_workspace(op, sys[i].m, single);
+        off = align256(off + q.seed_bytes);
+        q.proj_off = off;
+        q.proj_bytes = project_workspace(op->n, sys[i].m, cpl);
+        off = align256(off + q.proj_bytes);
+        q.cg_off = off;
+        q.cg_bytes = cg_workspace(op, sys[i].k, single);
+        off = align256(off + q.cg_bytes);
+    }
+    *total = off + 256;
+    return p;
+}
+
+// A cached instantiated graph for one argument set.
+struct GraphKey {
+    std::vector<char> bytes;
+    bool operator==(const GraphKey& o) const { return bytes == o.bytes; }
+};
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec = nullptr;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;  // most recent last
+constexpr size_t kGraphCache = 4;
+
+GraphKey make_key(int nsys, const sc_batch_system* sys, const void* work, hipStream_t s) {
+    GraphKey k;
+    auto put = [&](const void* p, size_t n) {
+        const char* c = (const char*)p;
+        k.bytes.insert(k.bytes.end(), c, c + n);
+    };
+    put(&nsys, sizeof nsys);
+    put(&work, sizeof work);
+    put(&s, sizeof s);
+    for (int i = 0; i < nsys; ++i) {
+        put(&sys[i].op, sizeof sys[i].op);
+        put(&sys[i].B_dev, sizeof sys[i].B_dev);
+        put(&sys[i].ldb, sizeof sys[i].ldb);
+        put(&sys[i].X_dev, sizeof sys[i].X_dev);
+        put(&sys[i].ldx, sizeof sys[i].ldx);
+        put(&sys[i].k, sizeof sys[i].k);
+        put(&sys[i].m, sizeof sys[i].m);
+        put(&sys[i].reorth_freq, sizeof sys[i].reorth_freq);
+        put(&sys[i].mixed, sizeof sys[i].mixed);
+    }
+    return k;
+}
+
+}  // namespace
+
+size_t batch_workspace(int nsys, const sc_batch_system* sys) {
+    size_t total = 0;
+    plan_batch(nsys, sys, &total);
+    return total;
+}
+
+sc_status batch_solve(int nsys, sc_batch_system* sys, void* work, size_t work_bytes, hipStream_t s) {
+    size_t total = 0;
+    std::vector<SysPlan> plan = plan_batch(nsys, sys, &total);
+    char* base = (char*)(((uintptr_t)work + 255) & ~uintptr_t(255));
+    if ((size_t)(base - (char*)work) + total - 256 > work_bytes) {
+        set_error("batch_solve: work buffer too small");
+        return SC_ERR_WORKSPACE;
+    }
+    std::vector<SeedWork> sw(nsys);
+    for (int i = 0; i < nsys; ++i) {
+        bool ok = false;
+        sw[i] = seed_carve(base + plan[i].seed_off, plan[i].seed_bytes, sys[i].op, sys[i].m, sys[i].mixed != 0, &ok);
+        if (!ok) {
+            set_error("batch_solve: seed workspace carving failed");
+            return SC_ERR_WORKSPACE;
+        }
+    }
+    // one stream per system, forked from and joined back to a private capture
+    // stream (the caller's stream may be the null stream, which cannot capture)
+    std::vector<hipStream_t> ss(nsys + 1, nullptr);
+    std::vector<hipEvent_t> ev(nsys + 1, nullptr);
+    auto cleanup = [&]() {
+        for (auto& x : ss)
+            if (x) hipStreamDestroy(x);
+        for (auto& e : ev)
+            if (e) hipEventDestroy(e);
+    };
+    for (int i = 0; i <= nsys; ++i)
+        if (hipStreamCreateWithFlags(&ss[i], hipStreamNonBlocking) != hipSuccess) {
+            cleanup();
+            set_error("batch_solve: stream creation failed");
+            return SC_ERR_HIP;
+        }
+    for (auto& e : ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            cleanup();
+            set_error("batch_solve: event creation failed");
+            return SC_ERR_HIP;
+        }
+
+    sc_status st = SC_OK;
+    // tune each lattice's seed-phase stencil shape before any capture
+    for (int i = 0; i < nsys && st == SC_OK; ++i) st = seed_pretune(sys[i].op, sys[i].mixed != 0, sw[i], s);
+    if (st != SC_OK) {
+        cleanup();
+        return st;
+    }
+
+    // ---- seed phases: one graph over all systems
+    GraphKey key = make_key(nsys, sys, work, s);
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (size_t j = 0; j < g_graphs.size(); ++j)
+            if (g_graphs[j].key == key) {
+                exec = g_graphs[j].exec;
+                GraphEntry e = g_graphs[j];
+                g_graphs.erase(g_graphs.begin() + j);
+                g_graphs.push_back(e);
+                break;
+            }
+    }
+    if (!exec) {
+        hipGraph_t graph = nullptr;
+        hipStream_t cap = ss[nsys];
+        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            cleanup();
+            set_error("batch_solve: stream capture could not start");
+            return SC_ERR_HIP;
+        }
+        hipEventRecord(ev[nsys], cap);
+        for (int i = 0; i < nsys && st == SC_OK; ++i) {
+            const sc_batch_system& b = sys[i];
+            hipStreamWaitEvent(ss[i], ev[nsys], 0);
+            const int64_t N2 = b.op->n * (is_complex(b.op->dtype) ? 2 : 1);
+            // X = 0: the seed refines column 0 in place (x0 = 0)
+            st = fill<double>((double*)b.X_dev, (b.k - 1) * b.ldx * (is_complex(b.op->dtype) ? 2 : 1) + N2, 0.0,
+                              ss[i]);
+            if (st == SC_OK)
+                st = seed_enqueue_any(b.op, b.B_dev, b.X_dev, b.m, b.reorth_freq, base + plan[i].v_off, b.op->n,
+                                      plan[i].vdt, (double*)(base + plan[i].a_off), (double*)(base + plan[i].b_off),
+                                      sw[i], ss[i]);
+            hipEventRecord(ev[i], ss[i]);
+            hipStreamWaitEvent(cap, ev[i], 0);
+        }
+        const hipError_t ce = hipStreamEndCapture(cap, &graph);
+        if (st != SC_OK || ce != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            cleanup();
+            if (st == SC_OK) {
+                set_error(std::string("batch_solve: capture failed: ") + hipGetErrorString(ce));
+                st = SC_ERR_HIP;
+            }
+            return st;
+        }
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            cleanup();
+            set_error(std::string("batch_solve: graph instantiation failed: ") + hipGetErrorString(ie));
+            return SC_ERR_HIP;
+        }
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        if (g_graphs.size() >= kGraphCache) {
+            hipGraphExecDestroy(g_graphs.front().exec);
+            g_graphs.erase(g_graphs.begin());
+        }
+        g_graphs.push_back({key, exec});
+    }
+    if (hipGraphLaunch(exec, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        cleanup();
+        set_error("batch_solve: graph launch failed");
+        return SC_ERR_HIP;
+    }
+
+    // ---- per system: x^1, projection, CG (one thread and one stream each)
+    std::vector<sc_status> res(nsys, SC_OK);
+    std::vector<std::string> err(nsys);
+    auto finish = [&](int i) {
+        sc_batch_system& b = sys[i];
+        const SysPlan& q = plan[i];
+        hipStream_t st_i = ss[i];
+        sc_status seed_status = SC_OK;
+        sc_status r = seed_finalize_any(b.op, b.X_dev, base + q.v_off, b.op->n, q.vdt, (double*)(base + q.a_off),
+                                        (double*)(base + q.b_off), &b.m_done, sw[i], st_i, &seed_status);
+        if (r == SC_OK && (seed_status == SC_ERR_NOT_PD || seed_status == SC_ERR_NONFINITE)) r = seed_status;
+        const size_t eb = dtype_bytes(b.op->dtype);
+        if (r == SC_OK && b.k > 1 && b.m_done >= 1)
+            r = project_impl(b.op->n, base + q.v_off, b.op->n, q.vdt, b.m_done, (double*)(base + q.a_off),
+                             (double*)(base + q.b_off), b.op->dtype, (const char*)b.B_dev + b.ldb * eb, b.ldb, b.k - 1,
+                             (char*)b.X_dev + b.ldx * eb, b.ldx, base + q.proj_off, q.proj_bytes, st_i);
+        if (r == SC_OK)
+            r = solve_cg(b.op, b.mixed, b.B_dev, b.ldb, b.X_dev, b.ldx, b.k, b.tol, b.maxit, b.iters, b.relres,
+                         base + q.cg_off, q.cg_bytes, st_i);
+        if (r == SC_OK && seed_status == SC_BREAKDOWN) r = SC_BREAKDOWN;
+        b.status = r;
+        res[i] = r;
+        if (r < 0) err[i] = sc_last_error();
+    };
+    std::vector<std::thread> th;
+    for (int i = 1; i < nsys; ++i) th.emplace_back(finish, i);
+    finish(0);
+    for (auto& t : th) t.join();
+    for (int i = 0; i < nsys; ++i) {
+        hipEventRecord(ev[i], ss[i]);
+        hipStreamWaitEvent(s, ev[i], 0);
+    }
+    hipStreamSynchronize(s);
+    cleanup();
+    sc_status out = SC_OK;
+    for (int i = 0; i < nsys; ++i) {
+        if (res[i] < 0) {
+            set_error("batch_solve: system " + std::to_string(i) + ": " + err[i]);
+            return res[i];
+        }
+        if (res[i] == SC_NOT_CONVERGED) out = SC_NOT_CONVERGED;
+        else if (res[i] == SC_BREAKDOWN && out == SC_OK) out = SC_BREAKDOWN;
+    }
+    return out;
+}
+
+}  // namespace sc

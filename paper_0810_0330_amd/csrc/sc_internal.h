@@ -75,4 +75,43 @@ sc_status gemm_nn(bool cplx, bool vsingle, const void* V, int64_t ldv, int64_t n
 sc_status tridiag_solve(const double* alpha, const double* beta, int M, double* Y, int N, bool cplx,
                         const double* e1_beta0, double* work, const int* halt, hipStream_t s);
 
+// ---------------------------------------------------------------- seed phase (seed.hip)
+struct SeedState;
+struct SeedWork {
+    void* av;        // A v_i          (vector precision)
+    void* f;         // f              (vector precision)
+    void* tmp;       // op scratch     (vector precision)
+    double* r64;     // r0^1           (FP64)
+    double* ax64;    // A x0           (FP64)
+    void* tmp64;     // op scratch     (FP64)
+    double* part_a;  // partials of alpha_i
+    double* part_f;  // partials of ||f||^2
+    double* part_v;  // partials of ||v_i||^2 (reorthogonalization)
+    double* delta;   // LU pivots delta_1..delta_m (index i)
+    SeedState* st;
+    double* G;       // reorthogonalization coefficients, (m) x 2 complex
+    double* G2;      // one complex coefficient
+    double* gpart;   // gemm_cn partials
+    double* y;       // T^{-1} beta_0 e_1 (m complex)
+    double* trid;    // LU work (2m)
+};
+size_t seed_workspace(const sc_op* op, int m, bool single);
+SeedWork seed_carve(void* work, size_t work_bytes, const sc_op* op, int m, bool single, bool* ok);
+sc_status seed_pretune(const sc_op* op, bool single, const SeedWork& w, hipStream_t s);
+// steps 1-9 enqueued with no host synchronisation (capturable)
+sc_status seed_enqueue_any(const sc_op* op, const void* b1, void* x1, int m, int freq, void* V, int64_t ldv,
+                           sc_dtype vdt, double* alpha, double* beta, const SeedWork& w, hipStream_t s);
+// one synchronisation: final state, then x^1
+sc_status seed_finalize_any(const sc_op* op, void* x1, void* V, int64_t ldv, sc_dtype vdt, double* alpha,
+                            double* beta, int* m_done, const SeedWork& w, hipStream_t s, sc_status* result);
+
+// ---------------------------------------------------------------- projection and CG
+size_t project_workspace(int64_t n, int m, bool cpl);
+sc_status project_impl(int64_t n, const void* V, int64_t ldv, sc_dtype vdt, int m, const double* alpha,
+                       const double* beta, sc_dtype xdt, const void* R0, int64_t ldr, int k, void* X, int64_t ldx,
+                       void* work, size_t work_bytes, hipStream_t s);
+size_t cg_workspace(const sc_op* op, int k, bool mixed);
+sc_status solve_cg(const sc_op* op, int mixed, const void* B, int64_t ldb, void* X, int64_t ldx, int k, double tol,
+                   int maxit, int* iters, double* relres, void* work, size_t work_bytes, hipStream_t s);
+
 }  // namespace sc

@@ -183,25 +183,6 @@ __global__ __launch_bounds__(kBlock) void k_scale_norm(R* __restrict__ v, int64_
 }
 
 // ----------------------------------------------------------------------------
-struct SeedWork {
-    void* av;        // A v_i          (vector precision)
-    void* f;         // f              (vector precision)
-    void* tmp;       // op scratch     (vector precision)
-    double* r64;     // r0^1           (FP64)
-    double* ax64;    // A x0           (FP64)
-    void* tmp64;     // op scratch     (FP64)
-    double* part_a;  // partials of alpha_i
-    double* part_f;  // partials of ||f||^2
-    double* part_v;  // partials of ||v_i||^2 (reorthogonalization)
-    double* delta;   // LU pivots delta_1..delta_m (index i)
-    SeedState* st;
-    double* G;       // reorthogonalization coefficients, (m) x 2 complex
-    double* G2;      // one complex coefficient
-    double* gpart;   // gemm_cn partials
-    double* y;       // T^{-1} beta_0 e_1 (m complex)
-    double* trid;    // LU work (2m)
-};
-
 static SeedWork carve_seed(Carver& c, const sc_op* op, int m, bool single) {
     const bool cpl = is_complex(op->dtype);
     const int64_t N2 = op->n * (cpl ? 2 : 1);
@@ -233,10 +214,11 @@ size_t seed_workspace(const sc_op* op, int m, bool single) {
     return c.off + 256;
 }
 
+// Steps 1-9 for m steps, enqueued on `s` with no host synchronisation (the
+// phase has static control flow, so it can be captured in a graph).
 template <typename R, bool VEC>
-static sc_status seed_run(const sc_op* op, const void* b1, void* x1, int m, int freq, R* V, int64_t ldv,
-                          double* alpha, double* beta, int* m_done, const SeedWork& w, hipStream_t s,
-                          sc_status* result) {
+static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, int freq, R* V, int64_t ldv,
+                              double* alpha, double* beta, const SeedWork& w, hipStream_t s) {
     const bool single = sizeof(R) == 4;
     const bool cpl = is_complex(op->dtype);
     const int64_t N2 = op->n * (cpl ? 2 : 1);
@@ -297,7 +279,15 @@ static sc_status seed_run(const sc_op* op, const void* b1, void* x1, int m, int 
         hipLaunchKernelGGL((k_lz_next<R, R>), dim3(g), blk, 0, s, vnext, f, N2, beta, i, w.st, w.part_f, g);
         SC_LAUNCH_CHECK();
     }
+    return SC_OK;
+}
 
+// Reads the phase's final state (one synchronisation) and forms x^1.
+template <typename R>
+static sc_status seed_finalize(const sc_op* op, void* x1, R* V, int64_t ldv, double* alpha, double* beta,
+                               int* m_done, const SeedWork& w, hipStream_t s, sc_status* result) {
+    const bool single = sizeof(R) == 4;
+    const bool cpl = is_complex(op->dtype);
     SeedState hst;
     SC_HIP(hipMemcpyAsync(&hst, w.st, sizeof(SeedState), hipMemcpyDeviceToHost, s));
     SC_HIP(hipStreamSynchronize(s));
@@ -313,6 +303,41 @@ static sc_status seed_run(const sc_op* op, const void* b1, void* x1, int m, int 
     return SC_OK;
 }
 
+sc_status seed_enqueue_any(const sc_op* op, const void* b1, void* x1, int m, int freq, void* V, int64_t ldv,
+                           sc_dtype vdt, double* alpha, double* beta, const SeedWork& w, hipStream_t s) {
+    const bool single = is_single(vdt);
+    // 16-byte packs need 16-byte aligned columns
+    const int64_t N2 = op->n * (is_complex(op->dtype) ? 2 : 1);
+    const size_t rb = single ? 4 : 8;
+    const bool vec = ((uintptr_t)V % 16 == 0) && ((ldv * (is_complex(vdt) ? 2 : 1) * rb) % 16 == 0) &&
+                     ((N2 * rb) % 16 == 0);
+    if (single) {
+        if (vec) return seed_enqueue<float, true>(op, b1, x1, m, freq, (float*)V, ldv, alpha, beta, w, s);
+        return seed_enqueue<float, false>(op, b1, x1, m, freq, (float*)V, ldv, alpha, beta, w, s);
+    }
+    if (vec) return seed_enqueue<double, true>(op, b1, x1, m, freq, (double*)V, ldv, alpha, beta, w, s);
+    return seed_enqueue<double, false>(op, b1, x1, m, freq, (double*)V, ldv, alpha, beta, w, s);
+}
+
+sc_status seed_finalize_any(const sc_op* op, void* x1, void* V, int64_t ldv, sc_dtype vdt, double* alpha,
+                            double* beta, int* m_done, const SeedWork& w, hipStream_t s, sc_status* result) {
+    if (is_single(vdt)) return seed_finalize<float>(op, x1, (float*)V, ldv, alpha, beta, m_done, w, s, result);
+    return seed_finalize<double>(op, x1, (double*)V, ldv, alpha, beta, m_done, w, s, result);
+}
+
+SeedWork seed_carve(void* work, size_t work_bytes, const sc_op* op, int m, bool single, bool* ok) {
+    Carver c(work, work_bytes);
+    SeedWork w = carve_seed(c, op, m, single);
+    *ok = c.ok();
+    return w;
+}
+
+// Warm the stencil autotuner for the seed phase's shape (one column at the
+// basis precision) outside any graph capture.
+sc_status seed_pretune(const sc_op* op, bool single, const SeedWork& w, hipStream_t s) {
+    return op_apply(op, single, w.f, op->n, w.av, op->n, 1, w.tmp, s);
+}
+
 sc_status seed_lanczos(const sc_op* op, const void* b1, void* x1, int m, int freq, void* V, int64_t ldv,
                        sc_dtype vdt, double* alpha, double* beta, int* m_done, void* work, size_t work_bytes,
                        hipStream_t s) {
@@ -324,18 +349,9 @@ sc_status seed_lanczos(const sc_op* op, const void* b1, void* x1, int m, int fre
         return SC_ERR_WORKSPACE;
     }
     sc_status result = SC_OK;
-    // 16-byte packs need 16-byte aligned columns
-    const int64_t N2 = op->n * (is_complex(op->dtype) ? 2 : 1);
-    const size_t rb = single ? 4 : 8;
-    const bool vec = ((uintptr_t)V % 16 == 0) && ((ldv * (is_complex(vdt) ? 2 : 1) * rb) % 16 == 0) &&
-                     ((N2 * rb) % 16 == 0);
-    if (single) {
-        if (vec) SC_TRY((seed_run<float, true>(op, b1, x1, m, freq, (float*)V, ldv, alpha, beta, m_done, w, s, &result)));
-        else SC_TRY((seed_run<float, false>(op, b1, x1, m, freq, (float*)V, ldv, alpha, beta, m_done, w, s, &result)));
-    } else {
-        if (vec) SC_TRY((seed_run<double, true>(op, b1, x1, m, freq, (double*)V, ldv, alpha, beta, m_done, w, s, &result)));
-        else SC_TRY((seed_run<double, false>(op, b1, x1, m, freq, (double*)V, ldv, alpha, beta, m_done, w, s, &result)));
-    }
+    SC_TRY(seed_enqueue_any(op, b1, x1, m, freq, V, ldv, vdt, alpha, beta, w, s));
+    if (single) SC_TRY(seed_finalize<float>(op, x1, (float*)V, ldv, alpha, beta, m_done, w, s, &result));
+    else SC_TRY(seed_finalize<double>(op, x1, (double*)V, ldv, alpha, beta, m_done, w, s, &result));
     if (result == SC_ERR_NOT_PD) set_error("seed_lanczos: non-positive pivot, A is not positive definite");
     if (result == SC_ERR_NONFINITE) set_error("seed_lanczos: non-finite value in the Lanczos recurrence");
     return result;

@@ -36,6 +36,8 @@ bool timer_on() { return g_on; }
 TimerScope::TimerScope(int cls, hipStream_t s, double bytes, double flops)
     : cls_(cls), s_(s), bytes_(bytes), flops_(flops), a_(nullptr) {
     if (!g_on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;  // not in graphs
     std::lock_guard<std::mutex> lk(g_mu);
     a_ = take_event();
     if (a_) hipEventRecord((hipEvent_t)a_, s_);

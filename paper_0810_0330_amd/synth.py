@@ -152,3 +152,34 @@ def make_inputs(w: Workload):
     if w.nrhs > npt:
         B = np.concatenate([B, z4_noise(w.n, w.nrhs - npt, rng(w.config_id, 1))], axis=1)
     return {"B": B, "U": U, "kappa": w.kappa}
+
+
+UNEVEN_LATTICES = [(8, 8, 8, 8), (8, 8, 8, 16), (12, 12, 12, 12), (12, 12, 12, 24), (16, 16, 16, 16), (16, 16, 16, 32)]
+
+
+def uneven_batch(lattices=UNEVEN_LATTICES, config_id=4, nrhs_range=(4, 24), kappa_range=(0.10, 0.13)):
+    """Independent Wilson systems of different sizes, each with its own links and kappa.
+
+    Per system s (stream 3 of the config, then a per-system links stream):
+    nrhs_s uniform on nrhs_range, kappa_s uniform on kappa_range; right-hand sides are
+    the first min(nrhs_s, 12) point sources, then Z4 noise.  Returns a list of dicts
+    with dims, kappa, U (natural layout), B (n x nrhs natural layout).
+    """
+    g = rng(config_id, 3)
+    out = []
+    for i, dims in enumerate(lattices):
+        k = int(g.integers(nrhs_range[0], nrhs_range[1] + 1))
+        kap = float(g.uniform(kappa_range[0], kappa_range[1]))
+        U = su3_links(dims, rng(config_id, 10 + i))
+        n = volume(dims) * 12
+        npt = min(k, 12)
+        B = point_sources(dims, ALL_SPIN_COLOUR[:npt])
+        if k > npt:
+            B = np.concatenate([B, z4_noise(n, k - npt, rng(config_id, 20 + i))], axis=1)
+        out.append({"dims": dims, "kappa": kap, "U": U, "B": B, "nrhs": k})
+    return out
+
+
+def seed_steps(k1, cap=1000):
+    """m from a plain-CG count: 2 k1 rounded up to a multiple of 50, capped."""
+    return int(min(cap, max(50, -(-2 * k1 // 50) * 50)))
