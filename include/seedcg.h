@@ -128,14 +128,16 @@ sc_status sc_wilson_dslash(const sc_op* op, sc_dtype dtype, int which, const voi
  * keeps the fastest; SEEDCG_TUNE=0 in the environment selects fixed defaults,
  * and no tuning happens while the stream is being captured.  variant (host):
  * 0 = unrolled hops, 1 column per thread; 1, 2, 3 = rolled hop loop with 1, 2,
- * 4 columns per thread (-1: not tuned yet).  us (host, 4 floats): measured
- * microseconds per pass of each candidate (-1 if not run). */
+ * 4 columns per thread, a site tile's columns processed together; 4, 5, 6 =
+ * the same with one column group swept over the whole lattice before the next
+ * (-1: not tuned yet; FP64 uses 2 columns for 3 and 6).  us (host, 7 floats):
+ * measured microseconds per pass of each candidate (-1 if not run). */
 sc_status sc_wilson_tune_info(const sc_op* op, sc_dtype dtype, int k, int* variant, float* us);
 
 /* Pin the stencil launch shape for (this op's lattice, dtype, k) instead of
  * tuning it (variant 0..3 as above); variant -1 forgets the choice so the next
  * pass tunes again.  Errors: SC_ERR_ARG for a non-Wilson op, k < 1 or a
- * variant outside -1..3. */
+ * variant outside -1..6. */
 sc_status sc_wilson_tune_set(const sc_op* op, sc_dtype dtype, int k, int variant);
 
 /* ------------------------------------------------------------------ workspace */

@@ -270,7 +270,7 @@ class Op:
     def tune_info(self, k, single=True):
         """(variant, [us per candidate]) chosen by the stencil autotuner for k columns."""
         v = _INT()
-        us = (ctypes.c_float * 4)()
+        us = (ctypes.c_float * 7)()
         dt = SC_C64 if single else SC_C128
         _check(lib().sc_wilson_tune_info(self._h, dt, int(k), ctypes.byref(v), us))
         return v.value, [round(float(u), 2) for u in us]

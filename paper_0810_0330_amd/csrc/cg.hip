@@ -170,6 +170,56 @@ __global__ __launch_bounds__(kBlock) void k_cg_p(R* __restrict__ p, const R* __r
     }
 }
 
+// ---------------------------------------------------------------- reliable updates
+// Batched over the paused columns listed in cols[0..nu): gather, residual, direction.
+
+// x64_j += xs_j; xs_j = 0; xg_c = x64_j
+__global__ __launch_bounds__(kBlock) void k_ru_gather(const int* __restrict__ cols, double* __restrict__ X,
+                                                      int64_t ldx, float* __restrict__ xs, double* __restrict__ xg,
+                                                      int64_t N) {
+    const int c = blockIdx.y;
+    const int j = cols[c];
+    double* x = X + j * ldx;
+    float* a = xs + j * N;
+    double* o = xg + c * N;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock) {
+        const double v = x[i] + (double)a[i];
+        x[i] = v;
+        a[i] = 0.0f;
+        o[i] = v;
+    }
+}
+
+// r64_j = b_j - (A x)_c; r32_j = r64_j; partials of ||r64_j||^2
+__global__ __launch_bounds__(kBlock) void k_ru_resid(const int* __restrict__ cols, const double* __restrict__ B,
+                                                     int64_t ldb, const double* __restrict__ ax,
+                                                     double* __restrict__ r64, float* __restrict__ r32, int64_t N,
+                                                     double* part) {
+    __shared__ double sh[kWaves];
+    const int c = blockIdx.y;
+    const int j = cols[c];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock) {
+        const double v = B[j * ldb + i] - ax[c * N + i];
+        r64[j * N + i] = v;
+        r32[j * N + i] = (float)v;
+        acc += v * v;
+    }
+    block_partial(acc, part + (int64_t)c * gridDim.x, sh);
+}
+
+// p_j = r_j + beta_c p_j for the listed columns (beta_c = 0 restarts the direction)
+__global__ __launch_bounds__(kBlock) void k_ru_dir(const int* __restrict__ cols, const double* __restrict__ beta,
+                                                   float* __restrict__ p, const float* __restrict__ r, int64_t N) {
+    const int c = blockIdx.y;
+    const int j = cols[c];
+    const float b = (float)beta[c];
+    float* pc = p + j * N;
+    const float* rc = r + j * N;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock)
+        pc[i] = rc[i] + b * pc[i];
+}
+
 // ----------------------------------------------------------------------------
 struct CGWork {
     void* r;       // k x N2 (vector precision)
@@ -187,6 +237,8 @@ struct CGWork {
     CGCol* st[2];
     double* rho;
     double* bn;
+    int* cols;        // reliable update: paused column list (k)
+    double* ru_beta;  // reliable update: per listed column beta (k)
 };
 
 static CGWork carve_cg(Carver& c, const sc_op* op, int k, bool mixed) {
@@ -213,6 +265,8 @@ static CGWork carve_cg(Carver& c, const sc_op* op, int k, bool mixed) {
     w.st[1] = c.take<CGCol>(k);
     w.rho = c.take<double>(k);
     w.bn = c.take<double>(k);
+    w.cols = c.take<int>(k);
+    w.ru_beta = c.take<double>(k);
     return w;
 }
 
@@ -302,42 +356,47 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
                 if (mixed && hst[j].flag != 0 && hst[j].iters < hst[j].maxit) upd.push_back(j);
             }
             if (!upd.empty()) {
-                // reliable update of the paused columns: x64 += xs; r64 = b - A x64; r = r64; xs = 0
+                // reliable update of the paused columns (batched over the list):
+                // x64 += xs; xs = 0; r64 = b - A64 x64; r = r64; then the direction
                 const int nu = (int)upd.size();
-                for (int c = 0; c < nu; ++c) {
-                    const int j = upd[c];
-                    float* xs = (float*)w.xs + j * N2;
-                    SC_TRY(lincomb(0, X + j * ldx2, N2, 0, X + j * ldx2, N2, 1, xs, N2, N2, 1, 1.0, 1.0, s));
-                    SC_TRY(fill<float>(xs, N2, 0.0f, s));
-                    SC_TRY(lincomb(0, w.xg + c * N2, N2, 0, X + j * ldx2, N2, 0, nullptr, 0, N2, 1, 1.0, 0.0, s));
-                }
+                const int gr = red_grid(N2, 4);
+                SC_HIP(hipMemcpyAsync(w.cols, upd.data(), sizeof(int) * nu, hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(k_ru_gather, dim3(gr, nu), blk, 0, s, w.cols, X, ldx2, (float*)w.xs, w.xg, N2);
+                SC_LAUNCH_CHECK();
                 SC_TRY(op_apply(op, false, w.xg, op->n, w.ax64, op->n, nu, w.tmp64, s));
-                for (int c = 0; c < nu; ++c) {
-                    const int j = upd[c];
-                    SC_TRY(lincomb(0, w.r64 + j * N2, N2, 0, B + j * ldb2, N2, 0, w.ax64 + c * N2, N2, N2, 1, 1.0,
-                                   -1.0, s));
-                    SC_TRY(dot(0, w.r64 + j * N2, N2, 0, w.r64 + j * N2, N2, N2, 1, w.rho + j, w.part, nullptr, s));
-                }
-                SC_HIP(hipMemcpyAsync(hrr.data(), w.rho, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+                hipLaunchKernelGGL(k_ru_resid, dim3(gr, nu), blk, 0, s, w.cols, B, ldb2, w.ax64, w.r64, (float*)r, N2,
+                                   w.part);
+                SC_LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_dot_finish, dim3(nu), blk, 0, s, w.part, gr, w.rho);
+                SC_LAUNCH_CHECK();
+                SC_HIP(hipMemcpyAsync(hrr.data(), w.rho, sizeof(double) * nu, hipMemcpyDeviceToHost, s));
                 SC_HIP(hipStreamSynchronize(s));
-                for (int j : upd) {
-                    CGCol& c = hst[j];
-                    R* rj = r + j * N2;
-                    R* pj = p + j * N2;
-                    SC_TRY(lincomb(1, rj, N2, 0, w.r64 + j * N2, N2, 0, nullptr, 0, N2, 1, 1.0, 0.0, s));
-                    const bool done = !(hrr[j] > c.tol2);
+                std::vector<double> hb(nu);
+                std::vector<int> dl;
+                std::vector<double> db;
+                for (int c = 0; c < nu; ++c) {
+                    CGCol& cc = hst[upd[c]];
+                    const double rr = hrr[c];
+                    const bool done = !(rr > cc.tol2);
                     if (!done) {
                         // flag 1: the FP32 recurrence drifted below tol; restart the direction.
                         // flag 2: continue CG with the true residual: p = r + (rho_true / rho_prev) p.
-                        const double b = c.flag == 1 ? 0.0 : hrr[j] / c.rho_prev;
-                        SC_TRY(lincomb(1, pj, N2, 1, rj, N2, 1, pj, N2, N2, 1, 1.0, b, s));
+                        dl.push_back(upd[c]);
+                        db.push_back(cc.flag == 1 ? 0.0 : rr / cc.rho_prev);
                     }
-                    c.rho = hrr[j];
-                    c.rho_prev = hrr[j];
-                    c.rmax2 = hrr[j];
-                    c.active = done ? 0 : 1;
-                    c.flag = 0;
-                    any |= c.active != 0;
+                    cc.rho = rr;
+                    cc.rho_prev = rr;
+                    cc.rmax2 = rr;
+                    cc.active = done ? 0 : 1;
+                    cc.flag = 0;
+                    any |= cc.active != 0;
+                }
+                if (!dl.empty()) {
+                    SC_HIP(hipMemcpyAsync(w.cols, dl.data(), sizeof(int) * dl.size(), hipMemcpyHostToDevice, s));
+                    SC_HIP(hipMemcpyAsync(w.ru_beta, db.data(), sizeof(double) * db.size(), hipMemcpyHostToDevice, s));
+                    hipLaunchKernelGGL(k_ru_dir, dim3(gr, (unsigned)dl.size()), blk, 0, s, w.cols, w.ru_beta, (float*)p,
+                                       (const float*)r, N2);
+                    SC_LAUNCH_CHECK();
                 }
                 SC_HIP(hipMemcpyAsync(w.st[cur], hst.data(), sizeof(CGCol) * k, hipMemcpyHostToDevice, s));
                 SC_HIP(hipStreamSynchronize(s));

@@ -162,22 +162,25 @@ __device__ __forceinline__ void load_link(const R* __restrict__ U, unsigned V, i
 
 // Block -> work mapping.  Workgroups are dispatched round-robin over the 8
 // XCDs (block b runs on XCD b % 8), each with its own L2.  Logical work item
-// L = (b % 8) * per_xcd + b / 8 gives every XCD a contiguous range of the
-// lattice, and the column groups of one site tile are consecutive in L, so a
-// tile's links and its neighbours' spinors are reused from that XCD's L2.
+// L = (b % 8) * per_xcd + b / 8 gives every XCD a contiguous range of L.  In
+// tile-major order the column groups of one site tile are consecutive in L
+// (a tile's links are reused from L2); in column-major order one column group
+// sweeps the whole lattice before the next, so the t-neighbour slices of that
+// group stay in L2 even when all k columns together exceed the caches (the
+// links are then re-read once per group, from the 256 MB infinity cache).
 constexpr int kXcd = 8;
 
 // MODE 0: out = in - kappa * H in (D or D^H);  MODE 1: out = H in (or H^H in).
 // NC columns per thread: each link is loaded once and applied to NC spinors.
-template <typename R, bool DAG, int MODE, int NC, int MINW, bool BAR = false>
+template <typename R, bool DAG, int MODE, int NC, int MINW, bool BAR = false, bool COLMAJOR = false>
 __global__ __launch_bounds__(kBlock, MINW) void k_wilson(R* __restrict__ out, int64_t ldo, const R* __restrict__ in,
                                                    int64_t ldi, const R* __restrict__ U, Geom g, R kappa, R tsign,
                                                    int k, int ncg, int ntiles, int per_xcd) {
     const int b = blockIdx.x;
     const int L = (b % kXcd) * per_xcd + b / kXcd;
     if (L >= ntiles * ncg) return;
-    const int tile = L / ncg;
-    const int c0 = (L % ncg) * NC;
+    const int tile = COLMAJOR ? L % ntiles : L / ncg;
+    const int c0 = (COLMAJOR ? L / ntiles : L % ncg) * NC;
     const int s = tile * kBlock + threadIdx.x;
     const int V = (int)g.V;
     if (s >= V) return;
@@ -262,15 +265,15 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson(R* __restrict__ out, in
 // Rolled variant: a runtime loop over the 8 hops with a wave-uniform switch.
 // Only one hop's operands are live at a time (low register use, high
 // occupancy); the latency of a hop's loads is hidden by the other waves.
-template <typename R, bool DAG, int MODE, int NC, int MINW>
+template <typename R, bool DAG, int MODE, int NC, int MINW, bool COLMAJOR = false>
 __global__ __launch_bounds__(kBlock, MINW) void k_wilson_r(R* __restrict__ out, int64_t ldo, const R* __restrict__ in,
                                                          int64_t ldi, const R* __restrict__ U, Geom g, R kappa,
                                                          R tsign, int k, int ncg, int ntiles, int per_xcd) {
     const int b = blockIdx.x;
     const int L = (b % kXcd) * per_xcd + b / kXcd;
     if (L >= ntiles * ncg) return;
-    const int tile = L / ncg;
-    const int c0 = (L % ncg) * NC;
+    const int tile = COLMAJOR ? L % ntiles : L / ncg;
+    const int c0 = (COLMAJOR ? L / ntiles : L % ncg) * NC;
     const int s = tile * kBlock + threadIdx.x;
     const int V = (int)g.V;
     if (s >= V) return;
@@ -353,9 +356,18 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson_r(R* __restrict__ out, 
 // ---------------------------------------------------------------- launchers
 // ---------------------------------------------------------------- variants and autotuning
 // Candidate launch shapes of a stencil pass (columns per thread x loop form).
-enum WilsonVariant { WV_UNROLLED_1 = 0, WV_ROLLED_1 = 1, WV_ROLLED_2 = 2, WV_ROLLED_4 = 3, WV_COUNT = 4 };
+enum WilsonVariant {
+    WV_UNROLLED_1 = 0,
+    WV_ROLLED_1 = 1,
+    WV_ROLLED_2 = 2,
+    WV_ROLLED_4 = 3,
+    WV_ROLLED_1_CM = 4,
+    WV_ROLLED_2_CM = 5,
+    WV_ROLLED_4_CM = 6,
+    WV_COUNT = 7
+};
 
-template <typename R, int NC, bool ROLLED>
+template <typename R, int NC, bool ROLLED, bool CM>
 static void wilson_launch_v(const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k, const R* U,
                             hipStream_t s) {
     Geom g{op->dims[0], op->dims[1], op->dims[2], op->dims[3], op->vol};
@@ -368,11 +380,11 @@ static void wilson_launch_v(const sc_op* op, int which, const R* X, int64_t ldx,
     // ld arguments are in reals (2 per complex element)
 #define SC_WL(DAG, MODE)                                                                                       \
     if (ROLLED)                                                                                                \
-        hipLaunchKernelGGL((k_wilson_r<R, DAG, MODE, NC, 1>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X, 2 * ldx, U, \
-                           g, kap, ts, k, ncg, ntiles, per_xcd);                                               \
+        hipLaunchKernelGGL((k_wilson_r<R, DAG, MODE, NC, 1, CM>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,     \
+                           2 * ldx, U, g, kap, ts, k, ncg, ntiles, per_xcd);                                   \
     else                                                                                                       \
-        hipLaunchKernelGGL((k_wilson<R, DAG, MODE, NC, 1>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X, 2 * ldx, U,   \
-                           g, kap, ts, k, ncg, ntiles, per_xcd);
+        hipLaunchKernelGGL((k_wilson<R, DAG, MODE, NC, 1, false, CM>), grid, dim3(kBlock), 0, s, Y, 2 * ldy,   \
+                           X, 2 * ldx, U, g, kap, ts, k, ncg, ntiles, per_xcd);
     switch (which) {
         case 0: SC_WL(false, 0) break;
         case 1: SC_WL(true, 0) break;
@@ -382,17 +394,19 @@ static void wilson_launch_v(const sc_op* op, int which, const R* X, int64_t ldx,
 #undef SC_WL
 }
 
+// FP64 has no 4-column shape (it would spill): those ids fall back to 2 columns
 template <typename R>
 static void wilson_launch_variant(int v, const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k,
                                   const R* U, hipStream_t s) {
+    constexpr int N4 = sizeof(R) == 4 ? 4 : 2;
     switch (v) {
-        case WV_UNROLLED_1: wilson_launch_v<R, 1, false>(op, which, X, ldx, Y, ldy, k, U, s); break;
-        case WV_ROLLED_1: wilson_launch_v<R, 1, true>(op, which, X, ldx, Y, ldy, k, U, s); break;
-        case WV_ROLLED_2: wilson_launch_v<R, 2, true>(op, which, X, ldx, Y, ldy, k, U, s); break;
-        default:
-            if (sizeof(R) == 4) wilson_launch_v<R, 4, true>(op, which, X, ldx, Y, ldy, k, U, s);
-            else wilson_launch_v<R, 2, true>(op, which, X, ldx, Y, ldy, k, U, s);
-            break;
+        case WV_UNROLLED_1: wilson_launch_v<R, 1, false, false>(op, which, X, ldx, Y, ldy, k, U, s); break;
+        case WV_ROLLED_1: wilson_launch_v<R, 1, true, false>(op, which, X, ldx, Y, ldy, k, U, s); break;
+        case WV_ROLLED_2: wilson_launch_v<R, 2, true, false>(op, which, X, ldx, Y, ldy, k, U, s); break;
+        case WV_ROLLED_4: wilson_launch_v<R, N4, true, false>(op, which, X, ldx, Y, ldy, k, U, s); break;
+        case WV_ROLLED_1_CM: wilson_launch_v<R, 1, true, true>(op, which, X, ldx, Y, ldy, k, U, s); break;
+        case WV_ROLLED_2_CM: wilson_launch_v<R, 2, true, true>(op, which, X, ldx, Y, ldy, k, U, s); break;
+        default: wilson_launch_v<R, N4, true, true>(op, which, X, ldx, Y, ldy, k, U, s); break;
     }
 }
 
@@ -434,7 +448,8 @@ static TuneRec tune_variants(const sc_op* op, int which, const R* X, int64_t ldx
     float best = 1e30f;
     for (int v = 0; v < WV_COUNT; ++v) {
         rec.us[v] = -1.0f;
-        if (sizeof(R) == 8 && v == WV_ROLLED_4) continue;  // same shape as WV_ROLLED_2 in FP64
+        if (sizeof(R) == 8 && (v == WV_ROLLED_4 || v == WV_ROLLED_4_CM)) continue;  // FP64 has no 4-column shape
+        if (k == 1 && v >= WV_ROLLED_1_CM) continue;  // order is irrelevant for one column
         wilson_launch_variant<R>(v, op, which, X, ldx, Y, ldy, k, U, s);  // warm
         hipEventRecord(e0, s);
         for (int r = 0; r < 3; ++r) wilson_launch_variant<R>(v, op, which, X, ldx, Y, ldy, k, U, s);

@@ -25,6 +25,241 @@ __device__ __forceinline__ cplx<double> ld_elem(const R* p, int64_t idx) {
     }
 }
 
+// ---------------------------------------------------------------- FP64 MFMA versions (complex)
+// v_mfma_f64_16x16x4f64: D(16x16) += A(16x4) B(4x16); lane l supplies
+// A[l%16][l/16] and B[l/16][l%16] and holds D[l/16 + 4v][l%16] in register v.
+// A complex product is four real ones on the real and imaginary parts.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// G = V^H W: block = 4 waves over 64 basis columns (16 per wave) x 16*NJ
+// right-hand columns, one row chunk; LDS stages of 32 complex rows.
+template <typename VR, typename WR, int NJ>
+__global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, int64_t ldv, int64_t n, int M,
+                                                    ColPtrs<const void> W, int N, double* __restrict__ part,
+                                                    int64_t rows_per_chunk, const int* halt) {
+    if (halt && *halt) return;
+    constexpr int KR = 32;          // complex rows per LDS stage
+    constexpr int TA = 64;          // basis columns per block
+    constexpr int TJ = 16 * NJ;     // right-hand columns per block
+    __shared__ double vr[KR][TA + 1], vi[KR][TA + 1];
+    __shared__ double wr[KR][TJ + 1], wi[KR][TJ + 1];
+    const int a0 = blockIdx.y * TA;
+    const int64_t r0 = blockIdx.x * rows_per_chunk;
+    const int64_t r1 = min(n, r0 + rows_per_chunk);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    d4_t accr[NJ], acci[NJ];
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) accr[t] = acci[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int64_t rb = r0; rb < r1; rb += KR) {
+        __syncthreads();
+        // V tile: column a, rows rb..rb+KR; consecutive threads walk down a column
+        for (int e = threadIdx.x; e < KR * TA; e += kBlock) {
+            const int rr = e % KR, aa = e / KR;
+            const int64_t r = rb + rr;
+            const int a = a0 + aa;
+            cplx<double> v{0.0, 0.0};
+            if (r < r1 && a < M) {
+                const cplx<VR> c = ld2(V, (int64_t)a * ldv + r);
+                v = {(double)c.re, (double)c.im};
+            }
+            vr[rr][aa] = v.re;
+            vi[rr][aa] = v.im;
+        }
+        for (int e = threadIdx.x; e < KR * TJ; e += kBlock) {
+            const int rr = e % KR, jj = e / KR;
+            const int64_t r = rb + rr;
+            cplx<double> w{0.0, 0.0};
+            if (r < r1 && jj < N) {
+                const cplx<WR> c = ld2((const WR*)W.p[jj], r);
+                w = {(double)c.re, (double)c.im};
+            }
+            wr[rr][jj] = w.re;
+            wi[rr][jj] = w.im;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < KR / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            const double ar = vr[kr][wv * 16 + (lane & 15)];
+            const double ai = vi[kr][wv * 16 + (lane & 15)];
+#pragma unroll
+            for (int t = 0; t < NJ; ++t) {
+                const double br = wr[kr][t * 16 + (lane & 15)];
+                const double bi = wi[kr][t * 16 + (lane & 15)];
+                accr[t] = mfma16(ar, br, accr[t]);   // Re += Vr Wr + Vi Wi
+                accr[t] = mfma16(ai, bi, accr[t]);
+                acci[t] = mfma16(ar, bi, acci[t]);   // Im += Vr Wi - Vi Wr
+                acci[t] = mfma16(ai, -br, acci[t]);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) {
+        const int j = t * 16 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int a = a0 + wv * 16 + (lane >> 4) + 4 * v;
+            if (a < M && j < N) {
+                const int64_t o = ((int64_t)blockIdx.x * M + a) * N + j;
+                part[2 * o] = accr[t][v];
+                part[2 * o + 1] = acci[t][v];
+            }
+        }
+    }
+}
+
+// X_j += scale * V Y_j: block = 4 waves over 64 rows (16 per wave) x 16*NJ
+// columns; LDS stages of 32 basis columns.
+template <typename VR, typename XR, int NJ>
+__global__ __launch_bounds__(kBlock) void k_nn_mfma(const VR* __restrict__ V, int64_t ldv, int64_t n, int M,
+                                                    const double* __restrict__ Y, int N, ColPtrs<void> X,
+                                                    double scale, const int* halt) {
+    if (halt && *halt) return;
+    constexpr int KA = 32;          // basis columns per LDS stage
+    constexpr int TR = 64;          // rows per block
+    constexpr int TJ = 16 * NJ;
+    __shared__ double vr[TR][KA + 1], vi[TR][KA + 1];
+    __shared__ double yr[KA][TJ + 1], yi[KA][TJ + 1];
+    const int64_t row0 = (int64_t)blockIdx.x * TR;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    d4_t accr[NJ], acci[NJ];
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) accr[t] = acci[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int ab = 0; ab < M; ab += KA) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < TR * KA; e += kBlock) {
+            const int rr = e % TR, aa = e / TR;
+            const int64_t r = row0 + rr;
+            const int a = ab + aa;
+            cplx<double> v{0.0, 0.0};
+            if (r < n && a < M) {
+                const cplx<VR> c = ld2(V, (int64_t)a * ldv + r);
+                v = {(double)c.re, (double)c.im};
+            }
+            vr[rr][aa] = v.re;
+            vi[rr][aa] = v.im;
+        }
+        for (int e = threadIdx.x; e < KA * TJ; e += kBlock) {
+            const int aa = e / TJ, jj = e % TJ;
+            const int a = ab + aa;
+            double re = 0.0, im = 0.0;
+            if (a < M && jj < N) {
+                re = Y[((int64_t)a * N + jj) * 2];
+                im = Y[((int64_t)a * N + jj) * 2 + 1];
+            }
+            yr[aa][jj] = re;
+            yi[aa][jj] = im;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < KA / 4; ++ks) {
+            const int ka = ks * 4 + (lane >> 4);
+            const double ar = vr[wv * 16 + (lane & 15)][ka];
+            const double ai = vi[wv * 16 + (lane & 15)][ka];
+#pragma unroll
+            for (int t = 0; t < NJ; ++t) {
+                const double br = yr[ka][t * 16 + (lane & 15)];
+                const double bi = yi[ka][t * 16 + (lane & 15)];
+                accr[t] = mfma16(ar, br, accr[t]);   // Re += Vr Yr - Vi Yi
+                accr[t] = mfma16(ai, -bi, accr[t]);
+                acci[t] = mfma16(ar, bi, acci[t]);   // Im += Vr Yi + Vi Yr
+                acci[t] = mfma16(ai, br, acci[t]);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) {
+        const int j = t * 16 + (lane & 15);
+        if (j >= N) continue;
+        XR* x = (XR*)X.p[j];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t r = row0 + wv * 16 + (lane >> 4) + 4 * v;
+            if (r < n) {
+                cplx<XR> c = ld2(x, r);
+                c.re = (XR)((double)c.re + scale * accr[t][v]);
+                c.im = (XR)((double)c.im + scale * acci[t][v]);
+                st2(x, r, c);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- G = V^H W, N <= 2 (reorthogonalization)
+// Bandwidth kernel: each thread keeps RPT rows of the (at most two) W columns
+// in registers and streams the basis columns once; per basis column the
+// block's sum is formed by wave shuffles and a 4-entry LDS reduction.
+constexpr int kSmallRPT = 8;     // rows per thread
+constexpr int kSmallCols = 64;   // basis columns per block
+
+template <typename VR, typename WR>
+__global__ __launch_bounds__(kBlock) void k_cn_small(const VR* __restrict__ V, int64_t ldv, int64_t n, int M,
+                                                     ColPtrs<const void> W, int N, double* __restrict__ part,
+                                                     const int* halt) {
+    if (halt && *halt) return;
+    __shared__ double red[kSmallCols][kWaves][4];
+    const int64_t rbase = (int64_t)blockIdx.x * kBlock * kSmallRPT;
+    const int a0 = blockIdx.y * kSmallCols;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    cplx<double> w0[kSmallRPT], w1[kSmallRPT];
+    bool ok[kSmallRPT];
+#pragma unroll
+    for (int t = 0; t < kSmallRPT; ++t) {
+        const int64_t r = rbase + threadIdx.x + (int64_t)t * kBlock;
+        ok[t] = r < n;
+        w0[t] = w1[t] = cplx<double>{0.0, 0.0};
+        if (ok[t]) {
+            const cplx<WR> c0 = ld2((const WR*)W.p[0], r);
+            w0[t] = {(double)c0.re, (double)c0.im};
+            if (N > 1) {
+                const cplx<WR> c1 = ld2((const WR*)W.p[1], r);
+                w1[t] = {(double)c1.re, (double)c1.im};
+            }
+        }
+    }
+    const int na = min(kSmallCols, M - a0);
+    for (int aa = 0; aa < na; ++aa) {
+        const VR* col = V + 2 * ((int64_t)(a0 + aa) * ldv);
+        double s0r = 0.0, s0i = 0.0, s1r = 0.0, s1i = 0.0;
+#pragma unroll
+        for (int t = 0; t < kSmallRPT; ++t) {
+            if (!ok[t]) continue;
+            const int64_t r = rbase + threadIdx.x + (int64_t)t * kBlock;
+            const cplx<VR> c = ld2(col, r);
+            const double vr = (double)c.re, vi = (double)c.im;
+            s0r += vr * w0[t].re + vi * w0[t].im;   // conj(v) w
+            s0i += vr * w0[t].im - vi * w0[t].re;
+            s1r += vr * w1[t].re + vi * w1[t].im;
+            s1i += vr * w1[t].im - vi * w1[t].re;
+        }
+        s0r = wave_sum(s0r);
+        s0i = wave_sum(s0i);
+        s1r = wave_sum(s1r);
+        s1i = wave_sum(s1i);
+        if (lane == 0) {
+            red[aa][wv][0] = s0r;
+            red[aa][wv][1] = s0i;
+            red[aa][wv][2] = s1r;
+            red[aa][wv][3] = s1i;
+        }
+    }
+    __syncthreads();
+    // thread -> (column, output): 64 columns x (N complex) values
+    for (int e = threadIdx.x; e < na * 2 * N; e += kBlock) {
+        const int aa = e / (2 * N), q = e % (2 * N);
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) v += red[aa][w][q];
+        const int j = q >> 1;
+        const int64_t o = ((int64_t)blockIdx.x * M + a0 + aa) * N + j;
+        part[2 * o + (q & 1)] = v;
+    }
+}
+
 // ---------------------------------------------------------------- G = V^H W
 // TM basis columns per block, G_ = 256/TM thread groups, QN W-columns per thread.
 template <typename VR, typename WR, bool CPLX, int TM, int QN, int KT>
@@ -102,10 +337,19 @@ struct CnPlan {
     int64_t rows;
 };
 
-static CnPlan cn_plan(int64_t n, int M, int N) {
+// Complex contractions use the MFMA kernel (64 basis columns x 32-row stages);
+// real ones the vector kernel.
+static CnPlan cn_plan(int64_t n, int M, int N, bool cplx = false) {
     CnPlan p;
-    p.tm = N <= 2 ? 128 : 32;
-    p.kt = N <= 2 ? 16 : 64;
+    if (cplx && N <= 2) {  // k_cn_small: fixed row chunks of kBlock * kSmallRPT rows
+        p.tm = kSmallCols;
+        p.kt = kBlock * kSmallRPT;
+        p.rows = p.kt;
+        p.nchunk = (int)std::max<int64_t>(1, (n + p.rows - 1) / p.rows);
+        return p;
+    }
+    p.tm = cplx ? 64 : (N <= 2 ? 128 : 32);
+    p.kt = cplx ? 32 : (N <= 2 ? 16 : 64);
     const int mt = (M + p.tm - 1) / p.tm;
     int64_t want = std::max<int64_t>(1, (2048 + mt - 1) / mt);
     const int64_t maxchunk = std::max<int64_t>(1, (n + p.kt - 1) / p.kt);
@@ -119,11 +363,11 @@ static CnPlan cn_plan(int64_t n, int M, int N) {
 
 // Partials needed by any call with M' <= M basis columns and N' <= N columns:
 // the split plan gives smaller M more row chunks, so the maximum is not at M.
-size_t gemm_cn_part_doubles(int64_t n, int M, int N, bool) {
+size_t gemm_cn_part_doubles(int64_t n, int M, int N, bool cplx) {
     size_t best = 0;
     for (int nq = 1; nq <= N; ++nq)
         for (int mm = 1; mm <= M; ++mm) {
-            const CnPlan p = cn_plan(n, mm, nq);
+            const CnPlan p = cn_plan(n, mm, nq, cplx);
             best = std::max(best, (size_t)p.nchunk * mm * nq * 2);
         }
     return best;
@@ -141,6 +385,18 @@ static void cn_launch(const CnPlan& p, const VR* V, int64_t ldv, int64_t n, int 
         hipLaunchKernelGGL((k_cn_partial<VR, WR, CPLX, 32, 4, 64>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
 }
 
+template <typename VR, typename WR>
+static void cn_mfma_launch(const CnPlan& p, const VR* V, int64_t ldv, int64_t n, int M, const ColPtrs<const void>& W,
+                           int N, double* part, const int* halt, hipStream_t s) {
+    dim3 grid((unsigned)p.nchunk, (unsigned)((M + 63) / 64));
+    if (N <= 2)
+        hipLaunchKernelGGL((k_cn_small<VR, WR>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, halt);
+    else if (N <= 16)
+        hipLaunchKernelGGL((k_cn_mfma<VR, WR, 1>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
+    else
+        hipLaunchKernelGGL((k_cn_mfma<VR, WR, 2>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
+}
+
 sc_status gemm_cn(bool cplx, bool vsingle, const void* V, int64_t ldv, int64_t n, int M, bool wsingle,
                   const ColPtrs<const void>& W, int N, double* G, double* part, const int* halt, hipStream_t s) {
     if (M <= 0 || N <= 0) return SC_OK;
@@ -148,20 +404,22 @@ sc_status gemm_cn(bool cplx, bool vsingle, const void* V, int64_t ldv, int64_t n
         set_error("gemm_cn: too many columns");
         return SC_ERR_ARG;
     }
-    CnPlan p = cn_plan(n, M, N);
+    CnPlan p = cn_plan(n, M, N, cplx);
     const double eb = (cplx ? 2.0 : 1.0);
     TimerScope ts_(TC_GEMM_CN, s,
                    (double)n * M * eb * (vsingle ? 4 : 8) + (double)n * N * eb * (wsingle ? 4 : 8) + (double)M * N * eb * 8,
                    (cplx ? 8.0 : 2.0) * n * M * N);
 #define SC_CN(VR, WR, C) cn_launch<VR, WR, C>(p, (const VR*)V, ldv, n, M, W, N, part, halt, s)
+#define SC_CNM(VR, WR) cn_mfma_launch<VR, WR>(p, (const VR*)V, ldv, n, M, W, N, part, halt, s)
     if (cplx) {
-        if (vsingle) { if (wsingle) SC_CN(float, float, true); else SC_CN(float, double, true); }
-        else { if (wsingle) SC_CN(double, float, true); else SC_CN(double, double, true); }
+        if (vsingle) { if (wsingle) SC_CNM(float, float); else SC_CNM(float, double); }
+        else { if (wsingle) SC_CNM(double, float); else SC_CNM(double, double); }
     } else {
         if (vsingle) { if (wsingle) SC_CN(float, float, false); else SC_CN(float, double, false); }
         else { if (wsingle) SC_CN(double, float, false); else SC_CN(double, double, false); }
     }
 #undef SC_CN
+#undef SC_CNM
     SC_LAUNCH_CHECK();
     const int64_t nout = (int64_t)M * N * (cplx ? 2 : 1);
     hipLaunchKernelGGL(k_cn_reduce, dim3((unsigned)((nout + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, part,
@@ -229,6 +487,14 @@ __global__ __launch_bounds__(kBlock) void k_nn(const VR* __restrict__ V, int64_t
 template <typename VR, typename XR, bool CPLX>
 static void nn_launch(const VR* V, int64_t ldv, int64_t n, int M, const double* Y, int N, const ColPtrs<void>& X,
                       double scale, const int* halt, hipStream_t s) {
+    if (CPLX && N > 2) {
+        dim3 gm((unsigned)((n + 63) / 64));
+        if (N <= 16)
+            hipLaunchKernelGGL((k_nn_mfma<VR, XR, 1>), gm, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
+        else
+            hipLaunchKernelGGL((k_nn_mfma<VR, XR, 2>), gm, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
+        return;
+    }
     dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
     if (N <= 2)
         hipLaunchKernelGGL((k_nn<VR, XR, CPLX, 2>), grid, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);

@@ -60,6 +60,8 @@ sc_status dot(int xt, const void* x, int64_t ldx, int yt, const void* y, int64_t
               double* res, double* part, unsigned* ctr, hipStream_t s);
 template <typename T>
 sc_status fill(T* p, int64_t n, T v, hipStream_t s);
+// res[b] = sum of part[b*G .. b*G+G) (one block per column), fixed order
+__global__ void k_dot_finish(const double* part, int G, double* res);
 
 // ---------------------------------------------------------------- tall-skinny (k_tsgemm.hip)
 // G[a*N + j] = sum_r conj(V[r,a]) W_j[r]  (a < M, j < N <= kMaxCols); G complex or real FP64.

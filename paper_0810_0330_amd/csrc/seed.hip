@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_norm_part(const R* __restrict__ x, i
 
 // step 9 (and step 2 for i = 0): beta_i = ||f|| from the partials, breakdown
 // and finiteness checks, v_{i+1} = f / beta_i stored as column i of V
-template <typename VT, typename FT>
+template <typename VT, typename FT, bool VEC>
 __global__ __launch_bounds__(kBlock) void k_lz_next(VT* __restrict__ vnext, const FT* __restrict__ f, int64_t N,
                                                     double* beta, int i, SeedState* st, const double* part, int G) {
     __shared__ double sh[kWaves];
@@ -84,8 +84,24 @@ __global__ __launch_bounds__(kBlock) void k_lz_next(VT* __restrict__ vnext, cons
     }
     const FT bf = (FT)b;
     const bool zero = brk || !fin;
-    for (int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x; j < N; j += (int64_t)gridDim.x * kBlock)
-        vnext[j] = zero ? VT(0) : (VT)(f[j] / bf);
+    if constexpr (VEC && sizeof(VT) == sizeof(FT)) {
+        constexpr int W = Pack<FT>::W;
+        const int64_t stride = (int64_t)gridDim.x * kBlock * W;
+        for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W; i0 < N; i0 += stride) {
+            if (i0 + W <= N) {
+                const Pack<FT> a = ldp(f, i0);
+                Pack<FT> o;
+#pragma unroll
+                for (int e = 0; e < W; ++e) o.v[e] = zero ? FT(0) : a.v[e] / bf;
+                stp((FT*)vnext, i0, o);
+            } else {
+                for (int64_t j = i0; j < N; ++j) vnext[j] = zero ? VT(0) : (VT)(f[j] / bf);
+            }
+        }
+    } else {
+        for (int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x; j < N; j += (int64_t)gridDim.x * kBlock)
+            vnext[j] = zero ? VT(0) : (VT)(f[j] / bf);
+    }
 }
 
 // step 5, first half: f = A v_i - beta_{i-1} v_{i-1}; partials of Re(v_i^H f)
@@ -238,7 +254,7 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
     // step 2: beta_0 = ||r0||, v_1 = r0 / beta_0
     hipLaunchKernelGGL((k_norm_part<double, VEC>), dim3(g), blk, 0, s, w.r64, N2, w.part_f, nullptr);
     SC_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_lz_next<R, double>), dim3(g), blk, 0, s, V, w.r64, N2, beta, 0, w.st, w.part_f, g);
+    hipLaunchKernelGGL((k_lz_next<R, double, false>), dim3(g), blk, 0, s, V, w.r64, N2, beta, 0, w.st, w.part_f, g);
     SC_LAUNCH_CHECK();
 
     for (int i = 1; i <= m; ++i) {
@@ -276,7 +292,7 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
             SC_LAUNCH_CHECK();
         }
         // step 9: beta_i = ||f||, v_{i+1} = f / beta_i
-        hipLaunchKernelGGL((k_lz_next<R, R>), dim3(g), blk, 0, s, vnext, f, N2, beta, i, w.st, w.part_f, g);
+        hipLaunchKernelGGL((k_lz_next<R, R, VEC>), dim3(g), blk, 0, s, vnext, f, N2, beta, i, w.st, w.part_f, g);
         SC_LAUNCH_CHECK();
     }
     return SC_OK;

@@ -172,7 +172,7 @@ def test_wilson_every_launch_shape(k):
     ref = {w: np.stack([f(fl).reshape(-1) for fl in fields], axis=1) for w, f in [
         (0, lambda fl: ops.wilson_D(fl, U, 0.12)), (1, lambda fl: ops.wilson_Ddag(fl, U, 0.12)),
         (2, lambda fl: ops.wilson_hop(fl, U)), (3, lambda fl: ops.wilson_hop(fl, U, dagger=True))]}
-    for v in range(4):
+    for v in range(7):
         for single in (False, True):
             op.tune_set(k, v, single=single)
             for which in range(4):
