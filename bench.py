@@ -45,10 +45,14 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timer", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--timer-every", type=int, default=8,
+                    help="time one launch in this many of each kernel class (an event pair costs a few us)")
     ap.add_argument("--micro", default=None, choices=["wilson_f32", "wilson_f64", "copy", "gemm_cn", "gemm_nn"],
                     help="time one kernel in isolation on the workload's lattice (for profilers)")
     ap.add_argument("--k", type=int, default=1, help="columns per launch in --micro mode")
     ap.add_argument("--reps", type=int, default=20, help="launches in --micro mode")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="--micro wilson_*: pin this stencil launch shape instead of autotuning")
     return ap.parse_args()
 
 
@@ -70,7 +74,9 @@ def micro(args, w):
     res = {"micro": args.micro, "k": k, "reps": args.reps, "n": op.n}
     if args.micro.startswith("wilson"):
         Y = torch.empty_like(X)
-        fn = lambda: op.dslash(X, 0, single=single)  # noqa: E731
+        if args.variant is not None:
+            op.tune_set(k, args.variant, single=single)
+        fn = lambda: op.dslash(X, 0, single=single, out=Y)  # noqa: E731
         bytes_per = (48.0 * k + 72.0) * (4 if single else 8) * (op.n // 12)
     elif args.micro == "copy":
         Y = torch.empty_like(X)
@@ -98,6 +104,8 @@ def micro(args, w):
     res["GBps"] = bytes_per / (res["avg_us"] * 1e-6) / 1e9
     res["kernels"] = {k2: v for k2, v in api.timer_read().items() if v["launches"]}
     api.timer_enable(False)
+    if args.micro.startswith("wilson"):
+        res["variant"], res["tune_us"] = op.tune_info(k, single=single)
     print(json.dumps(res), flush=True)
 
 
@@ -201,7 +209,7 @@ def main():
         log(f"[bench] warmup {i}: iters {out['iters']} max relres {max(out['relres']):.2e}")
     stream = torch.cuda.current_stream()
     if not args.no_timer:
-        api.timer_enable(True)
+        api.timer_enable(True, every=args.timer_every)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -239,7 +247,8 @@ def main():
         plain = {"rhs_per_s": w.nrhs / tp, "ms": tp * 1e3, "iters": pits, "dtype": "f64"}
         log(f"[bench] plain FP64 CG: {tp * 1e3:.1f} ms, {plain['rhs_per_s']:.1f} RHS/s, iters {pits}")
 
-    # ---- roofline of the dominant kernel class
+    # ---- roofline of the dominant kernel class (launches are a uniform sample of
+    # each class, so summed sampled time ranks the classes by their total time)
     roof = None
     kernels = {}
     for name, k in kern.items():
@@ -256,7 +265,8 @@ def main():
         achieved = kd["GBps"]
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_launch_us": kd["avg_us"], "bytes_per_launch": kd["bytes_per_launch"]}
+                "avg_launch_us": kd["avg_us"], "bytes_per_launch": kd["bytes_per_launch"],
+                "timed_launches": kd["launches"], "sample_every": args.timer_every}
 
     tuning = {}
     if w.op == "wilson":

@@ -126,18 +126,33 @@ sc_status sc_wilson_dslash(const sc_op* op, sc_dtype dtype, int which, const voi
  * first pass with a new (lattice, dtype, k) times each candidate shape on the
  * caller's buffers, which adds one host synchronisation to that call, and
  * keeps the fastest; SEEDCG_TUNE=0 in the environment selects fixed defaults,
- * and no tuning happens while the stream is being captured.  variant (host):
- * 0 = unrolled hops, 1 column per thread; 1, 2, 3 = rolled hop loop with 1, 2,
- * 4 columns per thread, a site tile's columns processed together; 4, 5, 6 =
- * the same with one column group swept over the whole lattice before the next
- * (-1: not tuned yet; FP64 uses 2 columns for 3 and 6).  us (host, 7 floats):
- * measured microseconds per pass of each candidate (-1 if not run). */
+ * and no tuning happens while the stream is being captured.
+ * variant (host) = order * 16 + shape * 4 + chunk, -1 if not tuned yet.
+ * shape 0: hops unrolled, 1 column per thread; 1, 2, 3: rolled hop loop with
+ * 1, 2, 4 columns per thread (FP64: 2 for shape 3).  The (256-site tile,
+ * column group) work items are enumerated in chunks of G column groups, the G
+ * groups of a tile consecutive: chunk 0: G = all groups (a tile's columns
+ * together), 1: G = 1 (one group sweeps the lattice before the next), 2: G =
+ * 2, 3: G = 4.  order 0: tiles in site order; 1: blocks of 4 tiles along z
+ * taken through all time slices before the next block (only when each time
+ * slice holds a multiple of 4 whole tiles, else as order 0).  32..43: for
+ * lattices with X Y = 256 only, one block per xy-plane walking t through
+ * segments of 4, 8, 16 time slices, x and y neighbours staged in LDS, t
+ * neighbours kept in registers: 32 + 6 * o + 3 * (c - 1) + {0, 1, 2} for
+ * segments of {4, 8, 16}, c = 1 or 2 columns per thread (2: FP32 only, FP64
+ * uses 1), o = 0: the planes of a segment are consecutive work items, 1: the
+ * column groups of a plane are.  44: one wave per direction mu and 64
+ * sites, the four partial sums added in LDS (for few columns).
+ * us (host, SC_WILSON_VARIANTS floats): measured microseconds per pass of each
+ * candidate (-1 if not run). */
+#define SC_WILSON_VARIANTS 45
 sc_status sc_wilson_tune_info(const sc_op* op, sc_dtype dtype, int k, int* variant, float* us);
 
 /* Pin the stencil launch shape for (this op's lattice, dtype, k) instead of
- * tuning it (variant 0..3 as above); variant -1 forgets the choice so the next
- * pass tunes again.  Errors: SC_ERR_ARG for a non-Wilson op, k < 1 or a
- * variant outside -1..6. */
+ * tuning it (variant as above); variant -1 forgets the choice so the next
+ * pass tunes again.  Errors: SC_ERR_ARG for a non-Wilson op, k < 1, a
+ * variant outside -1..SC_WILSON_VARIANTS-1, or a t-march variant (32..43) on
+ * a lattice with X Y != 256. */
 sc_status sc_wilson_tune_set(const sc_op* op, sc_dtype dtype, int k, int variant);
 
 /* ------------------------------------------------------------------ workspace */
@@ -215,19 +230,23 @@ sc_status sc_solve_cg(const sc_op* op, int mixed, const void* B_dev, int64_t ldb
 
 /* ------------------------------------------------------------------ timing
  * Optional event timing of the library's main kernels, for benchmarks (not
- * part of the method).  sc_timer_enable(1) clears earlier records and, from
- * then on, brackets every launch of the classes below with two HIP events on
- * the launch's own stream, recording the launch's algorithmic bytes and flops;
- * sc_timer_enable(0) stops recording.  sc_timer_read(cls, ...) waits for the
+ * part of the method).  sc_timer_enable(every) with every >= 1 clears earlier
+ * records and, from then on, brackets one launch in `every` of each class
+ * below (a fixed pseudo-random sample; every = 1 times all of them) with two
+ * HIP events on the launch's own stream, recording that launch's algorithmic
+ * bytes and flops; sc_timer_enable(0) stops recording.  Launches inside a
+ * stream capture are never timed.  sc_timer_read(cls, ...) waits for the
  * recorded events and returns, for class cls, the summed kernel time (ms),
- * the number of launches and the summed algorithmic bytes and flops:
- *   0  Wilson stencil pass, FP32: (48k + 72)*4 bytes and 1368k (D, D^H) or
- *      1320k (H, H^H) flops per site for k columns;
- *   1  Wilson stencil pass, FP64: (48k + 72)*8 bytes per site, same flops;
+ * the number of timed launches and their summed algorithmic bytes and flops:
+ *   0  Wilson stencil pass, FP32, k = 1: (48k + 72)*4 bytes and 1368k (D,
+ *      D^H) or 1320k (H, H^H) flops per site for k columns;
+ *   1  Wilson stencil pass, FP64, k = 1: (48k + 72)*8 bytes per site, same flops;
  *   2  G = V^H W: V, W read once, G written; 8 n M N flops (complex);
- *   3  X += V Y:  V read once, X read and written; 8 n M N flops (complex).
+ *   3  X += V Y:  V read once, X read and written; 8 n M N flops (complex);
+ *   4  Wilson stencil pass, FP32, k > 1 (bytes and flops as class 0);
+ *   5  Wilson stencil pass, FP64, k > 1 (bytes and flops as class 1).
  * Errors: SC_ERR_ARG for an unknown class or a NULL pointer. */
-sc_status sc_timer_enable(int on);
+sc_status sc_timer_enable(int every);
 sc_status sc_timer_read(int cls, double* ms, int64_t* launches, double* bytes, double* flops);
 
 /* ------------------------------------------------------------------ batches

@@ -131,15 +131,19 @@ def release_workspace():
 
 
 # ----------------------------------------------------------------------------- timing
-TIMER_CLASSES = {0: "wilson_f32", 1: "wilson_f64", 2: "gemm_cn", 3: "gemm_nn"}
+WILSON_VARIANTS = 45  # SC_WILSON_VARIANTS: tiled shapes (orders x shapes x chunks) and t-march shapes
+
+TIMER_CLASSES = {0: "wilson_f32_k1", 1: "wilson_f64_k1", 2: "gemm_cn", 3: "gemm_nn", 4: "wilson_f32_kn",
+                 5: "wilson_f64_kn"}
 
 
-def timer_enable(on=True):
-    _check(lib().sc_timer_enable(1 if on else 0))
+def timer_enable(on=True, every=1):
+    """Start (clearing earlier records) or stop event timing; `every` > 1 times a 1-in-`every` sample."""
+    _check(lib().sc_timer_enable(int(every) if on else 0))
 
 
 def timer_read():
-    """{class name: dict(ms, launches, bytes, flops)} for the launches recorded since timer_enable(True)."""
+    """{class name: dict(ms, launches, bytes, flops)} for the launches timed since timer_enable(True)."""
     out = {}
     for cls, name in TIMER_CLASSES.items():
         ms, nl, by, fl = _DBL(), _I64(), _DBL(), _DBL()
@@ -270,7 +274,7 @@ class Op:
     def tune_info(self, k, single=True):
         """(variant, [us per candidate]) chosen by the stencil autotuner for k columns."""
         v = _INT()
-        us = (ctypes.c_float * 7)()
+        us = (ctypes.c_float * WILSON_VARIANTS)()
         dt = SC_C64 if single else SC_C128
         _check(lib().sc_wilson_tune_info(self._h, dt, int(k), ctypes.byref(v), us))
         return v.value, [round(float(u), 2) for u in us]
@@ -279,11 +283,16 @@ class Op:
         """Pin the stencil launch shape for k columns (variant -1: tune again)."""
         _check(lib().sc_wilson_tune_set(self._h, SC_C64 if single else SC_C128, int(k), int(variant)))
 
-    def dslash(self, X, which=0, single=False):
-        """Wilson pass: which 0 = D, 1 = D^H, 2 = H, 3 = H^H (D = 1 - kappa H)."""
+    def dslash(self, X, which=0, single=False, out=None):
+        """Wilson pass: which 0 = D, 1 = D^H, 2 = H, 3 = H^H (D = 1 - kappa H); `out` (optional) receives Y."""
         dt = self.single_dtype if single else self.dtype
         X = self._vec(X, dt)
-        Y = torch.empty_like(X)
+        if out is None:
+            Y = torch.empty_like(X)
+        else:
+            if out.shape != X.shape or out.dtype != X.dtype or not out.is_contiguous() or out.device != X.device:
+                raise SeedCGError(-1, "dslash: out must be a contiguous tensor like X")
+            Y = out
         _check(lib().sc_wilson_dslash(self._h, _DT_OF[dt], int(which), _ptr(X), self.n, _ptr(Y), self.n,
                                       X.shape[0], _stream()))
         return Y

@@ -369,14 +369,14 @@ sc_status sc_wilson_tune_set(const sc_op* op, sc_dtype dtype, int k, int variant
     SC_GUARD_BEGIN
     SC_ARG(op && op->kind == SC_OPK_WILSON, "not a Wilson op");
     SC_ARG(dtype == SC_C128 || dtype == SC_C64, "dtype must be SC_C128 or SC_C64");
-    SC_ARG(k >= 1 && variant >= -1 && variant <= 6, "k must be >= 1 and variant in -1..6");
+    SC_ARG(k >= 1 && variant >= -1 && variant < SC_WILSON_VARIANTS, "k must be >= 1 and variant in -1..44");
     return wilson_tune_pin(op, dtype == SC_C64, k, variant);
     SC_GUARD_END
 }
 
-sc_status sc_timer_enable(int on) {
+sc_status sc_timer_enable(int every) {
     SC_GUARD_BEGIN
-    return timer_enable(on);
+    return timer_enable(every);
     SC_GUARD_END
 }
 

@@ -14,10 +14,11 @@
 //
 // mixed = 1: the vectors and the operator run in FP32; x and the true
 // residual are FP64.  A reliable update (x64 += x32, r = b - A64 x64, r32 =
-// r, x32 = 0) is made when a column's FP32 residual norm has fallen by 10x
-// since its last update (p is kept and CG continues with the true residual),
-// and when the FP32 residual reaches tol (then CG restarts from the true
-// residual if it is still above tol).
+// r, x32 = 0) is made for every column whose FP32 residual norm has fallen by
+// 10x since its last update, at the next host check (the column keeps
+// iterating meanwhile, so no column idles; p is kept and CG continues with
+// the true residual), and when the FP32 residual reaches tol (the column
+// stops; CG restarts from the true residual if it is still above tol).
 #include "sc_internal.h"
 
 #include <vector>
@@ -147,8 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_p(R* __restrict__ p, const R* __r
         c.flag = 1;
         c.active = 0;
     } else if (mixed && rr < 0.01 * c.rmax2) {
-        c.flag = 2;
-        c.active = 0;
+        c.flag = 2;  // reliable update due at the next host check; the column keeps iterating
     }
     if (c.iters >= c.maxit) c.active = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) st_next[col] = c;
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_p(R* __restrict__ p, const R* __r
 }
 
 // ---------------------------------------------------------------- reliable updates
-// Batched over the paused columns listed in cols[0..nu): gather, residual, direction.
+// Batched over the flagged columns listed in cols[0..nu): gather, residual, direction.
 
 // x64_j += xs_j; xs_j = 0; xg_c = x64_j
 __global__ __launch_bounds__(kBlock) void k_ru_gather(const int* __restrict__ cols, double* __restrict__ X,
@@ -237,7 +237,7 @@ struct CGWork {
     CGCol* st[2];
     double* rho;
     double* bn;
-    int* cols;        // reliable update: paused column list (k)
+    int* cols;        // reliable update: flagged column list (k)
     double* ru_beta;  // reliable update: per listed column beta (k)
 };
 
@@ -356,7 +356,7 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
                 if (mixed && hst[j].flag != 0 && hst[j].iters < hst[j].maxit) upd.push_back(j);
             }
             if (!upd.empty()) {
-                // reliable update of the paused columns (batched over the list):
+                // reliable update of the flagged columns (batched over the list):
                 // x64 += xs; xs = 0; r64 = b - A64 x64; r = r64; then the direction
                 const int nu = (int)upd.size();
                 const int gr = red_grid(N2, 4);
@@ -378,12 +378,14 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
                     CGCol& cc = hst[upd[c]];
                     const double rr = hrr[c];
                     const bool done = !(rr > cc.tol2);
-                    if (!done) {
-                        // flag 1: the FP32 recurrence drifted below tol; restart the direction.
-                        // flag 2: continue CG with the true residual: p = r + (rho_true / rho_prev) p.
+                    if (!done && cc.flag == 1) {
+                        // the FP32 recurrence reached tol but the true residual did not:
+                        // restart the direction from the true residual
                         dl.push_back(upd[c]);
-                        db.push_back(cc.flag == 1 ? 0.0 : rr / cc.rho_prev);
+                        db.push_back(0.0);
                     }
+                    // flag 2: p was formed from the recursive residual and is kept;
+                    // CG continues from the true residual (rho = ||r_true||^2)
                     cc.rho = rr;
                     cc.rho_prev = rr;
                     cc.rmax2 = rr;

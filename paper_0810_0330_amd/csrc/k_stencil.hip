@@ -68,30 +68,44 @@ __device__ __forceinline__ cplx<R> addis(cplx<R> a, cplx<R> b) {
     else return {a.re + b.im, a.im - b.re};
 }
 
-// chi = U h (DAGU = false) or U^H h (DAGU = true) for one colour vector
+template <typename R>
+__device__ __forceinline__ R fmar(R a, R b, R c) {
+    if constexpr (sizeof(R) == 4) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
+// chi = U h (DAGU = false) or U^H h (DAGU = true) for one colour vector; four
+// fused multiply-adds per complex product
 template <bool DAGU, typename R>
 __device__ __forceinline__ void su3_mul(const cplx<R> u[3][3], const cplx<R> h[3], cplx<R> chi[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        R re = 0, im = 0;
+        R re, im;
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             const cplx<R> m = DAGU ? u[b][a] : u[a][b];
-            if constexpr (DAGU) {  // conj(m) * h
-                re += m.re * h[b].re + m.im * h[b].im;
-                im += m.re * h[b].im - m.im * h[b].re;
+            const R mi = DAGU ? -m.im : m.im;  // conj(m) for U^H
+            if (b == 0) {
+                re = m.re * h[b].re;
+                im = m.re * h[b].im;
             } else {
-                re += m.re * h[b].re - m.im * h[b].im;
-                im += m.re * h[b].im + m.im * h[b].re;
+                re = fmar(m.re, h[b].re, re);
+                im = fmar(m.re, h[b].im, im);
             }
+            re = fmar(-mi, h[b].im, re);
+            im = fmar(mi, h[b].re, im);
         }
         chi[a] = {re, im};
     }
 }
 
-// acc += (1 + SIG gamma_MU) (U or U^H) psi * bf
+// One hop, acc += (1 + SIG gamma_MU) (U or U^H) psi (times bf for the time
+// direction), in two halves: hop_half projects psi to the two colour vectors
+// of the half spinor and multiplies them by the link; hop_acc rebuilds the
+// four spin components from them and adds them to acc.
 template <int MU, int SIG, bool DAGU, typename R>
-__device__ __forceinline__ void hop(cplx<R> acc[4][3], const cplx<R> psi[4][3], const cplx<R> u[3][3], R bf) {
+__device__ __forceinline__ void hop_half(const cplx<R> psi[4][3], const cplx<R> u[3][3], R bf, cplx<R> c0[3],
+                                         cplx<R> c1[3]) {
     cplx<R> h0[3], h1[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -109,13 +123,21 @@ __device__ __forceinline__ void hop(cplx<R> acc[4][3], const cplx<R> psi[4][3], 
             h1[c] = adds<SIG>(psi[1][c], psi[3][c]);
         }
     }
-    cplx<R> c0[3], c1[3];
+    if constexpr (MU == 3) {  // (anti)periodic boundary factor of the time hops
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            h0[c].re *= bf; h0[c].im *= bf;
+            h1[c].re *= bf; h1[c].im *= bf;
+        }
+    }
     su3_mul<DAGU>(u, h0, c0);
     su3_mul<DAGU>(u, h1, c1);
+}
+
+template <int MU, int SIG, typename R>
+__device__ __forceinline__ void hop_acc(cplx<R> acc[4][3], const cplx<R> c0[3], const cplx<R> c1[3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        c0[c].re *= bf; c0[c].im *= bf;
-        c1[c].re *= bf; c1[c].im *= bf;
         acc[0][c] = cadd(acc[0][c], c0[c]);
         acc[1][c] = cadd(acc[1][c], c1[c]);
         // lower half: SIG * A^H chi
@@ -133,6 +155,13 @@ __device__ __forceinline__ void hop(cplx<R> acc[4][3], const cplx<R> psi[4][3], 
             acc[3][c] = adds<SIG>(acc[3][c], c1[c]);
         }
     }
+}
+
+template <int MU, int SIG, bool DAGU, typename R>
+__device__ __forceinline__ void hop(cplx<R> acc[4][3], const cplx<R> psi[4][3], const cplx<R> u[3][3], R bf) {
+    cplx<R> c0[3], c1[3];
+    hop_half<MU, SIG, DAGU>(psi, u, bf, c0, c1);
+    hop_acc<MU, SIG>(acc, c0, c1);
 }
 
 // Loads with a wave-uniform base (scalar registers) plus one unsigned 32-bit
@@ -161,26 +190,58 @@ __device__ __forceinline__ void load_link(const R* __restrict__ U, unsigned V, i
 }
 
 // Block -> work mapping.  Workgroups are dispatched round-robin over the 8
-// XCDs (block b runs on XCD b % 8), each with its own L2.  Logical work item
-// L = (b % 8) * per_xcd + b / 8 gives every XCD a contiguous range of L.  In
-// tile-major order the column groups of one site tile are consecutive in L
-// (a tile's links are reused from L2); in column-major order one column group
-// sweeps the whole lattice before the next, so the t-neighbour slices of that
-// group stay in L2 even when all k columns together exceed the caches (the
-// links are then re-read once per group, from the 256 MB infinity cache).
+// XCDs (block b runs on XCD b % 8), each with its own 4 MB L2.  Logical work
+// item L = (b % 8) * per_xcd + b / 8 gives every XCD a contiguous range of L.
+// L enumerates (site tile, column group) pairs chunk by chunk: a chunk holds G
+// consecutive column groups, and within a chunk the G groups of one tile are
+// consecutive in L.  G = all groups: a tile's links are reused from L2 by every
+// column, but the t-neighbour tiles of all k columns must stay cached too;
+// G = 1: one column group sweeps the lattice before the next, so its
+// neighbour slices stay in L2 while the links are re-read once per group.
+// Intermediate G trades the two.
+//
+// Tile order: zb = 1 takes tiles in site order, so a tile's t-neighbours are
+// XYZ / 256 tiles away.  zb > 1 (when the tiles of a time slice split into
+// blocks of zb) walks zb tiles along z, then the next time slice, and so on
+// through all of t before the next block of z: the t-neighbours are then zb
+// tiles away and the z-neighbours one, except across block edges.
 constexpr int kXcd = 8;
+
+__device__ __forceinline__ bool map_work(int ntiles, int ncg, int G, int per_xcd, int zb, int T, int& tile,
+                                         int& cg) {
+    const int b = blockIdx.x;
+    const int L = (b % kXcd) * per_xcd + b / kXcd;
+    if (L >= ntiles * ncg) return false;
+    const int nfull = ncg / G;
+    const int span = ntiles * G;
+    const int c = L / span;
+    if (c < nfull) {
+        const int r = L - c * span;
+        tile = r / G;
+        cg = c * G + r % G;
+    } else {  // last, partial chunk
+        const int gl = ncg - nfull * G;
+        const int r = L - nfull * span;
+        tile = r / gl;
+        cg = nfull * G + r % gl;
+    }
+    if (zb > 1) {  // tiles per time slice = ntiles / T, a multiple of zb (checked by the host)
+        const int per_slab = T * zb;
+        const int zblk = tile / per_slab, r = tile - zblk * per_slab;
+        tile = (r / zb) * (ntiles / T) + zblk * zb + r % zb;
+    }
+    return true;
+}
 
 // MODE 0: out = in - kappa * H in (D or D^H);  MODE 1: out = H in (or H^H in).
 // NC columns per thread: each link is loaded once and applied to NC spinors.
-template <typename R, bool DAG, int MODE, int NC, int MINW, bool BAR = false, bool COLMAJOR = false>
+template <typename R, bool DAG, int MODE, int NC, int MINW, bool BAR = false>
 __global__ __launch_bounds__(kBlock, MINW) void k_wilson(R* __restrict__ out, int64_t ldo, const R* __restrict__ in,
                                                    int64_t ldi, const R* __restrict__ U, Geom g, R kappa, R tsign,
-                                                   int k, int ncg, int ntiles, int per_xcd) {
-    const int b = blockIdx.x;
-    const int L = (b % kXcd) * per_xcd + b / kXcd;
-    if (L >= ntiles * ncg) return;
-    const int tile = COLMAJOR ? L % ntiles : L / ncg;
-    const int c0 = (COLMAJOR ? L / ntiles : L % ncg) * NC;
+                                                   int k, int ncg, int ntiles, int per_xcd, int G, int zb) {
+    int tile, cgi;
+    if (!map_work(ntiles, ncg, G, per_xcd, zb, g.T, tile, cgi)) return;
+    const int c0 = cgi * NC;
     const int s = tile * kBlock + threadIdx.x;
     const int V = (int)g.V;
     if (s >= V) return;
@@ -228,13 +289,13 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson(R* __restrict__ out, in
     load_link(U, uV, MU, us, u);                                             \
     _Pragma("unroll") for (int c = 0; c < NC; ++c) {                         \
         load_spinor(src[c], uV, nb_p[MU], psi);                              \
-        hop<MU, SF, false>(acc[c], psi, u, MU == 3 ? bf_p : R(1));           \
+        hop<MU, SF, false>(acc[c], psi, u, bf_p);                            \
         if (BAR) asm volatile("" ::: "memory");                              \
     }                                                                        \
     load_link(U, uV, MU, nb_m[MU], u);                                       \
     _Pragma("unroll") for (int c = 0; c < NC; ++c) {                         \
         load_spinor(src[c], uV, nb_m[MU], psi);                              \
-        hop<MU, SB, true>(acc[c], psi, u, MU == 3 ? bf_m : R(1));            \
+        hop<MU, SB, true>(acc[c], psi, u, bf_m);                             \
         if (BAR) asm volatile("" ::: "memory");                              \
     }
     SC_WILSON_DIR(0)
@@ -265,15 +326,14 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson(R* __restrict__ out, in
 // Rolled variant: a runtime loop over the 8 hops with a wave-uniform switch.
 // Only one hop's operands are live at a time (low register use, high
 // occupancy); the latency of a hop's loads is hidden by the other waves.
-template <typename R, bool DAG, int MODE, int NC, int MINW, bool COLMAJOR = false>
+template <typename R, bool DAG, int MODE, int NC, int MINW>
 __global__ __launch_bounds__(kBlock, MINW) void k_wilson_r(R* __restrict__ out, int64_t ldo, const R* __restrict__ in,
                                                          int64_t ldi, const R* __restrict__ U, Geom g, R kappa,
-                                                         R tsign, int k, int ncg, int ntiles, int per_xcd) {
-    const int b = blockIdx.x;
-    const int L = (b % kXcd) * per_xcd + b / kXcd;
-    if (L >= ntiles * ncg) return;
-    const int tile = COLMAJOR ? L % ntiles : L / ncg;
-    const int c0 = (COLMAJOR ? L / ntiles : L % ncg) * NC;
+                                                         R tsign, int k, int ncg, int ntiles, int per_xcd, int G,
+                                                         int zb) {
+    int tile, cgi;
+    if (!map_work(ntiles, ncg, G, per_xcd, zb, g.T, tile, cgi)) return;
+    const int c0 = cgi * NC;
     const int s = tile * kBlock + threadIdx.x;
     const int V = (int)g.V;
     if (s >= V) return;
@@ -353,26 +413,343 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson_r(R* __restrict__ out, 
     }
 }
 
-// ---------------------------------------------------------------- launchers
-// ---------------------------------------------------------------- variants and autotuning
-// Candidate launch shapes of a stencil pass (columns per thread x loop form).
-enum WilsonVariant {
-    WV_UNROLLED_1 = 0,
-    WV_ROLLED_1 = 1,
-    WV_ROLLED_2 = 2,
-    WV_ROLLED_4 = 3,
-    WV_ROLLED_1_CM = 4,
-    WV_ROLLED_2_CM = 5,
-    WV_ROLLED_4_CM = 6,
-    WV_COUNT = 7
-};
+// t-march form, for lattices whose xy-plane is one 256-site tile.  A block
+// owns the xy-plane at one z for NC columns and walks t through a segment of
+// tlen time slices.  Per slice its spinors are staged in LDS, so the x and y
+// hops read LDS; the +t neighbour is the same lane's next slice, loaded one
+// slice ahead; the -t hop into the next slice, U_t^H (1 + SB gamma_t) psi(t),
+// is formed while the slice is current (its link is the one the +t hop
+// loads) and carried in registers as a half spinor.  Only the z hops read
+// other planes from L2.  Work items enumerate (column group, segment, z) with
+// z fastest (CGMINOR = false: the Z planes of a segment run together on one
+// XCD) or (segment, z, column group) with the column group fastest (CGMINOR =
+// true: all column groups of a plane share its links through one L2).
+template <typename R, bool DAG, int MODE, int NC, bool CGMINOR>
+__global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64_t ldo, const R* __restrict__ in,
+                                                      int64_t ldi, const R* __restrict__ U, Geom g, R kappa,
+                                                      R tsign, int k, int ncg, int nseg, int tlen, int per_xcd) {
+    using V2 = typename vec2<R>::type;
+    __shared__ V2 pl[NC * 12][kBlock];
+    const int b = blockIdx.x;
+    const int L = (b % kXcd) * per_xcd + b / kXcd;
+    if (g.X * g.Y != kBlock || L >= ncg * nseg * g.Z) return;  // uniform over the block
+    const int Lp = CGMINOR ? L / ncg : L % (g.Z * nseg);  // (segment, z) pair
+    const int z = Lp % g.Z;
+    const int seg = Lp / g.Z;
+    const int c0 = (CGMINOR ? L % ncg : L / (g.Z * nseg)) * NC;
+    const int t0 = seg * tlen;
+    const int t1 = min(g.T, t0 + tlen);
+    const int p = threadIdx.x;  // x + X y
+    const int x = p % g.X, y = p / g.X;
+    const int XY = kBlock, XYZ = XY * g.Z;
+    const unsigned uV = (unsigned)g.V;
+    const int pxp = (x == g.X - 1 ? p - (g.X - 1) : p + 1), pxm = (x == 0 ? p + (g.X - 1) : p - 1);
+    const int pyp = (y == g.Y - 1 ? p - (g.Y - 1) * g.X : p + g.X), pym = (y == 0 ? p + (g.Y - 1) * g.X : p - g.X);
+    const int zoff_p = (z == g.Z - 1 ? -(g.Z - 1) * XY : XY), zoff_m = (z == 0 ? (g.Z - 1) * XY : -XY);
+    constexpr int SF = DAG ? 1 : -1;
+    constexpr int SB = -SF;
 
-template <typename R, int NC, bool ROLLED, bool CM>
+    const R* src[NC];
+    bool live[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        live[c] = c0 + c < k;
+        src[c] = in + (int64_t)(live[c] ? c0 + c : c0) * ldi;
+    }
+
+    // carry into slice t0 from slice t0 - 1
+    cplx<R> cr0[NC][3], cr1[NC][3];
+    {
+        const int tm = (t0 == 0 ? g.T - 1 : t0 - 1);
+        const unsigned sm = (unsigned)(p + XY * z + XYZ * tm);
+        cplx<R> u[3][3], psi[4][3];
+        load_link(U, uV, 3, sm, u);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            load_spinor(src[c], uV, sm, psi);
+            hop_half<3, SB, true>(psi, u, t0 == 0 ? tsign : R(1), cr0[c], cr1[c]);
+        }
+    }
+    cplx<R> cur[NC][4][3];
+    {
+        const unsigned s0 = (unsigned)(p + XY * z + XYZ * t0);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) load_spinor(src[c], uV, s0, cur[c]);
+    }
+
+#pragma unroll 1
+    for (int t = t0; t < t1; ++t) {
+        const unsigned s = (unsigned)(p + XY * z + XYZ * t);
+        __syncthreads();  // every lane is done reading the previous slice
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) pl[c * 12 + a * 3 + cc][p] = V2{cur[c][a][cc].re, cur[c][a][cc].im};
+        __syncthreads();
+
+        cplx<R> acc[NC][4][3];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) acc[c][a][cc] = {R(0), R(0)};
+            hop_acc<3, SB>(acc[c], cr0[c], cr1[c]);  // -t, carried
+        }
+        cplx<R> u[3][3], psi[4][3];
+        // x, y hops from the staged slice (d = 0..3), then z hops from L2
+        // (d = 4, 5); a rolled loop keeps one hop's operands live
+#pragma unroll 1
+        for (int d = 0; d < 6; ++d) {
+            const bool fwd = (d & 1) == 0;
+            if (d < 4) {
+                const int pn = d == 0 ? pxp : (d == 1 ? pxm : (d == 2 ? pyp : pym));
+                load_link(U, uV, d >> 1, fwd ? s : (unsigned)((int)s - p + pn), u);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int cc = 0; cc < 3; ++cc) {
+                            const V2 v = pl[c * 12 + a * 3 + cc][pn];
+                            psi[a][cc] = {v.x, v.y};
+                        }
+                    switch (d) {
+                        case 0: hop<0, SF, false>(acc[c], psi, u, R(1)); break;
+                        case 1: hop<0, SB, true>(acc[c], psi, u, R(1)); break;
+                        case 2: hop<1, SF, false>(acc[c], psi, u, R(1)); break;
+                        default: hop<1, SB, true>(acc[c], psi, u, R(1)); break;
+                    }
+                }
+            } else {
+                const unsigned sn = (unsigned)((int)s + (fwd ? zoff_p : zoff_m));
+                load_link(U, uV, 2, fwd ? s : sn, u);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    load_spinor(src[c], uV, sn, psi);
+                    if (fwd) hop<2, SF, false>(acc[c], psi, u, R(1));
+                    else hop<2, SB, true>(acc[c], psi, u, R(1));
+                }
+            }
+        }
+        // +t hop with the next slice, which becomes current; carry the -t hop
+        // of the next slice, formed from this one with the same link
+        {
+            const unsigned sp = (unsigned)(t == g.T - 1 ? (int)s - (g.T - 1) * XYZ : (int)s + XYZ);
+            const R bfp = (t == g.T - 1) ? tsign : R(1);
+            load_link(U, uV, 3, s, u);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                load_spinor(src[c], uV, sp, psi);
+                hop<3, SF, false>(acc[c], psi, u, bfp);
+                hop_half<3, SB, true>(cur[c], u, R(1), cr0[c], cr1[c]);
+                // write this slice's result, then advance
+                if (live[c]) {
+                    R* dst = out + (int64_t)(c0 + c) * ldo;
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int cc = 0; cc < 3; ++cc) {
+                            cplx<R> r = acc[c][a][cc];
+                            if constexpr (MODE == 0) r = {cur[c][a][cc].re - kappa * r.re, cur[c][a][cc].im - kappa * r.im};
+                            reinterpret_cast<V2*>(dst + 2 * (size_t)((a * 3 + cc) * uV))[s] = V2{r.re, r.im};
+                        }
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) cur[c][a][cc] = psi[a][cc];
+            }
+        }
+    }
+}
+
+// Direction-split form, for few columns: a block covers 64 sites of one
+// column and its wave w takes the two hops of direction mu = w (wave-uniform,
+// so no lane diverges); the four partial sums meet in LDS and wave w writes
+// spin component w of the result.  Four times the waves of the one-site-per-
+// thread form, each with a chain of two dependent hops instead of eight: for
+// launches too small to hide memory latency otherwise.
+template <typename R, bool DAG, int MODE>
+__global__ __launch_bounds__(kBlock) void k_wilson_dir(R* __restrict__ out, int64_t ldo, const R* __restrict__ in,
+                                                       int64_t ldi, const R* __restrict__ U, Geom g, R kappa,
+                                                       R tsign, int k, int ntile, int per_xcd) {
+    __shared__ R red[4][24][64];
+    const int b = blockIdx.x;
+    const int L = (b % kXcd) * per_xcd + b / kXcd;
+    if (L >= ntile * k) return;  // uniform over the block
+    const int tile = L / k, col = L % k;
+    const int mu = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int s = tile * 64 + l;
+    const bool ok = s < (int)g.V;
+    const unsigned uV = (unsigned)g.V;
+    const R* src = in + (int64_t)col * ldi;
+    constexpr int SF = DAG ? 1 : -1;
+    constexpr int SB = -SF;
+    cplx<R> acc[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
+    if (ok) {
+        const int XY = g.X * g.Y, XYZ = XY * g.Z;
+        int np, nm;
+        R bfp = R(1), bfm = R(1);
+        switch (mu) {
+            case 0: {
+                const int x = s % g.X;
+                np = x == g.X - 1 ? s - (g.X - 1) : s + 1;
+                nm = x == 0 ? s + (g.X - 1) : s - 1;
+                break;
+            }
+            case 1: {
+                const int y = (s / g.X) % g.Y;
+                np = y == g.Y - 1 ? s - (g.Y - 1) * g.X : s + g.X;
+                nm = y == 0 ? s + (g.Y - 1) * g.X : s - g.X;
+                break;
+            }
+            case 2: {
+                const int z = (s / XY) % g.Z;
+                np = z == g.Z - 1 ? s - (g.Z - 1) * XY : s + XY;
+                nm = z == 0 ? s + (g.Z - 1) * XY : s - XY;
+                break;
+            }
+            default: {
+                const int t = s / XYZ;
+                np = t == g.T - 1 ? s - (g.T - 1) * XYZ : s + XYZ;
+                nm = t == 0 ? s + (g.T - 1) * XYZ : s - XYZ;
+                bfp = t == g.T - 1 ? tsign : R(1);
+                bfm = t == 0 ? tsign : R(1);
+                break;
+            }
+        }
+        cplx<R> u[3][3], psi[4][3];
+        load_link(U, uV, mu, (unsigned)s, u);
+        load_spinor(src, uV, (unsigned)np, psi);
+        switch (mu) {
+            case 0: hop<0, SF, false>(acc, psi, u, bfp); break;
+            case 1: hop<1, SF, false>(acc, psi, u, bfp); break;
+            case 2: hop<2, SF, false>(acc, psi, u, bfp); break;
+            default: hop<3, SF, false>(acc, psi, u, bfp); break;
+        }
+        load_link(U, uV, mu, (unsigned)nm, u);
+        load_spinor(src, uV, (unsigned)nm, psi);
+        switch (mu) {
+            case 0: hop<0, SB, true>(acc, psi, u, bfm); break;
+            case 1: hop<1, SB, true>(acc, psi, u, bfm); break;
+            case 2: hop<2, SB, true>(acc, psi, u, bfm); break;
+            default: hop<3, SB, true>(acc, psi, u, bfm); break;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            red[mu][(a * 3 + cc) * 2][l] = acc[a][cc].re;
+            red[mu][(a * 3 + cc) * 2 + 1][l] = acc[a][cc].im;
+        }
+    __syncthreads();
+    if (!ok) return;
+    R* dst = out + (int64_t)col * ldo;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+        const int j = (mu * 3 + cc) * 2;  // spin mu, colour cc
+        cplx<R> r = {red[0][j][l] + red[1][j][l] + red[2][j][l] + red[3][j][l],
+                     red[0][j + 1][l] + red[1][j + 1][l] + red[2][j + 1][l] + red[3][j + 1][l]};
+        const size_t cb = 2 * (size_t)((mu * 3 + cc) * uV);
+        if constexpr (MODE == 0) {
+            const cplx<R> p = ldc(src + cb, (unsigned)s);
+            r = {p.re - kappa * r.re, p.im - kappa * r.im};
+        }
+        reinterpret_cast<typename vec2<R>::type*>(dst + cb)[s] = typename vec2<R>::type{r.re, r.im};
+    }
+}
+
+// ---------------------------------------------------------------- variants and autotuning
+// A launch shape is (hop loop form x columns per thread), a column-chunk size
+// G and a tile order; variant id = order * 16 + shape * 4 + chunk with chunk
+// 0: G = all groups, 1: G = 1, 2: G = 2, 3: G = 4, and order 0: site order,
+// 1: z-blocked by 4 tiles.  Ids 32..43 are the t-march form: 32 + 6 * order
+// + 3 * (NC - 1) + {0, 1, 2} for segments of {4, 8, 16} time slices, order 0:
+// column group slowest, 1: fastest.  Id 44 is the direction-split form.
+enum WilsonShape { WS_UNROLLED_1 = 0, WS_ROLLED_1 = 1, WS_ROLLED_2 = 2, WS_ROLLED_4 = 3, WS_COUNT = 4 };
+constexpr int kChunks = 4;
+constexpr int kOrders = 2;
+constexpr int kZBlock = 4;
+constexpr int WV_TILED = kOrders * WS_COUNT * kChunks;
+constexpr int WV_TMARCH = 12;
+constexpr int WV_DIR = WV_TILED + WV_TMARCH;  // the direction-split form
+constexpr int WV_COUNT = WV_DIR + 1;
+static_assert(WV_COUNT == SC_WILSON_VARIANTS, "variant count must match the header");
+
+static int chunk_groups(int chunk, int ncg) {
+    const int g = chunk == 0 ? ncg : (chunk == 1 ? 1 : (chunk == 2 ? 2 : 4));
+    return std::max(1, std::min(g, ncg));
+}
+
+// the z-blocked order needs whole tiles per time slice, in blocks of kZBlock
+static bool zblock_ok(const sc_op* op) {
+    const int64_t slice = (int64_t)op->dims[0] * op->dims[1] * op->dims[2];
+    return slice % kBlock == 0 && (slice / kBlock) % kZBlock == 0 && slice / kBlock > kZBlock;
+}
+
+// the t-march form needs the xy-plane to be exactly one tile
+static bool tmarch_ok(const sc_op* op) { return op->dims[0] * op->dims[1] == kBlock; }
+
+template <typename R, int NC, bool CGMINOR>
+static void wilson_launch_tm(const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k,
+                             const R* U, int tlen, hipStream_t s) {
+    Geom g{op->dims[0], op->dims[1], op->dims[2], op->dims[3], op->vol};
+    tlen = std::max(1, std::min(tlen, g.T));
+    const int nseg = (g.T + tlen - 1) / tlen;
+    const int ncg = (k + NC - 1) / NC;
+    const int per_xcd = (ncg * nseg * g.Z + kXcd - 1) / kXcd;
+    dim3 grid((unsigned)(per_xcd * kXcd));
+    const R kap = (R)op->kappa;
+    const R ts = op->antiperiodic ? R(-1) : R(1);
+#define SC_WT(DAG, MODE)                                                                                   \
+    hipLaunchKernelGGL((k_wilson_tm<R, DAG, MODE, NC, CGMINOR>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,      \
+                       2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd);
+    switch (which) {
+        case 0: SC_WT(false, 0) break;
+        case 1: SC_WT(true, 0) break;
+        case 2: SC_WT(false, 1) break;
+        default: SC_WT(true, 1) break;
+    }
+#undef SC_WT
+}
+
+template <typename R>
+static void wilson_launch_dir(const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k,
+                              const R* U, hipStream_t s) {
+    Geom g{op->dims[0], op->dims[1], op->dims[2], op->dims[3], op->vol};
+    const int ntile = (int)((g.V + 63) / 64);
+    const int per_xcd = (ntile * k + kXcd - 1) / kXcd;
+    dim3 grid((unsigned)(per_xcd * kXcd));
+    const R kap = (R)op->kappa;
+    const R ts = op->antiperiodic ? R(-1) : R(1);
+#define SC_WD(DAG, MODE)                                                                                         \
+    hipLaunchKernelGGL((k_wilson_dir<R, DAG, MODE>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X, 2 * ldx, U, g, kap, \
+                       ts, k, ntile, per_xcd);
+    switch (which) {
+        case 0: SC_WD(false, 0) break;
+        case 1: SC_WD(true, 0) break;
+        case 2: SC_WD(false, 1) break;
+        default: SC_WD(true, 1) break;
+    }
+#undef SC_WD
+}
+
+template <typename R, int NC, bool ROLLED>
 static void wilson_launch_v(const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k, const R* U,
-                            hipStream_t s) {
+                            int chunk, int order, hipStream_t s) {
     Geom g{op->dims[0], op->dims[1], op->dims[2], op->dims[3], op->vol};
     const int ntiles = (int)((g.V + kBlock - 1) / kBlock);
     const int ncg = (k + NC - 1) / NC;
+    const int G = chunk_groups(chunk, ncg);
+    const int zb = (order == 1 && zblock_ok(op)) ? kZBlock : 1;
     const int per_xcd = (ntiles * ncg + kXcd - 1) / kXcd;
     dim3 grid((unsigned)(per_xcd * kXcd));
     const R kap = (R)op->kappa;
@@ -380,11 +757,11 @@ static void wilson_launch_v(const sc_op* op, int which, const R* X, int64_t ldx,
     // ld arguments are in reals (2 per complex element)
 #define SC_WL(DAG, MODE)                                                                                       \
     if (ROLLED)                                                                                                \
-        hipLaunchKernelGGL((k_wilson_r<R, DAG, MODE, NC, 1, CM>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,     \
-                           2 * ldx, U, g, kap, ts, k, ncg, ntiles, per_xcd);                                   \
+        hipLaunchKernelGGL((k_wilson_r<R, DAG, MODE, NC, 1>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,         \
+                           2 * ldx, U, g, kap, ts, k, ncg, ntiles, per_xcd, G, zb);                            \
     else                                                                                                       \
-        hipLaunchKernelGGL((k_wilson<R, DAG, MODE, NC, 1, false, CM>), grid, dim3(kBlock), 0, s, Y, 2 * ldy,   \
-                           X, 2 * ldx, U, g, kap, ts, k, ncg, ntiles, per_xcd);
+        hipLaunchKernelGGL((k_wilson<R, DAG, MODE, NC, 1, false>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,    \
+                           2 * ldx, U, g, kap, ts, k, ncg, ntiles, per_xcd, G, zb);
     switch (which) {
         case 0: SC_WL(false, 0) break;
         case 1: SC_WL(true, 0) break;
@@ -394,20 +771,61 @@ static void wilson_launch_v(const sc_op* op, int which, const R* X, int64_t ldx,
 #undef SC_WL
 }
 
-// FP64 has no 4-column shape (it would spill): those ids fall back to 2 columns
+static int default_variant(bool single, int k) {
+    return (k <= 1 ? WS_ROLLED_1 : (single ? WS_ROLLED_2 : WS_ROLLED_1)) * kChunks;
+}
+
+// FP64 has no 4-column shape (it would spill): it uses 2 columns there
 template <typename R>
 static void wilson_launch_variant(int v, const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k,
                                   const R* U, hipStream_t s) {
-    constexpr int N4 = sizeof(R) == 4 ? 4 : 2;
-    switch (v) {
-        case WV_UNROLLED_1: wilson_launch_v<R, 1, false, false>(op, which, X, ldx, Y, ldy, k, U, s); break;
-        case WV_ROLLED_1: wilson_launch_v<R, 1, true, false>(op, which, X, ldx, Y, ldy, k, U, s); break;
-        case WV_ROLLED_2: wilson_launch_v<R, 2, true, false>(op, which, X, ldx, Y, ldy, k, U, s); break;
-        case WV_ROLLED_4: wilson_launch_v<R, N4, true, false>(op, which, X, ldx, Y, ldy, k, U, s); break;
-        case WV_ROLLED_1_CM: wilson_launch_v<R, 1, true, true>(op, which, X, ldx, Y, ldy, k, U, s); break;
-        case WV_ROLLED_2_CM: wilson_launch_v<R, 2, true, true>(op, which, X, ldx, Y, ldy, k, U, s); break;
-        default: wilson_launch_v<R, N4, true, true>(op, which, X, ldx, Y, ldy, k, U, s); break;
+    if (v == WV_DIR) {
+        wilson_launch_dir<R>(op, which, X, ldx, Y, ldy, k, U, s);
+        return;
     }
+    if (v >= WV_TILED && !tmarch_ok(op)) v = default_variant(sizeof(R) == 4, k);  // not for this lattice
+    if (v >= WV_TILED) {
+        const int i = v - WV_TILED, tlen = i % 3 == 0 ? 4 : (i % 3 == 1 ? 8 : 16);
+        const int form = (i / 3) % 2;       // 0: 1 column per thread, 1: 2
+        const bool cgminor = i >= 6;
+        constexpr int N2 = sizeof(R) == 4 ? 2 : 1;  // FP64 with 2 columns would spill
+        if (form == 0) {
+            if (cgminor) wilson_launch_tm<R, 1, true>(op, which, X, ldx, Y, ldy, k, U, tlen, s);
+            else wilson_launch_tm<R, 1, false>(op, which, X, ldx, Y, ldy, k, U, tlen, s);
+        } else {
+            if (cgminor) wilson_launch_tm<R, N2, true>(op, which, X, ldx, Y, ldy, k, U, tlen, s);
+            else wilson_launch_tm<R, N2, false>(op, which, X, ldx, Y, ldy, k, U, tlen, s);
+        }
+        return;
+    }
+    constexpr int N4 = sizeof(R) == 4 ? 4 : 2;
+    const int chunk = v % kChunks, order = v / (WS_COUNT * kChunks);
+    switch ((v / kChunks) % WS_COUNT) {
+        case WS_UNROLLED_1: wilson_launch_v<R, 1, false>(op, which, X, ldx, Y, ldy, k, U, chunk, order, s); break;
+        case WS_ROLLED_1: wilson_launch_v<R, 1, true>(op, which, X, ldx, Y, ldy, k, U, chunk, order, s); break;
+        case WS_ROLLED_2: wilson_launch_v<R, 2, true>(op, which, X, ldx, Y, ldy, k, U, chunk, order, s); break;
+        default: wilson_launch_v<R, N4, true>(op, which, X, ldx, Y, ldy, k, U, chunk, order, s); break;
+    }
+}
+
+// variants worth timing for this lattice, precision and column count
+static bool variant_applies(const sc_op* op, int v, bool single, int k) {
+    if (v == WV_DIR) return k <= 4;
+    if (v >= WV_TILED) {
+        const int i = v - WV_TILED;
+        if (!tmarch_ok(op)) return false;
+        if ((i / 3) % 2 == 1 && (k == 1 || !single)) return false;  // 2 columns: FP64 would spill
+        if (i >= 6 && k == 1) return false;                           // one column group: orders agree
+        return true;
+    }
+    const int shape = (v / kChunks) % WS_COUNT, chunk = v % kChunks, order = v / (WS_COUNT * kChunks);
+    if (order == 1 && !zblock_ok(op)) return false;  // same as site order
+    if (!single && shape == WS_ROLLED_4) return false;  // same as 2 columns in FP64
+    const int nc = shape == WS_ROLLED_4 ? 4 : (shape == WS_ROLLED_2 ? 2 : 1);
+    if (nc > 1 && k == 1) return false;
+    const int ncg = (k + nc - 1) / nc;
+    if (chunk != 0 && chunk_groups(chunk, ncg) == ncg) return false;  // same order as chunk 0
+    return true;
 }
 
 namespace {
@@ -429,7 +847,7 @@ std::mutex g_tune_mu;
 std::map<TuneKey, TuneRec> g_tune;
 int g_tune_mode = -1;  // -1: read SEEDCG_TUNE on first use; 0: defaults only; 1: tune
 
-int default_variant(bool single, int k) { return k <= 1 ? WV_ROLLED_1 : (single ? WV_ROLLED_2 : WV_ROLLED_1); }
+
 }  // namespace
 
 // Time every variant on the caller's buffers (the output is rewritten by the
@@ -448,8 +866,7 @@ static TuneRec tune_variants(const sc_op* op, int which, const R* X, int64_t ldx
     float best = 1e30f;
     for (int v = 0; v < WV_COUNT; ++v) {
         rec.us[v] = -1.0f;
-        if (sizeof(R) == 8 && (v == WV_ROLLED_4 || v == WV_ROLLED_4_CM)) continue;  // FP64 has no 4-column shape
-        if (k == 1 && v >= WV_ROLLED_1_CM) continue;  // order is irrelevant for one column
+        if (!variant_applies(op, v, sizeof(R) == 4, k)) continue;
         wilson_launch_variant<R>(v, op, which, X, ldx, Y, ldy, k, U, s);  // warm
         hipEventRecord(e0, s);
         for (int r = 0; r < 3; ++r) wilson_launch_variant<R>(v, op, which, X, ldx, Y, ldy, k, U, s);
@@ -488,6 +905,10 @@ static int choose_variant(const sc_op* op, int which, const R* X, int64_t ldx, R
 }
 
 sc_status wilson_tune_pin(const sc_op* op, bool single, int k, int variant) {
+    if (variant >= WV_TILED && variant < WV_DIR && !tmarch_ok(op)) {
+        set_error("wilson_tune_set: the t-march shapes need an xy-plane of exactly 256 sites");
+        return SC_ERR_ARG;
+    }
     TuneKey key{{op->dims[0], op->dims[1], op->dims[2], op->dims[3]}, single ? 1 : 0, k};
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (variant < 0) {
@@ -524,7 +945,8 @@ static sc_status wilson_launch(const sc_op* op, int which, const R* X, int64_t l
     // per site and column (+48 for psi - kappa H psi)
     const double bytes = (48.0 * k + 72.0) * sizeof(R) * (double)op->vol;
     const double flops = (which < 2 ? 1368.0 : 1320.0) * k * (double)op->vol;
-    TimerScope ts_(sizeof(R) == 4 ? TC_WILSON_F32 : TC_WILSON_F64, s, bytes, flops);
+    const int cls = sizeof(R) == 4 ? (k == 1 ? TC_WILSON_F32 : TC_WILSON_F32_K) : (k == 1 ? TC_WILSON_F64 : TC_WILSON_F64_K);
+    TimerScope ts_(cls, s, bytes, flops);
     wilson_launch_variant<R>(v, op, which, X, ldx, Y, ldy, k, U, s);
     SC_LAUNCH_CHECK();
     return SC_OK;

@@ -6,11 +6,13 @@
 namespace sc {
 
 enum TimerClass {
-    TC_WILSON_F32 = 0,  // one Wilson stencil pass, FP32
-    TC_WILSON_F64 = 1,  // one Wilson stencil pass, FP64
-    TC_GEMM_CN = 2,     // G = V^H W
-    TC_GEMM_NN = 3,     // X += V Y
-    TC_COUNT = 4
+    TC_WILSON_F32 = 0,    // one Wilson stencil pass, FP32, one column
+    TC_WILSON_F64 = 1,    // one Wilson stencil pass, FP64, one column
+    TC_GEMM_CN = 2,       // G = V^H W
+    TC_GEMM_NN = 3,       // X += V Y
+    TC_WILSON_F32_K = 4,  // one Wilson stencil pass, FP32, several columns
+    TC_WILSON_F64_K = 5,  // one Wilson stencil pass, FP64, several columns
+    TC_COUNT = 6
 };
 
 bool timer_on();

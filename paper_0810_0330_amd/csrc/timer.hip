@@ -1,7 +1,10 @@
 // Optional per-kernel-class timing with HIP events, for benchmarks: when
-// enabled, every launch of an instrumented kernel is bracketed by two events
-// on the stream it runs on, and its algorithmic bytes and flops are recorded.
-// Disabled (the default), the scopes cost one branch.
+// enabled, a sample of the launches of each instrumented class (one in
+// `every`, picked by a hash of the class's launch counter so that periodic
+// launch patterns do not alias) is bracketed by two events on the stream it
+// runs on, and its algorithmic bytes and flops are recorded.  An event pair
+// costs a few microseconds of queue time, so sampling keeps the timed run
+// close to an untimed one.  Disabled (the default), the scopes cost one branch.
 #include <mutex>
 #include <vector>
 
@@ -17,9 +20,20 @@ struct Rec {
 };
 std::mutex g_mu;
 bool g_on = false;
+int g_every = 1;
+uint64_t g_count[TC_COUNT];
 std::vector<Rec> g_recs;      // recorded this session
 std::vector<hipEvent_t> g_pool;  // reusable events
 size_t g_pool_used = 0;
+
+// splitmix64 finaliser of (class, launch counter)
+bool sampled(int cls) {
+    uint64_t z = (g_count[cls]++) * 0x9E3779B97F4A7C15ull + (uint64_t)cls * 0xD1B54A32D192ED03ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return g_every <= 1 || z % (uint64_t)g_every == 0;
+}
 
 hipEvent_t take_event() {
     if (g_pool_used == g_pool.size()) {
@@ -39,6 +53,7 @@ TimerScope::TimerScope(int cls, hipStream_t s, double bytes, double flops)
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;  // not in graphs
     std::lock_guard<std::mutex> lk(g_mu);
+    if (cls < 0 || cls >= TC_COUNT || !sampled(cls)) return;
     a_ = take_event();
     if (a_) hipEventRecord((hipEvent_t)a_, s_);
 }
@@ -52,11 +67,13 @@ TimerScope::~TimerScope() {
     g_recs.push_back({(hipEvent_t)a_, b, cls_, bytes_, flops_});
 }
 
-sc_status timer_enable(int on) {
+sc_status timer_enable(int every) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_recs.clear();
     g_pool_used = 0;
-    g_on = on != 0;
+    g_on = every > 0;
+    g_every = every > 0 ? every : 1;
+    for (auto& c : g_count) c = 0;
     return SC_OK;
 }
 

@@ -89,3 +89,42 @@ def test_op_create_info_destroy_on_host(lib):
     assert lib.sc_project(ctypes.c_int64(512), p, ctypes.c_int64(512), 1, 10, p, p, 0, p, ctypes.c_int64(512), 1, p,
                           ctypes.c_int64(512), p, ctypes.c_size_t(1 << 30), None) == -1
     assert lib.sc_op_destroy(out) == 0
+
+
+def test_timer_host_side(lib):
+    # enabling, reading with no recorded launches and the class check need no device
+    ms, nl, by, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    assert lib.sc_timer_enable(8) == 0
+    for cls in range(6):
+        assert lib.sc_timer_read(cls, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(by), ctypes.byref(fl)) == 0
+        assert nl.value == 0 and ms.value == 0.0
+    assert lib.sc_timer_read(6, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(by), ctypes.byref(fl)) == -1
+    assert lib.sc_timer_read(0, None, ctypes.byref(nl), ctypes.byref(by), ctypes.byref(fl)) == -1
+    assert lib.sc_timer_enable(0) == 0
+
+
+def test_variant_count_matches_header():
+    from paper_0810_0330_amd import api
+    m = re.search(r"#define\s+SC_WILSON_VARIANTS\s+(\d+)", open(HEADER).read())
+    assert m and int(m.group(1)) == api.WILSON_VARIANTS
+
+
+def test_tune_set_refuses_tmarch_on_other_lattices(lib):
+    # pinning is host-only; the t-march shapes need an xy-plane of 256 sites
+    out = ctypes.c_void_p()
+    dims = (ctypes.c_int * 4)(4, 4, 4, 4)
+    assert lib.sc_op_wilson_normal(dims, ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_double(0.12), 1,
+                                   ctypes.byref(out)) == 0
+    assert lib.sc_wilson_tune_set(out, 1, 3, 32) == -1
+    assert b"256" in lib.sc_last_error()
+    assert lib.sc_wilson_tune_set(out, 1, 3, 31) == 0
+    assert lib.sc_wilson_tune_set(out, 1, 3, 45) == -1
+    assert lib.sc_wilson_tune_set(out, 1, 3, 44) == 0
+    assert lib.sc_wilson_tune_set(out, 1, 3, -1) == 0
+    assert lib.sc_op_destroy(out) == 0
+    dims = (ctypes.c_int * 4)(16, 16, 2, 2)
+    assert lib.sc_op_wilson_normal(dims, ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_double(0.12), 1,
+                                   ctypes.byref(out)) == 0
+    assert lib.sc_wilson_tune_set(out, 1, 3, 43) == 0
+    assert lib.sc_wilson_tune_set(out, 1, 3, -1) == 0
+    assert lib.sc_op_destroy(out) == 0

@@ -159,11 +159,16 @@ def test_wilson_passes(dims):
     assert _rel(yn, refn) < 1e-13
 
 
-@pytest.mark.parametrize("k", [1, 3, 5])
-def test_wilson_every_launch_shape(k):
-    # each stencil variant the autotuner may pick, pinned in turn, on a ragged
-    # lattice (volume not a multiple of the 256-site tile) and k columns
-    dims = (3, 5, 4, 6)
+@pytest.mark.parametrize("dims,k", [((3, 5, 4, 6), 1), ((3, 5, 4, 6), 3), ((3, 5, 4, 6), 5), ((3, 5, 4, 6), 9),
+                                    ((16, 16, 8, 9), 1), ((16, 16, 8, 9), 5)])
+def test_wilson_every_launch_shape(dims, k):
+    # each stencil variant the autotuner may pick, pinned in turn, and k
+    # columns (k = 5 and 9 leave partial column chunks): on a ragged lattice
+    # (volume not a multiple of the 256-site tile), and on one whose time
+    # slices hold 8 whole tiles, where the z-blocked tile order applies, and
+    # whose xy-plane is one tile, where the t-march form applies (T = 9: the
+    # last time segment is partial); outputs start as NaN so that a work item
+    # the launch skips cannot pass on stale memory
     _say("wilson launch shapes", dims, "k", k)
     U, op = _wilson(dims, cfg=8)
     x = synth.complex_gaussian(op.n, k, synth.rng(5, 2))
@@ -172,12 +177,18 @@ def test_wilson_every_launch_shape(k):
     ref = {w: np.stack([f(fl).reshape(-1) for fl in fields], axis=1) for w, f in [
         (0, lambda fl: ops.wilson_D(fl, U, 0.12)), (1, lambda fl: ops.wilson_Ddag(fl, U, 0.12)),
         (2, lambda fl: ops.wilson_hop(fl, U)), (3, lambda fl: ops.wilson_hop(fl, U, dagger=True))]}
-    for v in range(7):
+    tmarch = dims[0] * dims[1] == 256
+    for v in range(api.WILSON_VARIANTS):
+        if 32 <= v < 44 and not tmarch:  # the t-march shapes need a 256-site xy-plane: refused
+            with pytest.raises(api.SeedCGError):
+                op.tune_set(k, v, single=True)
+            continue
         for single in (False, True):
             op.tune_set(k, v, single=single)
             for which in range(4):
                 Xin = X.to(torch.complex64) if single else X
-                y = _to_nat(op.dslash(Xin, which, single=single))
+                out = torch.full_like(Xin, complex(float("nan"), float("nan")))
+                y = _to_nat(op.dslash(Xin, which, single=single, out=out))
                 assert _rel(y, ref[which]) < (4e-6 if single else 1e-13), (v, single, which)
     op.tune_set(k, -1, single=True)
     op.tune_set(k, -1, single=False)
@@ -352,3 +363,28 @@ def test_zero_rhs_seed():
     basis = api.seed_lanczos(op, torch.zeros(64, dtype=torch.float64, device=DEV), 10, 1)
     assert basis.status == 2 and basis.m_done == 0
     assert float(basis.x1.abs().max()) == 0.0
+
+
+def test_timer_sampling():
+    _say("event timer: full and sampled recording")
+    dims = (8, 8, 8, 8)
+    U, op = _wilson(dims)
+    X = _to_lib(synth.complex_gaussian(op.n, 3, synth.rng(5, 1))).to(torch.complex64)
+    x1 = X[:1].contiguous()
+    vol = 8 ** 4
+    for every, lo, hi in [(1, 64, 64), (8, 1, 20)]:
+        api.timer_enable(True, every=every)
+        for _ in range(32):
+            op.apply(x1, single=True)     # two one-column FP32 passes
+        op.apply(X, single=True)          # two three-column FP32 passes (timed only when every = 1)
+        torch.cuda.synchronize()
+        t = api.timer_read()
+        api.timer_enable(False)
+        k1 = t["wilson_f32_k1"]
+        assert lo <= k1["launches"] <= hi, (every, k1)
+        assert k1["ms"] > 0.0
+        assert k1["bytes"] == pytest.approx(k1["launches"] * (48 + 72) * 4 * vol)
+        if every == 1:
+            assert t["wilson_f32_kn"]["launches"] == 2
+            assert t["wilson_f32_kn"]["bytes"] == pytest.approx(2 * (48 * 3 + 72) * 4 * vol)
+        assert t["wilson_f64_k1"]["launches"] == 0
