@@ -231,10 +231,11 @@ sc_status sc_solve_cg(const sc_op* op, int mixed, const void* B_dev, int64_t ldb
 /* ------------------------------------------------------------------ timing
  * Optional event timing of the library's main kernels, for benchmarks (not
  * part of the method).  sc_timer_enable(every) with every >= 1 clears earlier
- * records and, from then on, brackets one launch in `every` of each class
- * below (a fixed pseudo-random sample; every = 1 times all of them) with two
- * HIP events on the launch's own stream, recording that launch's algorithmic
- * bytes and flops; sc_timer_enable(0) stops recording.  Launches inside a
+ * records and, from then on, brackets one launch in `every` of each stencil
+ * class below (a fixed pseudo-random sample; every = 1 times all of them) and
+ * every launch of classes 2 and 3 with two HIP events on the launch's own
+ * stream, recording that launch's algorithmic bytes and flops;
+ * sc_timer_enable(0) stops recording.  Launches inside a
  * stream capture are never timed.  sc_timer_read(cls, ...) waits for the
  * recorded events and returns, for class cls, the summed kernel time (ms),
  * the number of timed launches and their summed algorithmic bytes and flops:

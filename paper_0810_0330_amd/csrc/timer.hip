@@ -1,8 +1,9 @@
 // Optional per-kernel-class timing with HIP events, for benchmarks: when
-// enabled, a sample of the launches of each instrumented class (one in
-// `every`, picked by a hash of the class's launch counter so that periodic
-// launch patterns do not alias) is bracketed by two events on the stream it
-// runs on, and its algorithmic bytes and flops are recorded.  An event pair
+// enabled, a sample of the launches of each stencil class (one in `every`,
+// picked by a hash of the class's launch counter so that periodic launch
+// patterns do not alias) and every contraction launch is bracketed by two
+// events on the stream it runs on, and its algorithmic bytes and flops are
+// recorded.  An event pair
 // costs a few microseconds of queue time, so sampling keeps the timed run
 // close to an untimed one.  Disabled (the default), the scopes cost one branch.
 #include <mutex>
@@ -26,8 +27,10 @@ std::vector<Rec> g_recs;      // recorded this session
 std::vector<hipEvent_t> g_pool;  // reusable events
 size_t g_pool_used = 0;
 
-// splitmix64 finaliser of (class, launch counter)
+// splitmix64 finaliser of (class, launch counter); the contraction classes,
+// whose launches last milliseconds, are always timed
 bool sampled(int cls) {
+    if (cls == TC_GEMM_CN || cls == TC_GEMM_NN) return true;
     uint64_t z = (g_count[cls]++) * 0x9E3779B97F4A7C15ull + (uint64_t)cls * 0xD1B54A32D192ED03ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
