@@ -190,65 +190,91 @@ __global__ __launch_bounds__(kBlock) void k_nn_mfma(const VR* __restrict__ V, in
 }
 
 // ---------------------------------------------------------------- G = V^H W, N <= 2 (reorthogonalization)
-// Bandwidth kernel: each thread keeps RPT rows of the (at most two) W columns
-// in registers and streams the basis columns once; per basis column the
-// block's sum is formed by wave shuffles and a 4-entry LDS reduction.
-constexpr int kSmallRPT = 8;     // rows per thread
+// Bandwidth kernel: a block owns a range of rows, in sub-chunks of
+// kBlock * kSmallRPT rows, and 64 basis columns.  Per sub-chunk each thread
+// holds its kSmallRPT rows of the (at most two) W columns in registers and
+// streams the basis columns: all loads of a column are issued before they are
+// used and the next column's loads are issued before the current column is
+// reduced.  The four sums of a column (re, im for two W columns) are reduced
+// over the wave by a reduce-scatter (7 exchanges instead of 24) and added to a
+// block-private LDS slot; one partial per block and output is written at the
+// end.  Rows past n are read from row n - 1 with a zero weight, so no lane
+// branches.
+constexpr int kSmallRPT = 8;     // rows per thread per sub-chunk
 constexpr int kSmallCols = 64;   // basis columns per block
+constexpr int kSmallSub = kBlock * kSmallRPT;
+
+// v0..v3: this lane's four partial sums.  On return lanes 0, 16, 32, 48 hold
+// the wave totals of sums 0, 1, 2, 3 (lane l: sum 2 * (l >= 32) + ((l >> 4) & 1)).
+__device__ __forceinline__ double reduce_scatter4(double v0, double v1, double v2, double v3) {
+    const int lane = threadIdx.x & 63;
+    const bool hi32 = lane >= 32;
+    // step 1 (xor 32): keep sums {2, 3} on the upper half, {0, 1} on the lower
+    const double s0 = hi32 ? v0 : v2, s1 = hi32 ? v1 : v3;  // what the partner keeps
+    const double k0 = hi32 ? v2 : v0, k1 = hi32 ? v3 : v1;
+    const double a = k0 + __shfl_xor(s0, 32, 64);
+    const double b = k1 + __shfl_xor(s1, 32, 64);
+    // step 2 (xor 16): keep the second of the pair on odd 16-lane groups
+    const bool hi16 = (lane >> 4) & 1;
+    double t = (hi16 ? b : a) + __shfl_xor(hi16 ? a : b, 16, 64);
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    return t;
+}
 
 template <typename VR, typename WR>
 __global__ __launch_bounds__(kBlock) void k_cn_small(const VR* __restrict__ V, int64_t ldv, int64_t n, int M,
                                                      ColPtrs<const void> W, int N, double* __restrict__ part,
-                                                     const int* halt) {
+                                                     int64_t rows_per_block, const int* halt) {
     if (halt && *halt) return;
     __shared__ double red[kSmallCols][kWaves][4];
-    const int64_t rbase = (int64_t)blockIdx.x * kBlock * kSmallRPT;
     const int a0 = blockIdx.y * kSmallCols;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    cplx<double> w0[kSmallRPT], w1[kSmallRPT];
-    bool ok[kSmallRPT];
-#pragma unroll
-    for (int t = 0; t < kSmallRPT; ++t) {
-        const int64_t r = rbase + threadIdx.x + (int64_t)t * kBlock;
-        ok[t] = r < n;
-        w0[t] = w1[t] = cplx<double>{0.0, 0.0};
-        if (ok[t]) {
-            const cplx<WR> c0 = ld2((const WR*)W.p[0], r);
-            w0[t] = {(double)c0.re, (double)c0.im};
-            if (N > 1) {
-                const cplx<WR> c1 = ld2((const WR*)W.p[1], r);
-                w1[t] = {(double)c1.re, (double)c1.im};
-            }
-        }
-    }
     const int na = min(kSmallCols, M - a0);
-    for (int aa = 0; aa < na; ++aa) {
-        const VR* col = V + 2 * ((int64_t)(a0 + aa) * ldv);
-        double s0r = 0.0, s0i = 0.0, s1r = 0.0, s1i = 0.0;
+    for (int e = threadIdx.x; e < kSmallCols * kWaves * 4; e += kBlock) (&red[0][0][0])[e] = 0.0;
+    __syncthreads();
+    const int64_t rb0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t rb1 = min(n, rb0 + rows_per_block);
+    const WR* W0 = (const WR*)W.p[0];
+    const WR* W1 = (const WR*)W.p[N > 1 ? 1 : 0];
+    const double w1on = N > 1 ? 1.0 : 0.0;
+    for (int64_t rbase = rb0; rbase < rb1; rbase += kSmallSub) {
+        int64_t rr[kSmallRPT];
+        cplx<double> w0[kSmallRPT], w1[kSmallRPT];
 #pragma unroll
         for (int t = 0; t < kSmallRPT; ++t) {
-            if (!ok[t]) continue;
             const int64_t r = rbase + threadIdx.x + (int64_t)t * kBlock;
-            const cplx<VR> c = ld2(col, r);
-            const double vr = (double)c.re, vi = (double)c.im;
-            s0r += vr * w0[t].re + vi * w0[t].im;   // conj(v) w
-            s0i += vr * w0[t].im - vi * w0[t].re;
-            s1r += vr * w1[t].re + vi * w1[t].im;
-            s1i += vr * w1[t].im - vi * w1[t].re;
+            const double on = r < rb1 ? 1.0 : 0.0;
+            rr[t] = r < rb1 ? r : rb1 - 1;
+            const cplx<WR> c0 = ld2(W0, rr[t]);
+            const cplx<WR> c1 = ld2(W1, rr[t]);
+            w0[t] = {on * (double)c0.re, on * (double)c0.im};
+            w1[t] = {on * w1on * (double)c1.re, on * w1on * (double)c1.im};
         }
-        s0r = wave_sum(s0r);
-        s0i = wave_sum(s0i);
-        s1r = wave_sum(s1r);
-        s1i = wave_sum(s1i);
-        if (lane == 0) {
-            red[aa][wv][0] = s0r;
-            red[aa][wv][1] = s0i;
-            red[aa][wv][2] = s1r;
-            red[aa][wv][3] = s1i;
+        cplx<VR> vb[kSmallRPT], vn[kSmallRPT];
+#pragma unroll
+        for (int t = 0; t < kSmallRPT; ++t) vb[t] = ld2(V + 2 * ((int64_t)a0 * ldv), rr[t]);
+        for (int aa = 0; aa < na; ++aa) {
+            const int an = aa + 1 < na ? aa + 1 : aa;  // prefetch the next column
+#pragma unroll
+            for (int t = 0; t < kSmallRPT; ++t) vn[t] = ld2(V + 2 * ((int64_t)(a0 + an) * ldv), rr[t]);
+            double s0r = 0.0, s0i = 0.0, s1r = 0.0, s1i = 0.0;
+#pragma unroll
+            for (int t = 0; t < kSmallRPT; ++t) {
+                const double vr = (double)vb[t].re, vi = (double)vb[t].im;
+                s0r += vr * w0[t].re + vi * w0[t].im;  // conj(v) w
+                s0i += vr * w0[t].im - vi * w0[t].re;
+                s1r += vr * w1[t].re + vi * w1[t].im;
+                s1i += vr * w1[t].im - vi * w1[t].re;
+            }
+            const double tot = reduce_scatter4(s0r, s0i, s1r, s1i);
+            if ((lane & 15) == 0) red[aa][wv][lane >> 4] += tot;
+#pragma unroll
+            for (int t = 0; t < kSmallRPT; ++t) vb[t] = vn[t];
         }
     }
     __syncthreads();
-    // thread -> (column, output): 64 columns x (N complex) values
+    // one partial per (block, column, output), summed over the waves in order
     for (int e = threadIdx.x; e < na * 2 * N; e += kBlock) {
         const int aa = e / (2 * N), q = e % (2 * N);
         double v = 0.0;
@@ -318,18 +344,27 @@ __global__ __launch_bounds__(kBlock) void k_cn_partial(const VR* __restrict__ V,
     }
 }
 
-__global__ void k_cn_reduce(const double* __restrict__ part, int nchunk, int64_t nout /* doubles */,
-                            double* __restrict__ G, bool cplx, const int* halt) {
+// G[o] = sum over chunks of the partials: a block takes 64 outputs, its 4
+// waves sum interleaved quarters of the chunks, and the quarters are added in
+// a fixed order (deterministic).
+__global__ __launch_bounds__(kBlock) void k_cn_reduce(const double* __restrict__ part, int nchunk,
+                                                      int64_t nout /* doubles */, double* __restrict__ G, bool cplx,
+                                                      const int* halt) {
     if (halt && *halt) return;
-    const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (o >= nout) return;
+    __shared__ double sh[kWaves][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t o = blockIdx.x * (int64_t)64 + lane;
     double s = 0.0;
-    if (cplx) {
-        for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * nout + o];
-    } else {  // partials keep (re, im) pairs; the real result is the re part
-        for (int c = 0; c < nchunk; ++c) s += part[2 * ((int64_t)c * nout + o)];
+    if (o < nout) {
+        if (cplx) {
+            for (int c = wv; c < nchunk; c += kWaves) s += part[(int64_t)c * nout + o];
+        } else {  // partials keep (re, im) pairs; the real result is the re part
+            for (int c = wv; c < nchunk; c += kWaves) s += part[2 * ((int64_t)c * nout + o)];
+        }
     }
-    G[o] = s;
+    sh[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && o < nout) G[o] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
 }
 
 struct CnPlan {
@@ -341,10 +376,14 @@ struct CnPlan {
 // real ones the vector kernel.
 static CnPlan cn_plan(int64_t n, int M, int N, bool cplx = false) {
     CnPlan p;
-    if (cplx && N <= 2) {  // k_cn_small: fixed row chunks of kBlock * kSmallRPT rows
+    if (cplx && N <= 2) {  // k_cn_small: row ranges of whole sub-chunks, enough blocks to fill the chip
         p.tm = kSmallCols;
-        p.kt = kBlock * kSmallRPT;
-        p.rows = p.kt;
+        p.kt = kSmallSub;
+        const int mt = (M + kSmallCols - 1) / kSmallCols;
+        const int64_t maxchunk = std::max<int64_t>(1, (n + kSmallSub - 1) / kSmallSub);
+        const int64_t want = std::min<int64_t>(maxchunk, std::max<int64_t>(64, (2048 + mt - 1) / mt));
+        const int64_t subs = (maxchunk + want - 1) / want;  // sub-chunks per block
+        p.rows = subs * kSmallSub;
         p.nchunk = (int)std::max<int64_t>(1, (n + p.rows - 1) / p.rows);
         return p;
     }
@@ -390,7 +429,7 @@ static void cn_mfma_launch(const CnPlan& p, const VR* V, int64_t ldv, int64_t n,
                            int N, double* part, const int* halt, hipStream_t s) {
     dim3 grid((unsigned)p.nchunk, (unsigned)((M + 63) / 64));
     if (N <= 2)
-        hipLaunchKernelGGL((k_cn_small<VR, WR>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, halt);
+        hipLaunchKernelGGL((k_cn_small<VR, WR>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
     else if (N <= 16)
         hipLaunchKernelGGL((k_cn_mfma<VR, WR, 1>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
     else
@@ -422,7 +461,7 @@ sc_status gemm_cn(bool cplx, bool vsingle, const void* V, int64_t ldv, int64_t n
 #undef SC_CNM
     SC_LAUNCH_CHECK();
     const int64_t nout = (int64_t)M * N * (cplx ? 2 : 1);
-    hipLaunchKernelGGL(k_cn_reduce, dim3((unsigned)((nout + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, part,
+    hipLaunchKernelGGL(k_cn_reduce, dim3((unsigned)((nout + 63) / 64)), dim3(kBlock), 0, s, part,
                        p.nchunk, cplx ? nout : (int64_t)M * N, G, cplx, halt);
     SC_LAUNCH_CHECK();
     return SC_OK;
