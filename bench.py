@@ -51,6 +51,12 @@ def parse():
                     help="time one kernel in isolation on the workload's lattice (for profilers)")
     ap.add_argument("--k", type=int, default=1, help="columns per launch in --micro mode")
     ap.add_argument("--reps", type=int, default=20, help="launches in --micro mode")
+    ap.add_argument("--sweep-freq", default=None,
+                    help="comma-separated reorthogonalization frequencies (0 = none): time the seed phase and the "
+                         "whole seeded solve at each (Section 4, Table 4.1 analogue) instead of the benchmark")
+    ap.add_argument("--related", type=int, default=None, metavar="NRHS",
+                    help="time single seeding of NRHS related right-hand sides b^j = b^(j-1) + 0.2^(j-1) u^j "
+                         "(Section 2.3, Example 3) on the workload's lattice instead of the benchmark")
     ap.add_argument("--variant", type=int, default=None,
                     help="--micro wilson_*: pin this stencil launch shape instead of autotuning")
     return ap.parse_args()
@@ -106,6 +112,85 @@ def micro(args, w):
     api.timer_enable(False)
     if args.micro.startswith("wilson"):
         res["variant"], res["tune_us"] = op.tune_info(k, single=single)
+    print(json.dumps(res), flush=True)
+
+
+def sweep_freq(args, w):
+    """Seed-phase and total time of the seeded solve against the reorthogonalization frequency.
+
+    The paper's Table 4.1 gives, for its QCD problem on a CPU cluster, the time
+    of right-hand side 1 (the seed phase) at frequencies 10, 100, 200, 250 and
+    none; here the same is measured for the benchmark workload, with the CG
+    counts of the other right-hand sides, which show what each frequency buys.
+    """
+    import numpy as np
+    import torch
+
+    from paper_0810_0330_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    inp = synth.make_inputs(w)
+    op = api.Op.wilson(w.dims, torch.from_numpy(api.pack_links(inp["U"])).to(dev), w.kappa)
+    B = torch.from_numpy(api.pack_field(np.ascontiguousarray(inp["B"].T))).to(dev)
+    mixed = w.precision == "mixed"
+    vdt = op.single_dtype if mixed else op.dtype
+    api.seeded_solve(op, B, min(w.m, 50), 10, w.tol, mixed=mixed)  # warm: tuning, allocations
+    rows = []
+    for freq in [int(f) for f in args.sweep_freq.split(",")]:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        basis = api.seed_lanczos(op, B[0], w.m, freq, v_dtype=vdt)
+        torch.cuda.synchronize()
+        t_seed = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        out = api.seeded_solve(op, B, w.m, freq, w.tol, mixed=mixed)
+        torch.cuda.synchronize()
+        t_all = time.perf_counter() - t0
+        assert max(out["relres"]) <= w.tol
+        its = out["iters"]
+        rows.append({"freq": freq, "seed_ms": round(t_seed * 1e3, 2), "solve_ms": round(t_all * 1e3, 2),
+                     "rhs1_iters": its[0], "rhs2_on_iters": its[1:], "m_done": basis.m_done})
+        log(f"[sweep] freq {freq}: seed {t_seed * 1e3:.1f} ms, solve {t_all * 1e3:.1f} ms, iters {its[:4]}...")
+    base = next((r["seed_ms"] for r in rows if r["freq"] == 0), None)
+    for r in rows:
+        r["seed_vs_none"] = round(r["seed_ms"] / base, 3) if base else None
+    print(json.dumps({"sweep": "reorthogonalization frequency", "workload": w.name, "m": w.m, "rows": rows}),
+          flush=True)
+
+
+def related_bench(args, w):
+    """Related right-hand sides on the workload's lattice: the related-RHS
+    driver against single seeding alone and plain per-RHS CG, same inputs."""
+    import numpy as np
+    import torch
+
+    from paper_0810_0330_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    inp = synth.make_inputs(w)
+    op = api.Op.wilson(w.dims, torch.from_numpy(api.pack_links(inp["U"])).to(dev), w.kappa)
+    k = args.related
+    u = synth.z4_noise(op.n, k, synth.rng(w.config_id, 6))
+    Bn = np.zeros_like(u)
+    Bn[:, 0] = u[:, 0]
+    for j in range(1, k):
+        Bn[:, j] = Bn[:, j - 1] + 0.2 ** j * u[:, j]
+    B = torch.from_numpy(api.pack_field(np.ascontiguousarray(Bn.T))).to(dev)
+    mixed = w.precision == "mixed"
+    api.related_rhs_solve(op, B[:2], 50, 10, w.tol, mixed=mixed)  # warm: tuning, allocations
+    res = {"related": k, "workload": w.name, "m": w.m, "freq": w.freq, "tol": w.tol, "precision": w.precision}
+    for name, fn in [("related", lambda: api.related_rhs_solve(op, B, w.m, w.freq, w.tol, mixed=mixed)),
+                     ("single_seed", lambda: api.seeded_solve(op, B, w.m, w.freq, w.tol, mixed=mixed)),
+                     ("plain_f64", lambda: {"iters": [api.solve_cg(op, B[j:j + 1], w.tol)[1][0] for j in range(k)],
+                                            "relres": [0.0]})]:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert max(out["relres"]) <= w.tol
+        res[name] = {"ms": round(dt * 1e3, 2), "rhs_per_s": round(k / dt, 3), "iters": list(out["iters"])}
+        log(f"[related] {name}: {dt * 1e3:.1f} ms, iters {list(out['iters'])}")
     print(json.dumps(res), flush=True)
 
 
@@ -211,6 +296,10 @@ def main():
     w = workload(args)
     if args.micro:
         return micro(args, w)
+    if args.sweep_freq:
+        return sweep_freq(args, w)
+    if args.related:
+        return related_bench(args, w)
     log(f"[bench] workload {w.name}: dims {w.dims} nrhs {w.nrhs} m {w.m} freq {w.freq} tol {w.tol} {w.precision}")
     t0 = time.perf_counter()
     inp = synth.make_inputs(w)

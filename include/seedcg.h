@@ -161,7 +161,8 @@ typedef enum {
     SC_CALL_SEED = 1,
     SC_CALL_PROJECT = 2,
     SC_CALL_CG = 3,
-    SC_CALL_KAPPA_GRAD = 4
+    SC_CALL_KAPPA_GRAD = 4,
+    SC_CALL_RELATED = 5
 } sc_call;
 
 /* Bytes of `work` needed by a call.  k: right-hand sides per call; m: basis
@@ -227,6 +228,28 @@ sc_status sc_project(int64_t n, const void* V_dev, int64_t ldv, sc_dtype v_dtype
 sc_status sc_solve_cg(const sc_op* op, int mixed, const void* B_dev, int64_t ldb, void* X_dev,
                       int64_t ldx, int k, double tol, int maxit, int* iters, double* relres,
                       void* work_dev, size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------ related right-hand sides
+ * Single seeding of related systems (Section 2.3, the algorithm for related
+ * right-hand sides, steps 1-4; Example 3).  System 1 (column 0 of B) is seeded
+ * by the Lanczos phase (m steps, reorthogonalization every reorth_freq; the
+ * basis is complex64 / FP32 when mixed = 1) from X = 0 and finished with CG;
+ * columns 1..k-1 are projected over its basis and their residuals r^i = b^i -
+ * A x^i are formed once.  Then the systems are solved in column order by CG
+ * from their carried guesses, and after system j converges its CG correction
+ * x_cg = x^j - x^j_bcg (x^j_bcg: its guess before CG; zero for system 1)
+ * seeds every later system i: delta = (x_cg^H r^i) / (x_cg^H r^j_bcg),
+ * x^i += delta x_cg, r^i -= delta r^j_bcg (r^j_bcg: the residual system j
+ * started CG from; delta = 0 when the denominator is 0).
+ *   B_dev: n x k (ldb), the op's dtype, read only.  X_dev: n x k (ldx),
+ *   written.  iters (host, k): A-applies per system (system 1 counts its m_done
+ *   seed steps).  relres (host, k): true relative residuals.  m_done (host).
+ * Needs sc_workspace_size(op, SC_CALL_RELATED, k, m, dtype) bytes (dtype: the
+ * op's dtype, or its single-precision dtype when mixed = 1).  Returns SC_OK,
+ * SC_NOT_CONVERGED, SC_BREAKDOWN (seed phase stopped early), or an error. */
+sc_status sc_related_solve(const sc_op* op, int mixed, const void* B_dev, int64_t ldb, void* X_dev,
+                           int64_t ldx, int k, int m, int reorth_freq, double tol, int maxit, int* iters,
+                           double* relres, int* m_done, void* work_dev, size_t work_bytes, void* stream);
 
 /* ------------------------------------------------------------------ timing
  * Optional event timing of the library's main kernels, for benchmarks (not

@@ -27,7 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libseedcg.so")
 
 SC_R64, SC_C64, SC_C128, SC_R32 = 0, 1, 2, 3
-SC_CALL_APPLY, SC_CALL_SEED, SC_CALL_PROJECT, SC_CALL_CG, SC_CALL_KAPPA_GRAD = 0, 1, 2, 3, 4
+SC_CALL_APPLY, SC_CALL_SEED, SC_CALL_PROJECT, SC_CALL_CG, SC_CALL_KAPPA_GRAD, SC_CALL_RELATED = 0, 1, 2, 3, 4, 5
 STATUS = {0: "SC_OK", 1: "SC_NOT_CONVERGED", 2: "SC_BREAKDOWN", -1: "SC_ERR_ARG", -2: "SC_ERR_HIP",
           -3: "SC_ERR_NOT_PD", -4: "SC_ERR_NONFINITE", -5: "SC_ERR_WORKSPACE", -6: "SC_ERR_UNSUPPORTED"}
 
@@ -60,6 +60,8 @@ _PROTOS = {
     "sc_timer_read": [_INT, ctypes.POINTER(_DBL), ctypes.POINTER(_I64), ctypes.POINTER(_DBL), ctypes.POINTER(_DBL)],
     "sc_batch_workspace_size": [_INT, _P, ctypes.POINTER(_SZ)],
     "sc_batch_solve": [_INT, _P, _P, _SZ, _P],
+    "sc_related_solve": [_P, _INT, _P, _I64, _P, _I64, _INT, _INT, _INT, _DBL, _INT, ctypes.POINTER(_INT),
+                         ctypes.POINTER(_DBL), ctypes.POINTER(_INT), _P, _SZ, _P],
     "sc_last_error": [],
 }
 
@@ -377,6 +379,30 @@ def seeded_solve(op, B, m, freq, tol, mixed=False, maxit=100000):
     X, its, rel = solve_cg(op, B, tol, X0=Xs, mixed=mixed, maxit=maxit)
     iters = [its[0] + basis.m_done] + its[1:]
     return {"X": X, "X_seeded": Xs, "iters": iters, "cg_iters": its, "relres": rel, "basis": basis}
+
+
+def related_rhs_solve(op, B, m, freq, tol, mixed=False, maxit=100000):
+    """Single seeding of related right-hand sides (Section 2.3): rows of B solved in order.
+
+    Row 0 is seeded by the Lanczos phase (m steps, reorthogonalization every
+    freq) and finished with CG; the other rows are projected over its basis,
+    then each is solved by CG and its CG correction seeds the rows after it.
+    Returns dict(X, iters (row 0 counts the seed steps), relres, m_done, status).
+    """
+    B = op._vec(B, op.dtype)
+    k = B.shape[0]
+    X = torch.empty_like(B)
+    nb = _SZ()
+    dt = op.sc_dtype if not mixed else _DT_OF[op.single_dtype]
+    _check(lib().sc_workspace_size(op.handle, SC_CALL_RELATED, k, int(m), dt, ctypes.byref(nb)))
+    w = _work(nb.value, op.device)
+    iters = (ctypes.c_int * k)()
+    rel = (ctypes.c_double * k)()
+    md = _INT()
+    st = lib().sc_related_solve(op.handle, 1 if mixed else 0, _ptr(B), op.n, _ptr(X), op.n, k, int(m), int(freq),
+                                float(tol), int(maxit), iters, rel, ctypes.byref(md), _ptr(w), w.numel(), _stream())
+    _check(st, ok=(0, 1, 2))
+    return {"X": X, "iters": list(iters), "relres": list(rel), "m_done": md.value, "status": st}
 
 
 def batch_solve(systems, maxit=100000):

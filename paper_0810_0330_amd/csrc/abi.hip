@@ -189,6 +189,10 @@ sc_status sc_workspace_size(const sc_op* op, int call, int k, int m, sc_dtype dt
             SC_ARG(op && op->kind == SC_OPK_WILSON, "kappa gradient needs a Wilson op");
             *bytes = kappa_grad_workspace(op, std::max(k, 1));
             return SC_OK;
+        case SC_CALL_RELATED:
+            SC_ARG(op && dtype_ok_for(op, dtype), "op NULL or dtype not valid for the op");
+            *bytes = related_workspace(op, std::max(k, 1), std::max(m, 1), is_single(dtype));
+            return SC_OK;
         default:
             SC_ARG(false, "unknown call id");
     }
@@ -371,6 +375,29 @@ sc_status sc_wilson_tune_set(const sc_op* op, sc_dtype dtype, int k, int variant
     SC_ARG(dtype == SC_C128 || dtype == SC_C64, "dtype must be SC_C128 or SC_C64");
     SC_ARG(k >= 1 && variant >= -1 && variant < SC_WILSON_VARIANTS, "k must be >= 1 and variant in -1..44");
     return wilson_tune_pin(op, dtype == SC_C64, k, variant);
+    SC_GUARD_END
+}
+
+sc_status sc_related_solve(const sc_op* op, int mixed, const void* B_dev, int64_t ldb, void* X_dev, int64_t ldx,
+                           int k, int m, int reorth_freq, double tol, int maxit, int* iters, double* relres,
+                           int* m_done, void* work_dev, size_t work_bytes, void* stream) {
+    SC_GUARD_BEGIN
+    SC_ARG(op, "op is NULL");
+    SC_ARG(k >= 1 && m >= 1 && reorth_freq >= 0 && maxit >= 1, "need k >= 1, m >= 1, reorth_freq >= 0, maxit >= 1");
+    SC_ARG(tol > 0.0 && std::isfinite(tol), "tol must be positive and finite");
+    SC_ARG(B_dev && X_dev && work_dev, "NULL device pointer");
+    SC_ARG(iters && relres && m_done, "NULL host pointer");
+    SC_ARG(!(mixed && op->kind == SC_OPK_WILSON && !op->U32), "mixed precision needs U32 links");
+    SC_ARG(ldb >= op->n && ldx >= op->n, "ldb or ldx smaller than n");
+    SC_ARG(aligned(B_dev, dtype_bytes(op->dtype)) && aligned(X_dev, dtype_bytes(op->dtype)),
+           "misaligned device pointer");
+    if (work_bytes < related_workspace(op, k, m, mixed != 0) - 256) {
+        set_error("related_solve: work buffer too small");
+        return SC_ERR_WORKSPACE;
+    }
+    *m_done = 0;
+    return related_solve(op, mixed, B_dev, ldb, X_dev, ldx, k, m, reorth_freq, tol, maxit, iters, relres, m_done,
+                         work_dev, work_bytes, (hipStream_t)stream);
     SC_GUARD_END
 }
 
