@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="wilson_16x3x32", choices=["wilson_16x3x32", "wilson_8x4", "laplace_32x32"])
+    ap.add_argument("--workload", default="wilson_16x3x32",
+                    choices=["wilson_16x3x32", "wilson_8x4", "laplace_32x32", "diag_5000"])
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--freq", type=int, default=None)
     ap.add_argument("--no-plain", action="store_true")
@@ -57,6 +58,9 @@ def parse():
     ap.add_argument("--related", type=int, default=None, metavar="NRHS",
                     help="time single seeding of NRHS related right-hand sides b^j = b^(j-1) + 0.2^(j-1) u^j "
                          "(Section 2.3, Example 3) on the workload's lattice instead of the benchmark")
+    ap.add_argument("--compare-seeding", action="store_true",
+                    help="A-applies, vector operations and time of no / multiple / single seeding on the workload "
+                         "(Section 2, Table 2.1 analogue) instead of the benchmark")
     ap.add_argument("--variant", type=int, default=None,
                     help="--micro wilson_*: pin this stencil launch shape instead of autotuning")
     return ap.parse_args()
@@ -194,6 +198,66 @@ def related_bench(args, w):
     print(json.dumps(res), flush=True)
 
 
+def vector_ops(kind, iters, m=0, freq=0, nrhs=0):
+    """Length-n vector operations (one dot or axpy on an n-vector each), as Table 2.1 counts them.
+
+    CG: 2 dots + 3 axpys per iteration.  Multiple seeding adds, per iteration of
+    system j, a dot and two axpys for each later system.  Single seeding adds the
+    seed phase (5 per Lanczos step, 4 (i - 1) + 4 per reorthogonalization at step
+    i) and the projection (2 m per projected right-hand side).
+    """
+    if kind == "none":
+        return 5 * sum(iters)
+    if kind == "multiple":
+        k = len(iters)
+        return sum(it * (5 + 3 * (k - 1 - j)) for j, it in enumerate(iters))
+    seed = 5 * m + (sum(4 * (i - 1) + 4 for i in range(freq, m + 1, freq)) if freq > 0 else 0)
+    return seed + 2 * m * (nrhs - 1) + 5 * (sum(iters) - m)
+
+
+def compare_seeding(args, w):
+    """Table 2.1 analogue on the GPU path: no seeding (per-RHS CG), multiple
+    seeding (standard seed CG) and single seeding, on the same right-hand sides."""
+    import numpy as np
+    import torch
+
+    from paper_0810_0330_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    inp = synth.make_inputs(w)
+    if w.op == "diag":
+        op = api.Op.diag(torch.from_numpy(inp["d"]).to(dev))
+        B = torch.from_numpy(np.ascontiguousarray(inp["B"].T)).to(dev)
+    else:
+        op = api.Op.wilson(w.dims, torch.from_numpy(api.pack_links(inp["U"])).to(dev), w.kappa)
+        B = torch.from_numpy(api.pack_field(np.ascontiguousarray(inp["B"].T))).to(dev)
+    k = w.nrhs
+    api.solve_cg(op, B[:1], w.tol)  # warm: tuning, allocations
+    res = {"compare_seeding": w.name, "nrhs": k, "tol": w.tol, "m": w.m, "freq": w.freq}
+    none_its = []
+
+    def none():
+        for j in range(k):
+            none_its.append(api.solve_cg(op, B[j:j + 1], w.tol)[1][0])
+        return {"iters": list(none_its), "relres": [0.0]}
+
+    m_run = w.m
+    runs = [("none", none), ("multiple", lambda: api.multiple_seed_solve(op, B, w.tol)),
+            ("single", lambda: api.seeded_solve(op, B, m_run, w.freq, w.tol))]
+    for name, fn in runs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert max(out["relres"]) <= w.tol
+        its = list(out["iters"])
+        res[name] = {"a_applies": sum(its), "iters": its, "ms": round(dt * 1e3, 2),
+                     "vector_ops": vector_ops(name, its, m_run, w.freq, k)}
+        log(f"[compare] {name}: {sum(its)} A-applies, {dt * 1e3:.1f} ms")
+    print(json.dumps(res), flush=True)
+
+
 def workload(args):
     from paper_0810_0330_amd import synth
     if args.workload == "wilson_16x3x32":
@@ -201,6 +265,8 @@ def workload(args):
     elif args.workload == "wilson_8x4":
         w = synth.wilson_8x4(m=150)
         w.precision = "mixed"
+    elif args.workload == "diag_5000":
+        w = synth.diag_5000()
     else:
         w = synth.laplace_32x32()
     if args.m is not None:
@@ -249,6 +315,8 @@ def cpu_baseline(w, inp, counts):
 
     if w.op == "laplace2d":
         op = ops.Laplace2DOp(*w.dims)
+    elif w.op == "diag":
+        op = ops.DiagOp(inp["d"])
     else:
         op = ops.WilsonNormalOp(inp["U"], w.kappa)
     b = inp["B"][:, 0].copy()
@@ -257,7 +325,7 @@ def cpu_baseline(w, inp, counts):
     for _ in range(napply):
         b = op(b) / np.linalg.norm(b)
     t_apply = (time.perf_counter() - t0) / napply
-    v = inp["B"][:, 1].astype(np.complex128 if w.op != "laplace2d" else np.float64)
+    v = inp["B"][:, 1].astype(np.complex128 if w.op == "wilson" else np.float64)
     y = v.copy()
     t0 = time.perf_counter()
     nvec = 8
@@ -300,11 +368,16 @@ def main():
         return sweep_freq(args, w)
     if args.related:
         return related_bench(args, w)
+    if args.compare_seeding:
+        return compare_seeding(args, w)
     log(f"[bench] workload {w.name}: dims {w.dims} nrhs {w.nrhs} m {w.m} freq {w.freq} tol {w.tol} {w.precision}")
     t0 = time.perf_counter()
     inp = synth.make_inputs(w)
     if w.op == "laplace2d":
         op = api.Op.laplace2d(*w.dims)
+        B = torch.from_numpy(np.ascontiguousarray(inp["B"].T)).to(dev)
+    elif w.op == "diag":
+        op = api.Op.diag(torch.from_numpy(inp["d"]).to(dev))
         B = torch.from_numpy(np.ascontiguousarray(inp["B"].T)).to(dev)
     else:
         op = api.Op.wilson(w.dims, torch.from_numpy(api.pack_links(inp["U"])).to(dev), w.kappa)

@@ -162,7 +162,8 @@ typedef enum {
     SC_CALL_PROJECT = 2,
     SC_CALL_CG = 3,
     SC_CALL_KAPPA_GRAD = 4,
-    SC_CALL_RELATED = 5
+    SC_CALL_RELATED = 5,
+    SC_CALL_MULTISEED = 6
 } sc_call;
 
 /* Bytes of `work` needed by a call.  k: right-hand sides per call; m: basis
@@ -250,6 +251,24 @@ sc_status sc_solve_cg(const sc_op* op, int mixed, const void* B_dev, int64_t ldb
 sc_status sc_related_solve(const sc_op* op, int mixed, const void* B_dev, int64_t ldb, void* X_dev,
                            int64_t ldx, int k, int m, int reorth_freq, double tol, int maxit, int* iters,
                            double* relres, int* m_done, void* work_dev, size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------ multiple seeding (comparator)
+ * Standard seed CG, the method the paper compares single seeding against
+ * (Section 2.1, after Chan and Wan; Example 1, Table 2.1).  The k systems
+ * (columns of B) are solved in order by CG from X = 0; while system j
+ * iterates, every later system i is projected over each new A-conjugate
+ * direction p (q = A p): c = (p^H r^i) / (p^H q), x^i += c p, r^i -= c q, with
+ * r^i the carried residual of system i.  System j then starts its own CG from
+ * that guess with its true residual.  FP64 in the op's dtype; two host
+ * synchronisations per iteration (a comparator, not a fast path).
+ *   B_dev: n x k (ldb), read only.  X_dev: n x k (ldx), written.  iters (host,
+ *   k): CG iterations (A-applies) of each system's own solve.  relres (host, k):
+ *   true relative residuals.
+ * Needs sc_workspace_size(op, SC_CALL_MULTISEED, k, 0, dtype) bytes.  Returns
+ * SC_OK, SC_NOT_CONVERGED, SC_ERR_NOT_PD (p^H A p <= 0) or an argument error. */
+sc_status sc_multiple_seed_solve(const sc_op* op, const void* B_dev, int64_t ldb, void* X_dev, int64_t ldx,
+                                 int k, double tol, int maxit, int* iters, double* relres, void* work_dev,
+                                 size_t work_bytes, void* stream);
 
 /* ------------------------------------------------------------------ timing
  * Optional event timing of the library's main kernels, for benchmarks (not

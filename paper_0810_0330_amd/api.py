@@ -27,7 +27,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libseedcg.so")
 
 SC_R64, SC_C64, SC_C128, SC_R32 = 0, 1, 2, 3
-SC_CALL_APPLY, SC_CALL_SEED, SC_CALL_PROJECT, SC_CALL_CG, SC_CALL_KAPPA_GRAD, SC_CALL_RELATED = 0, 1, 2, 3, 4, 5
+(SC_CALL_APPLY, SC_CALL_SEED, SC_CALL_PROJECT, SC_CALL_CG, SC_CALL_KAPPA_GRAD, SC_CALL_RELATED,
+ SC_CALL_MULTISEED) = 0, 1, 2, 3, 4, 5, 6
 STATUS = {0: "SC_OK", 1: "SC_NOT_CONVERGED", 2: "SC_BREAKDOWN", -1: "SC_ERR_ARG", -2: "SC_ERR_HIP",
           -3: "SC_ERR_NOT_PD", -4: "SC_ERR_NONFINITE", -5: "SC_ERR_WORKSPACE", -6: "SC_ERR_UNSUPPORTED"}
 
@@ -60,6 +61,8 @@ _PROTOS = {
     "sc_timer_read": [_INT, ctypes.POINTER(_DBL), ctypes.POINTER(_I64), ctypes.POINTER(_DBL), ctypes.POINTER(_DBL)],
     "sc_batch_workspace_size": [_INT, _P, ctypes.POINTER(_SZ)],
     "sc_batch_solve": [_INT, _P, _P, _SZ, _P],
+    "sc_multiple_seed_solve": [_P, _P, _I64, _P, _I64, _INT, _DBL, _INT, ctypes.POINTER(_INT), ctypes.POINTER(_DBL),
+                               _P, _SZ, _P],
     "sc_related_solve": [_P, _INT, _P, _I64, _P, _I64, _INT, _INT, _INT, _DBL, _INT, ctypes.POINTER(_INT),
                          ctypes.POINTER(_DBL), ctypes.POINTER(_INT), _P, _SZ, _P],
     "sc_last_error": [],
@@ -379,6 +382,23 @@ def seeded_solve(op, B, m, freq, tol, mixed=False, maxit=100000):
     X, its, rel = solve_cg(op, B, tol, X0=Xs, mixed=mixed, maxit=maxit)
     iters = [its[0] + basis.m_done] + its[1:]
     return {"X": X, "X_seeded": Xs, "iters": iters, "cg_iters": its, "relres": rel, "basis": basis}
+
+
+def multiple_seed_solve(op, B, tol, maxit=100000):
+    """Standard (multiple) seed CG, the comparator of Section 2.1: rows of B solved in order, each
+    later row projected over every CG direction of the earlier ones.  Returns dict(X, iters, relres, status)."""
+    B = op._vec(B, op.dtype)
+    k = B.shape[0]
+    X = torch.empty_like(B)
+    nb = _SZ()
+    _check(lib().sc_workspace_size(op.handle, SC_CALL_MULTISEED, k, 0, op.sc_dtype, ctypes.byref(nb)))
+    w = _work(nb.value, op.device)
+    iters = (ctypes.c_int * k)()
+    rel = (ctypes.c_double * k)()
+    st = lib().sc_multiple_seed_solve(op.handle, _ptr(B), op.n, _ptr(X), op.n, k, float(tol), int(maxit), iters, rel,
+                                      _ptr(w), w.numel(), _stream())
+    _check(st, ok=(0, 1))
+    return {"X": X, "iters": list(iters), "relres": list(rel), "status": st}
 
 
 def related_rhs_solve(op, B, m, freq, tol, mixed=False, maxit=100000):

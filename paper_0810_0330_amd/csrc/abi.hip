@@ -189,6 +189,10 @@ sc_status sc_workspace_size(const sc_op* op, int call, int k, int m, sc_dtype dt
             SC_ARG(op && op->kind == SC_OPK_WILSON, "kappa gradient needs a Wilson op");
             *bytes = kappa_grad_workspace(op, std::max(k, 1));
             return SC_OK;
+        case SC_CALL_MULTISEED:
+            SC_ARG(op && dtype_ok_for(op, dtype), "op NULL or dtype not valid for the op");
+            *bytes = multiseed_workspace(op, std::max(k, 1));
+            return SC_OK;
         case SC_CALL_RELATED:
             SC_ARG(op && dtype_ok_for(op, dtype), "op NULL or dtype not valid for the op");
             *bytes = related_workspace(op, std::max(k, 1), std::max(m, 1), is_single(dtype));
@@ -398,6 +402,27 @@ sc_status sc_related_solve(const sc_op* op, int mixed, const void* B_dev, int64_
     *m_done = 0;
     return related_solve(op, mixed, B_dev, ldb, X_dev, ldx, k, m, reorth_freq, tol, maxit, iters, relres, m_done,
                          work_dev, work_bytes, (hipStream_t)stream);
+    SC_GUARD_END
+}
+
+sc_status sc_multiple_seed_solve(const sc_op* op, const void* B_dev, int64_t ldb, void* X_dev, int64_t ldx, int k,
+                                 double tol, int maxit, int* iters, double* relres, void* work_dev, size_t work_bytes,
+                                 void* stream) {
+    SC_GUARD_BEGIN
+    SC_ARG(op, "op is NULL");
+    SC_ARG(k >= 1 && maxit >= 1, "need k >= 1 and maxit >= 1");
+    SC_ARG(tol > 0.0 && std::isfinite(tol), "tol must be positive and finite");
+    SC_ARG(B_dev && X_dev && work_dev, "NULL device pointer");
+    SC_ARG(iters && relres, "NULL host pointer");
+    SC_ARG(ldb >= op->n && ldx >= op->n, "ldb or ldx smaller than n");
+    SC_ARG(aligned(B_dev, dtype_bytes(op->dtype)) && aligned(X_dev, dtype_bytes(op->dtype)),
+           "misaligned device pointer");
+    if (work_bytes < multiseed_workspace(op, k) - 256) {
+        set_error("multiple_seed_solve: work buffer too small");
+        return SC_ERR_WORKSPACE;
+    }
+    return multiseed_solve(op, B_dev, ldb, X_dev, ldx, k, tol, maxit, iters, relres, work_dev, work_bytes,
+                           (hipStream_t)stream);
     SC_GUARD_END
 }
 

@@ -116,6 +116,11 @@ size_t cg_workspace(const sc_op* op, int k, bool mixed);
 sc_status solve_cg(const sc_op* op, int mixed, const void* B, int64_t ldb, void* X, int64_t ldx, int k, double tol,
                    int maxit, int* iters, double* relres, void* work, size_t work_bytes, hipStream_t s);
 
+// ---------------------------------------------------------------- multiple seeding (multiseed.hip)
+size_t multiseed_workspace(const sc_op* op, int k);
+sc_status multiseed_solve(const sc_op* op, const void* B, int64_t ldb, void* X, int64_t ldx, int k, double tol,
+                          int maxit, int* iters, double* relres, void* work, size_t work_bytes, hipStream_t s);
+
 // ---------------------------------------------------------------- related right-hand sides (related.hip)
 size_t related_workspace(const sc_op* op, int k, int m, bool mixed);
 sc_status related_solve(const sc_op* op, int mixed, const void* B, int64_t ldb, void* X, int64_t ldx, int k, int m,

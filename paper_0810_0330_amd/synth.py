@@ -121,6 +121,8 @@ class Workload:
     def n(self):
         if self.op == "laplace2d":
             return self.dims[0] * self.dims[1]
+        if self.op == "diag":
+            return self.dims[0]
         return volume(self.dims) * 12
 
 
@@ -142,10 +144,19 @@ def wilson_12x4(m=200):
                     kappa=0.12, config_id=3)
 
 
+def diag_5000():
+    """Section 2, Example 1: diagonal n = 5000, entries uniform on [0, 1], 8 N(0, 1) right-hand sides,
+    tol 1e-8; the seed runs to the first system's convergence (m = 430 for this draw) without
+    reorthogonalization."""
+    return Workload("diag_5000_8rhs_f64", "diag", (5000,), 8, 1e-8, 430, 0, config_id=100)
+
+
 def make_inputs(w: Workload):
-    """Returns dict with 'B' (n x nrhs natural layout) and, for Wilson, 'U' and 'kappa'."""
+    """Returns dict with 'B' (n x nrhs natural layout) and, for Wilson, 'U' and 'kappa'; for diag, 'd'."""
     if w.op == "laplace2d":
         return {"B": real_gaussian(w.n, w.nrhs, rng(w.config_id, 1))}
+    if w.op == "diag":
+        return {"d": diag_example(w.dims[0], rng(w.config_id, 0)), "B": real_gaussian(w.dims[0], w.nrhs, rng(w.config_id, 1))}
     U = su3_links(w.dims, rng(w.config_id, 0))
     npt = min(w.nrhs, 12)
     B = point_sources(w.dims, ALL_SPIN_COLOUR[:npt])

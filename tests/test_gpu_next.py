@@ -180,3 +180,59 @@ def test_related_rhs_wilson_on_gpu():
     assert outm["status"] == 0 and max(outm["relres"]) <= 1e-8
     for j in range(5):
         assert abs(outm["iters"][j] - mv[j]) <= 6, (j, outm["iters"][j], mv[j])
+
+
+# ----------------------------------------------------------------------------
+# Standard (multiple) seed CG, the paper's comparator (Section 2.1, Example 1,
+# Table 2.1), through sc_multiple_seed_solve.  Parity: per-system CG counts
+# within +-2 of the oracle's, every system at tol, solutions within
+# 2 cond(A) tol.  Table 2.1's ordering (single < multiple < none in total
+# A-applies) is checked on the GPU's own counts.
+from oracle.seeded import multiple_seed_solve as o_multiple  # noqa: E402
+
+
+def test_multiple_seeding_example_1_on_gpu():
+    n = GOLDEN["example_1"]["n"]
+    nrhs = GOLDEN["example_1"]["nrhs"]
+    d = synth.diag_example(n, synth.rng(100, 0))
+    B = synth.real_gaussian(n, nrhs, synth.rng(100, 1))
+    op = ops.DiagOp(d)
+    _say("multiple seeding, Example 1 setup: n", n, "nrhs", nrhs)
+    gop = api.Op.diag(torch.from_numpy(d).to(DEV))
+    Bt = torch.from_numpy(np.ascontiguousarray(B.T)).to(DEV)
+    out = api.multiple_seed_solve(gop, Bt, 1e-8)
+    Xo, mv = o_multiple(op, B, 1e-8)
+    _say("gpu", out["iters"], "oracle", mv)
+    assert out["status"] == 0 and max(out["relres"]) <= 1e-8
+    for j in range(nrhs):
+        assert abs(out["iters"][j] - mv[j]) <= 2, (j, out["iters"][j], mv[j])
+    X = out["X"].cpu().numpy().T
+    cond = d.max() / d.min()
+    for j in range(nrhs):
+        assert np.linalg.norm(X[:, j] - Xo[:, j]) <= 2 * cond * 1e-8 * np.linalg.norm(Xo[:, j])
+    # Table 2.1 on the GPU's counts: single < multiple < none in total A-applies
+    none = [api.solve_cg(gop, Bt[j:j + 1], 1e-8)[1][0] for j in range(nrhs)]
+    k1 = none[0]
+    single = api.seeded_solve(gop, Bt, k1, 0, 1e-8)["iters"]
+    _say("A-applies: none", sum(none), "multiple", sum(out["iters"]), "single", sum(single))
+    assert sum(single) < sum(out["iters"]) < sum(none)
+    # Example 1: the second system benefits, the third is pushed back up
+    assert out["iters"][1] < 0.85 * out["iters"][0]
+    assert out["iters"][2] > out["iters"][1]
+
+
+def test_multiple_seeding_wilson_on_gpu():
+    dims = (4, 4, 4, 8)
+    U = synth.su3_links(dims, synth.rng(2, 0))
+    op = ops.WilsonNormalOp(U, 0.12)
+    B = synth.complex_gaussian(op.n, 4, synth.rng(2, 5))
+    gop = api.Op.wilson(dims, torch.from_numpy(api.pack_links(U)).to(DEV), 0.12)
+    out = api.multiple_seed_solve(gop, torch.from_numpy(api.pack_field(np.ascontiguousarray(B.T))).to(DEV), 1e-10)
+    Xo, mv = o_multiple(op, B, 1e-10)
+    _say("multiple seeding, Wilson", dims, "gpu", out["iters"], "oracle", mv)
+    assert out["status"] == 0 and max(out["relres"]) <= 1e-10
+    for j in range(4):
+        assert abs(out["iters"][j] - mv[j]) <= 2
+    X = api.unpack_field(out["X"].cpu().numpy()).T
+    for j in range(4):
+        assert np.linalg.norm(X[:, j] - Xo[:, j]) <= 1e-6 * np.linalg.norm(Xo[:, j])
