@@ -7,6 +7,8 @@
 //
 // One iteration is four kernels: q = A p (the operator), partials of <p, q>,
 // x += alpha p and r -= alpha q with partials of ||r||^2, and p = r + beta p.
+// For A = D^H D the partials of <p, q> = ||D p||^2 come from the D pass
+// itself when its tuned shape supports it, and the second kernel is skipped.
 // Each consumer block re-adds the producer's per-block partials in a fixed
 // order, so every block derives the same scalars.  The per-column state is
 // double-buffered: the last kernel of an iteration reads one copy and writes
@@ -332,15 +334,20 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
         for (int j = 0; j < k; ++j) any |= hst[j].active != 0;
         while (any) {
             for (int it = 0; it < chunk; ++it) {
-                SC_TRY(op_apply(op, mixed, p, op->n, q, op->n, k, w.tmp, s));
-                hipLaunchKernelGGL((k_cg_pq<R, VEC>), grid, blk, 0, s, p, q, N2, N2, w.st[cur], w.part_pq);
-                SC_LAUNCH_CHECK();
+                // q = A p; for A = D^H D the D pass can also leave <p, q> = ||D p||^2
+                int gpq = 0;
+                SC_TRY(op_apply_norm(op, mixed, p, op->n, q, op->n, k, w.tmp, w.part_pq, kMaxRedBlocks, &gpq, s));
+                if (gpq == 0) {
+                    hipLaunchKernelGGL((k_cg_pq<R, VEC>), grid, blk, 0, s, p, q, N2, N2, w.st[cur], w.part_pq);
+                    SC_LAUNCH_CHECK();
+                    gpq = g;
+                }
                 if (mixed)
                     hipLaunchKernelGGL((k_cg_xr<float, R, VEC>), grid, blk, 0, s, (float*)w.xs, N2, r, p, q, N2, N2,
-                                       w.st[cur], w.part_pq, g, w.part_rr);
+                                       w.st[cur], w.part_pq, gpq, w.part_rr);
                 else
                     hipLaunchKernelGGL((k_cg_xr<double, R, VEC>), grid, blk, 0, s, X, ldx2, r, p, q, N2, N2,
-                                       w.st[cur], w.part_pq, g, w.part_rr);
+                                       w.st[cur], w.part_pq, gpq, w.part_rr);
                 SC_LAUNCH_CHECK();
                 hipLaunchKernelGGL((k_cg_p<R, VEC>), grid, blk, 0, s, p, r, N2, N2, w.st[cur], w.st[1 - cur],
                                    w.part_rr, g, mixed ? 1 : 0);

@@ -424,12 +424,21 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson_r(R* __restrict__ out, 
 // z fastest (CGMINOR = false: the Z planes of a segment run together on one
 // XCD) or (segment, z, column group) with the column group fastest (CGMINOR =
 // true: all column groups of a plane share its links through one L2).
-template <typename R, bool DAG, int MODE, int NC, bool CGMINOR>
+//
+// NORM: the block also leaves, per column, the partial sum of |out|^2 over its
+// sites in norm_part[column * (Z * nseg) + (segment * Z + z)] (for A = D^H D,
+// <p, A p> = ||D p||^2, so CG needs no separate reduction over p and A p).
+template <typename R, bool DAG, int MODE, int NC, bool CGMINOR, bool NORM = false>
 __global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64_t ldo, const R* __restrict__ in,
                                                       int64_t ldi, const R* __restrict__ U, Geom g, R kappa,
-                                                      R tsign, int k, int ncg, int nseg, int tlen, int per_xcd) {
+                                                      R tsign, int k, int ncg, int nseg, int tlen, int per_xcd,
+                                                      double* __restrict__ norm_part = nullptr) {
     using V2 = typename vec2<R>::type;
     __shared__ V2 pl[NC * 12][kBlock];
+    __shared__ double nsh[kWaves];
+    double nacc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) nacc[c] = 0.0;
     const int b = blockIdx.x;
     const int L = (b % kXcd) * per_xcd + b / kXcd;
     if (g.X * g.Y != kBlock || L >= ncg * nseg * g.Z) return;  // uniform over the block
@@ -555,6 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64
                             cplx<R> r = acc[c][a][cc];
                             if constexpr (MODE == 0) r = {cur[c][a][cc].re - kappa * r.re, cur[c][a][cc].im - kappa * r.im};
                             reinterpret_cast<V2*>(dst + 2 * (size_t)((a * 3 + cc) * uV))[s] = V2{r.re, r.im};
+                            if constexpr (NORM) nacc[c] += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
                         }
                 }
 #pragma unroll
@@ -562,6 +572,13 @@ __global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64
 #pragma unroll
                     for (int cc = 0; cc < 3; ++cc) cur[c][a][cc] = psi[a][cc];
             }
+        }
+    }
+    if constexpr (NORM) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double tot = block_sum(nacc[c], nsh);
+            if (threadIdx.x == 0 && live[c]) norm_part[(int64_t)(c0 + c) * (g.Z * nseg) + seg * g.Z + z] = tot;
         }
     }
 }
@@ -700,7 +717,7 @@ static bool tmarch_ok(const sc_op* op) { return op->dims[0] * op->dims[1] == kBl
 
 template <typename R, int NC, bool CGMINOR>
 static void wilson_launch_tm(const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k,
-                             const R* U, int tlen, hipStream_t s) {
+                             const R* U, int tlen, hipStream_t s, double* norm_part = nullptr) {
     Geom g{op->dims[0], op->dims[1], op->dims[2], op->dims[3], op->vol};
     tlen = std::max(1, std::min(tlen, g.T));
     const int nseg = (g.T + tlen - 1) / tlen;
@@ -711,7 +728,12 @@ static void wilson_launch_tm(const sc_op* op, int which, const R* X, int64_t ldx
     const R ts = op->antiperiodic ? R(-1) : R(1);
 #define SC_WT(DAG, MODE)                                                                                   \
     hipLaunchKernelGGL((k_wilson_tm<R, DAG, MODE, NC, CGMINOR>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,      \
-                       2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd);
+                       2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, nullptr);
+    if (norm_part && which == 0) {  // D pass with the |D x|^2 partials
+        hipLaunchKernelGGL((k_wilson_tm<R, false, 0, NC, CGMINOR, true>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,
+                           2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, norm_part);
+        return;
+    }
     switch (which) {
         case 0: SC_WT(false, 0) break;
         case 1: SC_WT(true, 0) break;
@@ -950,6 +972,61 @@ static sc_status wilson_launch(const sc_op* op, int which, const R* X, int64_t l
     wilson_launch_variant<R>(v, op, which, X, ldx, Y, ldy, k, U, s);
     SC_LAUNCH_CHECK();
     return SC_OK;
+}
+
+// The t-march shape tlen/order/columns of variant v (v >= WV_TILED)
+static void tm_params(int v, int* tlen, int* form, bool* cgminor) {
+    const int i = v - WV_TILED;
+    *tlen = i % 3 == 0 ? 4 : (i % 3 == 1 ? 8 : 16);
+    *form = (i / 3) % 2;
+    *cgminor = i >= 6;
+}
+
+template <typename R>
+static sc_status wilson_d_norm(const sc_op* op, const R* X, int64_t ldx, R* Y, int64_t ldy, int k, const R* U,
+                               double* part, int max_parts, int* G, hipStream_t s) {
+    *G = 0;
+    const int v = choose_variant<R>(op, 0, X, ldx, Y, ldy, k, U, s);
+    if (v < WV_TILED || v >= WV_DIR || !tmarch_ok(op)) return wilson_launch<R>(op, 0, X, ldx, Y, ldy, k, U, s);
+    int tlen, form;
+    bool cgminor;
+    tm_params(v, &tlen, &form, &cgminor);
+    tlen = std::max(1, std::min(tlen, op->dims[3]));
+    const int parts = op->dims[2] * ((op->dims[3] + tlen - 1) / tlen);
+    if (parts > max_parts) return wilson_launch<R>(op, 0, X, ldx, Y, ldy, k, U, s);
+    const double bytes = (48.0 * k + 72.0) * sizeof(R) * (double)op->vol;
+    const int cls = sizeof(R) == 4 ? (k == 1 ? TC_WILSON_F32 : TC_WILSON_F32_K) : (k == 1 ? TC_WILSON_F64 : TC_WILSON_F64_K);
+    TimerScope ts_(cls, s, bytes, 1368.0 * k * (double)op->vol);
+    constexpr int N2 = sizeof(R) == 4 ? 2 : 1;
+    if (form == 0) {
+        if (cgminor) wilson_launch_tm<R, 1, true>(op, 0, X, ldx, Y, ldy, k, U, tlen, s, part);
+        else wilson_launch_tm<R, 1, false>(op, 0, X, ldx, Y, ldy, k, U, tlen, s, part);
+    } else {
+        if (cgminor) wilson_launch_tm<R, N2, true>(op, 0, X, ldx, Y, ldy, k, U, tlen, s, part);
+        else wilson_launch_tm<R, N2, false>(op, 0, X, ldx, Y, ldy, k, U, tlen, s, part);
+    }
+    SC_LAUNCH_CHECK();
+    *G = parts;
+    return SC_OK;
+}
+
+sc_status op_apply_norm(const sc_op* op, bool single, const void* X, int64_t ldx, void* Y, int64_t ldy, int k,
+                        void* tmp, double* part, int max_parts, int* G, hipStream_t s) {
+    *G = 0;
+    if (k <= 0) return SC_OK;
+    if (op->kind != SC_OPK_WILSON) return op_apply(op, single, X, ldx, Y, ldy, k, tmp, s);
+    if (single) {
+        if (!op->U32) {
+            set_error("single-precision Wilson apply needs U32 links");
+            return SC_ERR_ARG;
+        }
+        SC_TRY(wilson_d_norm<float>(op, (const float*)X, ldx, (float*)tmp, op->n, k, (const float*)op->U32, part,
+                                    max_parts, G, s));
+    } else {
+        SC_TRY(wilson_d_norm<double>(op, (const double*)X, ldx, (double*)tmp, op->n, k, (const double*)op->U64, part,
+                                     max_parts, G, s));
+    }
+    return wilson_pass(op, single, 1, tmp, op->n, Y, ldy, k, s);
 }
 
 sc_status wilson_pass(const sc_op* op, bool single, int which, const void* X, int64_t ldx, void* Y, int64_t ldy,

@@ -39,6 +39,11 @@ sc_status op_apply(const sc_op* op, bool single, const void* X, int64_t ldx, voi
                    void* tmp, hipStream_t s);
 // elements of scratch op_apply needs per column
 int64_t op_apply_tmp_elems(const sc_op* op);
+// Y = A X; for the Wilson normal operator, when the tuned D-pass shape can, it
+// also leaves per-column partial sums of ||D x_j||^2 = <x_j, A x_j> in
+// part[j * G + i] (i < G <= max_parts) and sets G; otherwise G = 0.
+sc_status op_apply_norm(const sc_op* op, bool single, const void* X, int64_t ldx, void* Y, int64_t ldy, int k,
+                        void* tmp, double* part, int max_parts, int* G, hipStream_t s);
 // one Wilson pass: which 0 = D, 1 = D^H, 2 = H, 3 = H^H
 sc_status wilson_pass(const sc_op* op, bool single, int which, const void* X, int64_t ldx, void* Y, int64_t ldy,
                       int k, hipStream_t s);

@@ -388,3 +388,27 @@ def test_timer_sampling():
             assert t["wilson_f32_kn"]["launches"] == 2
             assert t["wilson_f32_kn"]["bytes"] == pytest.approx(2 * (48 * 3 + 72) * 4 * vol)
         assert t["wilson_f64_k1"]["launches"] == 0
+
+
+def test_cg_inner_product_from_the_d_pass():
+    # On lattices whose xy-plane is one 256-site tile the t-march D pass leaves
+    # the partials of ||D p||^2 = <p, A p> and CG skips its own reduction; the
+    # iteration counts and solutions must match the oracle's CG either way.
+    dims = (16, 16, 4, 8)
+    _say("CG with <p, A p> from the D pass", dims)
+    U, op = _wilson(dims, cfg=9)
+    oop = ops.WilsonNormalOp(U, 0.12)
+    k = 3
+    B = synth.complex_gaussian(op.n, k, synth.rng(9, 1))
+    ref = [cg(oop, B[:, j], tol=1e-9) for j in range(k)]
+    Bl = _to_lib(B)
+    for variant in (32, 41, 4):  # t-march (1 and 2 columns per thread), tiled
+        for mixed in (False, True):
+            op.tune_set(k, variant, single=mixed)
+            X, its, rel = api.solve_cg(op, Bl, 1e-9, mixed=mixed)
+            assert max(rel) <= 1e-9, (variant, mixed, rel)
+            Xn = _to_nat(X)
+            for j in range(k):
+                assert abs(its[j] - ref[j][1]) <= (2 if not mixed else 4), (variant, mixed, j, its[j], ref[j][1])
+                assert _rel(Xn[:, j:j + 1], ref[j][0][:, None]) < 1e-6
+            op.tune_set(k, -1, single=mixed)
