@@ -1,21 +1,13 @@
 // Operator applies: the 2D Laplacian, the diagonal matrix, and the Wilson-Dirac
-// stencil D = 1 - kappa H, its adjoint, and the hopping term alone.
-//
-// The Wilson hopping term sums, over the four directions mu, a forward hop
-// (1 - gamma_mu) U_mu(x) psi(x+mu) and a backward hop
-// (1 + gamma_mu) U_mu(x-mu)^H psi(x-mu); the adjoint D^H swaps the two spin
-// projectors.  In the chiral basis gamma_mu = [[0, A_mu], [A_mu^H, 0]] with
-// A_k = -i sigma_k (k = x, y, z) and A_t = 1, so (1 + s gamma_mu) psi, s = +-1,
-// is fixed by its upper half h = psi_up + s A_mu psi_down: the lower half is
-// s A_mu^H h.  Each hop therefore projects the neighbour to a two-spin half
-// spinor, multiplies the two colour vectors by the link, and reconstructs:
-// 2 x (3x3 complex matrix-vector) per hop instead of 4.
+// stencil D = 1 - kappa H, its adjoint, and the hopping term alone, in several
+// launch shapes chosen by an autotuner.  The hop arithmetic is in wilson_dev.h.
 #include <cstdlib>
 #include <map>
 #include <mutex>
 
 #include "sc_internal.h"
 #include "sc_timer.h"
+#include "wilson_dev.h"
 
 namespace sc {
 
@@ -46,149 +38,6 @@ __global__ __launch_bounds__(kBlock) void k_diag(R* __restrict__ y, int64_t ldy,
     y[blockIdx.y * ldy + idx] = R(d[idx]) * x[blockIdx.y * ldx + idx];
 }
 
-// ---------------------------------------------------------------- Wilson
-struct Geom {
-    int X, Y, Z, T;
-    int64_t V;
-};
-
-template <typename R>
-__device__ __forceinline__ cplx<R> cadd(cplx<R> a, cplx<R> b) { return {a.re + b.re, a.im + b.im}; }
-
-// a + S*b
-template <int S, typename R>
-__device__ __forceinline__ cplx<R> adds(cplx<R> a, cplx<R> b) {
-    if constexpr (S > 0) return {a.re + b.re, a.im + b.im};
-    else return {a.re - b.re, a.im - b.im};
-}
-// a + S*i*b
-template <int S, typename R>
-__device__ __forceinline__ cplx<R> addis(cplx<R> a, cplx<R> b) {
-    if constexpr (S > 0) return {a.re - b.im, a.im + b.re};
-    else return {a.re + b.im, a.im - b.re};
-}
-
-template <typename R>
-__device__ __forceinline__ R fmar(R a, R b, R c) {
-    if constexpr (sizeof(R) == 4) return __builtin_fmaf(a, b, c);
-    else return __builtin_fma(a, b, c);
-}
-
-// chi = U h (DAGU = false) or U^H h (DAGU = true) for one colour vector; four
-// fused multiply-adds per complex product
-template <bool DAGU, typename R>
-__device__ __forceinline__ void su3_mul(const cplx<R> u[3][3], const cplx<R> h[3], cplx<R> chi[3]) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        R re, im;
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const cplx<R> m = DAGU ? u[b][a] : u[a][b];
-            const R mi = DAGU ? -m.im : m.im;  // conj(m) for U^H
-            if (b == 0) {
-                re = m.re * h[b].re;
-                im = m.re * h[b].im;
-            } else {
-                re = fmar(m.re, h[b].re, re);
-                im = fmar(m.re, h[b].im, im);
-            }
-            re = fmar(-mi, h[b].im, re);
-            im = fmar(mi, h[b].re, im);
-        }
-        chi[a] = {re, im};
-    }
-}
-
-// One hop, acc += (1 + SIG gamma_MU) (U or U^H) psi (times bf for the time
-// direction), in two halves: hop_half projects psi to the two colour vectors
-// of the half spinor and multiplies them by the link; hop_acc rebuilds the
-// four spin components from them and adds them to acc.
-template <int MU, int SIG, bool DAGU, typename R>
-__device__ __forceinline__ void hop_half(const cplx<R> psi[4][3], const cplx<R> u[3][3], R bf, cplx<R> c0[3],
-                                         cplx<R> c1[3]) {
-    cplx<R> h0[3], h1[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        if constexpr (MU == 0) {         // A = -i sigma_x: A psi_dn = (-i psi3, -i psi2)
-            h0[c] = addis<-SIG>(psi[0][c], psi[3][c]);
-            h1[c] = addis<-SIG>(psi[1][c], psi[2][c]);
-        } else if constexpr (MU == 1) {  // A = -i sigma_y: A psi_dn = (-psi3, psi2)
-            h0[c] = adds<-SIG>(psi[0][c], psi[3][c]);
-            h1[c] = adds<SIG>(psi[1][c], psi[2][c]);
-        } else if constexpr (MU == 2) {  // A = -i sigma_z: A psi_dn = (-i psi2, i psi3)
-            h0[c] = addis<-SIG>(psi[0][c], psi[2][c]);
-            h1[c] = addis<SIG>(psi[1][c], psi[3][c]);
-        } else {                         // A = 1
-            h0[c] = adds<SIG>(psi[0][c], psi[2][c]);
-            h1[c] = adds<SIG>(psi[1][c], psi[3][c]);
-        }
-    }
-    if constexpr (MU == 3) {  // (anti)periodic boundary factor of the time hops
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            h0[c].re *= bf; h0[c].im *= bf;
-            h1[c].re *= bf; h1[c].im *= bf;
-        }
-    }
-    su3_mul<DAGU>(u, h0, c0);
-    su3_mul<DAGU>(u, h1, c1);
-}
-
-template <int MU, int SIG, typename R>
-__device__ __forceinline__ void hop_acc(cplx<R> acc[4][3], const cplx<R> c0[3], const cplx<R> c1[3]) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        acc[0][c] = cadd(acc[0][c], c0[c]);
-        acc[1][c] = cadd(acc[1][c], c1[c]);
-        // lower half: SIG * A^H chi
-        if constexpr (MU == 0) {         // A^H = i sigma_x: (i chi1, i chi0)
-            acc[2][c] = addis<SIG>(acc[2][c], c1[c]);
-            acc[3][c] = addis<SIG>(acc[3][c], c0[c]);
-        } else if constexpr (MU == 1) {  // A^H = i sigma_y: (chi1, -chi0)
-            acc[2][c] = adds<SIG>(acc[2][c], c1[c]);
-            acc[3][c] = adds<-SIG>(acc[3][c], c0[c]);
-        } else if constexpr (MU == 2) {  // A^H = i sigma_z: (i chi0, -i chi1)
-            acc[2][c] = addis<SIG>(acc[2][c], c0[c]);
-            acc[3][c] = addis<-SIG>(acc[3][c], c1[c]);
-        } else {
-            acc[2][c] = adds<SIG>(acc[2][c], c0[c]);
-            acc[3][c] = adds<SIG>(acc[3][c], c1[c]);
-        }
-    }
-}
-
-template <int MU, int SIG, bool DAGU, typename R>
-__device__ __forceinline__ void hop(cplx<R> acc[4][3], const cplx<R> psi[4][3], const cplx<R> u[3][3], R bf) {
-    cplx<R> c0[3], c1[3];
-    hop_half<MU, SIG, DAGU>(psi, u, bf, c0, c1);
-    hop_acc<MU, SIG>(acc, c0, c1);
-}
-
-// Loads with a wave-uniform base (scalar registers) plus one unsigned 32-bit
-// lane offset: the 12 components of a spinor and the 9 entries of a link are
-// V elements apart, so every load of a site shares one offset register.
-template <typename R>
-__device__ __forceinline__ cplx<R> ldc(const R* __restrict__ base, unsigned site) {
-    const typename vec2<R>::type v = reinterpret_cast<const typename vec2<R>::type*>(base)[site];
-    return {v.x, v.y};
-}
-
-template <typename R>
-__device__ __forceinline__ void load_spinor(const R* __restrict__ f, unsigned V, unsigned site, cplx<R> psi[4][3]) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) psi[s][c] = ldc(f + 2 * (size_t)((s * 3 + c) * V), site);
-}
-
-template <typename R>
-__device__ __forceinline__ void load_link(const R* __restrict__ U, unsigned V, int mu, unsigned site, cplx<R> u[3][3]) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) u[a][b] = ldc(U + 2 * (size_t)(((mu * 3 + a) * 3 + b) * V), site);
-}
-
 // Block -> work mapping.  Workgroups are dispatched round-robin over the 8
 // XCDs (block b runs on XCD b % 8), each with its own 4 MB L2.  Logical work
 // item L = (b % 8) * per_xcd + b / 8 gives every XCD a contiguous range of L.
@@ -205,7 +54,6 @@ __device__ __forceinline__ void load_link(const R* __restrict__ U, unsigned V, i
 // blocks of zb) walks zb tiles along z, then the next time slice, and so on
 // through all of t before the next block of z: the t-neighbours are then zb
 // tiles away and the z-neighbours one, except across block edges.
-constexpr int kXcd = 8;
 
 __device__ __forceinline__ bool map_work(int ntiles, int ncg, int G, int per_xcd, int zb, int T, int& tile,
                                          int& cg) {
@@ -603,63 +451,12 @@ __global__ __launch_bounds__(kBlock) void k_wilson_dir(R* __restrict__ out, int6
     const bool ok = s < (int)g.V;
     const unsigned uV = (unsigned)g.V;
     const R* src = in + (int64_t)col * ldi;
-    constexpr int SF = DAG ? 1 : -1;
-    constexpr int SB = -SF;
     cplx<R> acc[4][3];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
-    if (ok) {
-        const int XY = g.X * g.Y, XYZ = XY * g.Z;
-        int np, nm;
-        R bfp = R(1), bfm = R(1);
-        switch (mu) {
-            case 0: {
-                const int x = s % g.X;
-                np = x == g.X - 1 ? s - (g.X - 1) : s + 1;
-                nm = x == 0 ? s + (g.X - 1) : s - 1;
-                break;
-            }
-            case 1: {
-                const int y = (s / g.X) % g.Y;
-                np = y == g.Y - 1 ? s - (g.Y - 1) * g.X : s + g.X;
-                nm = y == 0 ? s + (g.Y - 1) * g.X : s - g.X;
-                break;
-            }
-            case 2: {
-                const int z = (s / XY) % g.Z;
-                np = z == g.Z - 1 ? s - (g.Z - 1) * XY : s + XY;
-                nm = z == 0 ? s + (g.Z - 1) * XY : s - XY;
-                break;
-            }
-            default: {
-                const int t = s / XYZ;
-                np = t == g.T - 1 ? s - (g.T - 1) * XYZ : s + XYZ;
-                nm = t == 0 ? s + (g.T - 1) * XYZ : s - XYZ;
-                bfp = t == g.T - 1 ? tsign : R(1);
-                bfm = t == 0 ? tsign : R(1);
-                break;
-            }
-        }
-        cplx<R> u[3][3], psi[4][3];
-        load_link(U, uV, mu, (unsigned)s, u);
-        load_spinor(src, uV, (unsigned)np, psi);
-        switch (mu) {
-            case 0: hop<0, SF, false>(acc, psi, u, bfp); break;
-            case 1: hop<1, SF, false>(acc, psi, u, bfp); break;
-            case 2: hop<2, SF, false>(acc, psi, u, bfp); break;
-            default: hop<3, SF, false>(acc, psi, u, bfp); break;
-        }
-        load_link(U, uV, mu, (unsigned)nm, u);
-        load_spinor(src, uV, (unsigned)nm, psi);
-        switch (mu) {
-            case 0: hop<0, SB, true>(acc, psi, u, bfm); break;
-            case 1: hop<1, SB, true>(acc, psi, u, bfm); break;
-            case 2: hop<2, SB, true>(acc, psi, u, bfm); break;
-            default: hop<3, SB, true>(acc, psi, u, bfm); break;
-        }
-    }
+    if (ok) dir_hops<DAG, R>(acc, src, U, g, uV, s, mu, tsign);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll

@@ -523,6 +523,74 @@ __global__ __launch_bounds__(kBlock) void k_nn(const VR* __restrict__ V, int64_t
     }
 }
 
+// X += scale V Y for complex N <= 2 (reorthogonalization): each thread owns
+// kNnRPT rows, the coefficients of 64 basis columns at a time are staged in
+// LDS, and per column the thread's loads are issued together, the next
+// column's before the current one is used.  Rows past n read row n - 1 and
+// are not written.
+constexpr int kNnRPT = 4;
+
+template <typename VR, typename XR>
+__global__ __launch_bounds__(kBlock) void k_nn_small(const VR* __restrict__ V, int64_t ldv, int64_t n, int M,
+                                                     const double* __restrict__ Y, int N, ColPtrs<void> X,
+                                                     double scale, const int* halt) {
+    if (halt && *halt) return;
+    constexpr int AC = 64;
+    __shared__ double Ys[AC * 4];  // [column][y0.re, y0.im, y1.re, y1.im]
+    const int64_t r0 = (int64_t)blockIdx.x * kBlock * kNnRPT + threadIdx.x;
+    int64_t rr[kNnRPT];
+#pragma unroll
+    for (int t = 0; t < kNnRPT; ++t) rr[t] = min(r0 + (int64_t)t * kBlock, n - 1);
+    double a0r[kNnRPT], a0i[kNnRPT], a1r[kNnRPT], a1i[kNnRPT];
+#pragma unroll
+    for (int t = 0; t < kNnRPT; ++t) a0r[t] = a0i[t] = a1r[t] = a1i[t] = 0.0;
+    for (int c0 = 0; c0 < M; c0 += AC) {
+        const int na = min(AC, M - c0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < AC * 4; e += kBlock) {
+            const int aa = e >> 2, j = (e >> 1) & 1, pp = e & 1;
+            Ys[e] = (aa < na && j < N) ? Y[((int64_t)(c0 + aa) * N + j) * 2 + pp] : 0.0;
+        }
+        __syncthreads();
+        cplx<VR> vb[kNnRPT], vn[kNnRPT];
+#pragma unroll
+        for (int t = 0; t < kNnRPT; ++t) vb[t] = ld2(V + 2 * ((int64_t)c0 * ldv), rr[t]);
+        for (int aa = 0; aa < na; ++aa) {
+            const int an = aa + 1 < na ? aa + 1 : aa;
+#pragma unroll
+            for (int t = 0; t < kNnRPT; ++t) vn[t] = ld2(V + 2 * ((int64_t)(c0 + an) * ldv), rr[t]);
+            const double y0r = Ys[aa * 4], y0i = Ys[aa * 4 + 1], y1r = Ys[aa * 4 + 2], y1i = Ys[aa * 4 + 3];
+#pragma unroll
+            for (int t = 0; t < kNnRPT; ++t) {
+                const double vr = (double)vb[t].re, vi = (double)vb[t].im;
+                a0r[t] += vr * y0r - vi * y0i;
+                a0i[t] += vr * y0i + vi * y0r;
+                a1r[t] += vr * y1r - vi * y1i;
+                a1i[t] += vr * y1i + vi * y1r;
+            }
+#pragma unroll
+            for (int t = 0; t < kNnRPT; ++t) vb[t] = vn[t];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kNnRPT; ++t) {
+        const int64_t r = r0 + (int64_t)t * kBlock;
+        if (r >= n) continue;
+        XR* x0 = (XR*)X.p[0];
+        cplx<XR> c = ld2(x0, r);
+        c.re = (XR)((double)c.re + scale * a0r[t]);
+        c.im = (XR)((double)c.im + scale * a0i[t]);
+        st2(x0, r, c);
+        if (N > 1) {
+            XR* x1 = (XR*)X.p[1];
+            cplx<XR> d = ld2(x1, r);
+            d.re = (XR)((double)d.re + scale * a1r[t]);
+            d.im = (XR)((double)d.im + scale * a1i[t]);
+            st2(x1, r, d);
+        }
+    }
+}
+
 template <typename VR, typename XR, bool CPLX>
 static void nn_launch(const VR* V, int64_t ldv, int64_t n, int M, const double* Y, int N, const ColPtrs<void>& X,
                       double scale, const int* halt, hipStream_t s) {
@@ -532,6 +600,11 @@ static void nn_launch(const VR* V, int64_t ldv, int64_t n, int M, const double* 
             hipLaunchKernelGGL((k_nn_mfma<VR, XR, 1>), gm, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
         else
             hipLaunchKernelGGL((k_nn_mfma<VR, XR, 2>), gm, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
+        return;
+    }
+    if (CPLX && N <= 2) {
+        dim3 gs((unsigned)((n + kBlock * kNnRPT - 1) / (kBlock * kNnRPT)));
+        hipLaunchKernelGGL((k_nn_small<VR, XR>), gs, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
         return;
     }
     dim3 grid((unsigned)((n + kBlock - 1) / kBlock));

@@ -68,6 +68,8 @@ __device__ __forceinline__ void st2(R* p, int64_t idx, cplx<R> c) {
 // ---------------------------------------------------------------- reductions
 constexpr int kBlock = 256;          // threads per block of the streaming kernels
 constexpr int kWaves = kBlock / 64;  // 64-wide wavefronts
+// XCDs of the chip: workgroup b of a launch runs on XCD b % kXcd, each with its own L2
+constexpr int kXcd = 8;
 constexpr int kMaxRedBlocks = 512;   // split-reduction width cap
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -10,6 +10,8 @@
 // pass (two tall-skinny contractions and one tridiagonal solve).  x^1 is the
 // same projection with V_m^H r0^1 = beta_0 e_1.
 #include "sc_internal.h"
+#include "sc_timer.h"
+#include "wilson_dev.h"
 
 namespace sc {
 
@@ -187,6 +189,147 @@ __global__ __launch_bounds__(kBlock) void k_lz_f(R* __restrict__ f, const R* __r
     block_partial(acc, part_f, sh);
 }
 
+// ---------------------------------------------------------------- fused Wilson steps
+// For the Wilson normal operator the two stencil passes of a Lanczos step carry
+// the neighbouring vector work, on the direction-split launch shape (a block
+// covers 64 sites, wave w the hops of direction w; partial results meet in
+// LDS):
+//   D pass of step i >= 2 = step 9 of step i - 1 + the pass: beta_{i-1} = ||f||
+//     from the partials (the checks of k_lz_next), v_i = f / beta_{i-1} stored
+//     for the block's sites, and D v_i = (D f) / beta_{i-1};
+//   D^H pass of step i = the pass + the first half of step 5:
+//     f = D^H (D v_i) - beta_{i-1} v_{i-1} and the partials of Re(v_i^H f),
+//     one per 64-site tile.
+// The arithmetic of the recurrence is that of the separate kernels.
+
+// sum over the 4 direction waves of component j of spin mu, for lane l
+template <typename R>
+__device__ __forceinline__ cplx<R> dir_total(R (*red)[24][64], int mu, int cc, int l) {
+    const int j = (mu * 3 + cc) * 2;
+    return {red[0][j][l] + red[1][j][l] + red[2][j][l] + red[3][j][l],
+            red[0][j + 1][l] + red[1][j + 1][l] + red[2][j + 1][l] + red[3][j + 1][l]};
+}
+
+template <typename R>
+__device__ __forceinline__ void dir_stash(R (*red)[24][64], int mu, int l, const cplx<R> acc[4][3]) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            red[mu][(a * 3 + cc) * 2][l] = acc[a][cc].re;
+            red[mu][(a * 3 + cc) * 2 + 1][l] = acc[a][cc].im;
+        }
+}
+
+template <typename R, typename VT>
+__global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const R* __restrict__ f,
+                                                     VT* __restrict__ vnext, const R* __restrict__ U, Geom g, R kappa,
+                                                     R tsign, int ntile, int per_xcd, double* beta, int im1,
+                                                     SeedState* st, const double* part, int G) {
+    __shared__ R red[4][24][64];
+    __shared__ double sh[kWaves];
+    if (st->halt) return;
+    const int b = blockIdx.x;
+    const int L = (b % kXcd) * per_xcd + b / kXcd;
+    if (L >= ntile) return;  // uniform over the block
+    const double bn = sqrt(sum_partials(part, G, sh));
+    const bool fin = isfinite(bn);
+    const bool brk = fin && !(bn > kBreakdownTol * st->amax);
+    if (b == 0 && threadIdx.x == 0) {  // block 0 always holds a tile
+        beta[im1] = bn;
+        if (!fin) {
+            st->status = SC_ERR_NONFINITE;
+            st->halt_step = im1;
+            st->m_done = im1 - 1;
+            st->halt = 1;
+        } else if (brk) {
+            st->status = SC_BREAKDOWN;
+            st->halt_step = im1;
+            st->m_done = im1;
+            st->halt = 1;
+        } else {
+            st->m_done = im1;
+        }
+    }
+    const int mu = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int s = L * 64 + l;
+    const bool ok = s < (int)g.V;
+    const unsigned uV = (unsigned)g.V;
+    if (brk || !fin) {  // the basis ends here: v_i = 0, as the separate step 9 stores
+        if (ok)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc)
+                reinterpret_cast<typename vec2<VT>::type*>(vnext)[(mu * 3 + cc) * uV + s] =
+                    typename vec2<VT>::type{VT(0), VT(0)};
+        return;
+    }
+    cplx<R> acc[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
+    if (ok) dir_hops<false, R>(acc, f, U, g, uV, s, mu, tsign);
+    dir_stash(red, mu, l, acc);
+    __syncthreads();
+    if (!ok) return;
+    const R bR = (R)bn;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+        const cplx<R> h = dir_total(red, mu, cc, l);
+        const size_t cb = 2 * (size_t)((mu * 3 + cc) * uV);
+        const cplx<R> fv = ldc(f + cb, (unsigned)s);
+        const cplx<R> v = {fv.re / bR, fv.im / bR};                              // v_i = f / beta
+        const cplx<R> r = {(fv.re - kappa * h.re) / bR, (fv.im - kappa * h.im) / bR};  // D v_i
+        reinterpret_cast<typename vec2<R>::type*>(tmp + cb)[s] = typename vec2<R>::type{r.re, r.im};
+        reinterpret_cast<typename vec2<VT>::type*>(vnext)[(mu * 3 + cc) * uV + s] =
+            typename vec2<VT>::type{(VT)v.re, (VT)v.im};
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_lz_dhalpha(R* __restrict__ f, const R* __restrict__ tmp,
+                                                       const R* __restrict__ vi, const R* __restrict__ vprev,
+                                                       const R* __restrict__ U, Geom g, R kappa, R tsign, int ntile,
+                                                       int per_xcd, const double* beta, int i, const SeedState* st,
+                                                       double* part) {
+    __shared__ R red[4][24][64];
+    __shared__ double sh[kWaves];
+    if (st->halt) return;
+    const int b = blockIdx.x;
+    const int L = (b % kXcd) * per_xcd + b / kXcd;
+    if (L >= ntile) return;  // uniform over the block
+    const int mu = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int s = L * 64 + l;
+    const bool ok = s < (int)g.V;
+    const unsigned uV = (unsigned)g.V;
+    cplx<R> acc[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
+    if (ok) dir_hops<true, R>(acc, tmp, U, g, uV, s, mu, tsign);
+    dir_stash(red, mu, l, acc);
+    __syncthreads();
+    const R bp = (R)(i > 1 ? beta[i - 1] : 0.0);
+    double dacc = 0.0;
+    if (ok) {
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            const cplx<R> h = dir_total(red, mu, cc, l);
+            const size_t cb = 2 * (size_t)((mu * 3 + cc) * uV);
+            const cplx<R> t = ldc(tmp + cb, (unsigned)s);
+            const cplx<R> av = {t.re - kappa * h.re, t.im - kappa * h.im};  // A v_i = D^H (D v_i)
+            const cplx<R> pv = ldc(vprev + cb, (unsigned)s);
+            const cplx<R> v = ldc(vi + cb, (unsigned)s);
+            const cplx<R> fv = {av.re - bp * pv.re, av.im - bp * pv.im};
+            reinterpret_cast<typename vec2<R>::type*>(f + cb)[s] = typename vec2<R>::type{fv.re, fv.im};
+            dacc += (double)v.re * (double)fv.re + (double)v.im * (double)fv.im;
+        }
+    }
+    const double tot = block_sum(dacc, sh);
+    if (threadIdx.x == 0) part[L] = tot;
+}
+
 // v /= ||v|| (norm from partials)
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_scale_norm(R* __restrict__ v, int64_t N, const double* part, int G,
@@ -211,7 +354,7 @@ static SeedWork carve_seed(Carver& c, const sc_op* op, int m, bool single) {
     w.r64 = c.take<double>(N2);
     w.ax64 = c.take<double>(N2);
     w.tmp64 = c.take<double>(std::max<int64_t>(tmpn, 1));
-    w.part_a = c.take<double>(kMaxRedBlocks);
+    w.part_a = c.take<double>(std::max<int64_t>(kMaxRedBlocks, (op->n / 12 + 63) / 64));
     w.part_f = c.take<double>(kMaxRedBlocks);
     w.part_v = c.take<double>(kMaxRedBlocks);
     w.delta = c.take<double>((size_t)m + 2);
@@ -257,17 +400,54 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
     hipLaunchKernelGGL((k_lz_next<R, double, false>), dim3(g), blk, 0, s, V, w.r64, N2, beta, 0, w.st, w.part_f, g);
     SC_LAUNCH_CHECK();
 
+    // the fused Wilson form (direction-split passes carrying the vector work)
+    const bool fused = op->kind == SC_OPK_WILSON && (!single || op->U32);
+    const Geom geo{op->dims[0], op->dims[1], op->dims[2], op->dims[3], op->vol};
+    const int ntile = (int)((op->vol + 63) / 64);
+    const int per_xcd = (ntile + kXcd - 1) / kXcd;
+    const dim3 dgrid((unsigned)(per_xcd * kXcd));
+    const R* U = fused ? (const R*)(single ? op->U32 : op->U64) : nullptr;
+    const R kapR = (R)op->kappa;
+    const R tsg = op->antiperiodic ? R(-1) : R(1);
+    const double pass_bytes = (48.0 + 72.0) * sizeof(R) * (double)op->vol;
+    const int tcls = single ? TC_WILSON_F32 : TC_WILSON_F64;
+    R* tmpv = (R*)w.tmp;
+    int gf = g;  // partials of ||f||^2 left by the previous step
+
     for (int i = 1; i <= m; ++i) {
         R* vi = V + (int64_t)(i - 1) * ldv2;
         R* vprev = i > 1 ? V + (int64_t)(i - 2) * ldv2 : vi;
         R* vnext = V + (int64_t)i * ldv2;
-        // step 5: f = A v_i - beta_{i-1} v_{i-1}; alpha_i; f -= alpha_i v_i
-        SC_TRY(op_apply(op, single, vi, ldv, av, op->n, 1, w.tmp, s));
-        hipLaunchKernelGGL((k_lz_alpha<R, VEC>), dim3(g), blk, 0, s, f, av, vi, vprev, N2, beta, i, w.st, w.part_a);
-        SC_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_lz_f<R, VEC>), dim3(g), blk, 0, s, f, vi, N2, alpha, beta, w.delta, i, w.st, w.part_a,
-                           g, w.part_f);
-        SC_LAUNCH_CHECK();
+        if (fused) {
+            // D pass (with step 9 of step i - 1 for i >= 2), then D^H pass with the first half of step 5
+            if (i == 1) {
+                SC_TRY(wilson_pass(op, single, 0, vi, ldv, tmpv, op->n, 1, s));
+            } else {
+                TimerScope ts_(tcls, s, pass_bytes + 24.0 * sizeof(R) * op->vol, 1368.0 * op->vol);
+                hipLaunchKernelGGL((k_lz_dnext<R, R>), dgrid, blk, 0, s, tmpv, (const R*)f, vi, U, geo, kapR, tsg,
+                                   ntile, per_xcd, beta, i - 1, w.st, w.part_f, gf);
+                SC_LAUNCH_CHECK();
+            }
+            {
+                TimerScope ts_(tcls, s, pass_bytes + 48.0 * sizeof(R) * op->vol, 1368.0 * op->vol);
+                hipLaunchKernelGGL((k_lz_dhalpha<R>), dgrid, blk, 0, s, f, (const R*)tmpv, (const R*)vi,
+                                   (const R*)vprev, U, geo, kapR, tsg, ntile, per_xcd, beta, i, w.st, w.part_a);
+                SC_LAUNCH_CHECK();
+            }
+            hipLaunchKernelGGL((k_lz_f<R, VEC>), dim3(g), blk, 0, s, f, vi, N2, alpha, beta, w.delta, i, w.st,
+                               w.part_a, ntile, w.part_f);
+            SC_LAUNCH_CHECK();
+        } else {
+            // step 5: f = A v_i - beta_{i-1} v_{i-1}; alpha_i; f -= alpha_i v_i
+            SC_TRY(op_apply(op, single, vi, ldv, av, op->n, 1, w.tmp, s));
+            hipLaunchKernelGGL((k_lz_alpha<R, VEC>), dim3(g), blk, 0, s, f, av, vi, vprev, N2, beta, i, w.st,
+                               w.part_a);
+            SC_LAUNCH_CHECK();
+            hipLaunchKernelGGL((k_lz_f<R, VEC>), dim3(g), blk, 0, s, f, vi, N2, alpha, beta, w.delta, i, w.st,
+                               w.part_a, g, w.part_f);
+            SC_LAUNCH_CHECK();
+        }
+        gf = g;
         if (freq > 0 && i >= 2 && i % freq == 0) {
             // step 8: [v_i, f] -= V_{i-1} (V_{i-1}^H [v_i, f]); v_i /= ||v_i||; f -= v_i (v_i^H f)
             ColPtrs<const void> wc{};
@@ -291,9 +471,12 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
             hipLaunchKernelGGL((k_norm_part<R, VEC>), dim3(g), blk, 0, s, f, N2, w.part_f, halt);
             SC_LAUNCH_CHECK();
         }
-        // step 9: beta_i = ||f||, v_{i+1} = f / beta_i
-        hipLaunchKernelGGL((k_lz_next<R, R, VEC>), dim3(g), blk, 0, s, vnext, f, N2, beta, i, w.st, w.part_f, g);
-        SC_LAUNCH_CHECK();
+        // step 9: beta_i = ||f||, v_{i+1} = f / beta_i (the fused form does it in the next D pass)
+        if (!fused || i == m) {
+            hipLaunchKernelGGL((k_lz_next<R, R, VEC>), dim3(g), blk, 0, s, vnext, f, N2, beta, i, w.st, w.part_f,
+                               gf);
+            SC_LAUNCH_CHECK();
+        }
     }
     return SC_OK;
 }
