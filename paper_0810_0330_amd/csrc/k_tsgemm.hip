@@ -36,7 +36,12 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
 }
 
 // G = V^H W: block = 4 waves over 64 basis columns (16 per wave) x 16*NJ
-// right-hand columns, one row chunk; LDS stages of 32 complex rows.
+// right-hand columns, one row chunk; LDS stages of 32 complex rows.  The
+// stages are software-pipelined: each thread holds its share of the next
+// stage's V and W elements in registers, loaded before the current stage's
+// MFMAs are issued and written to LDS after them, so the global-load latency
+// of a stage hides behind the previous stage's compute.  V stays in its own
+// precision in LDS and is widened when it is fed to the MFMA.
 template <typename VR, typename WR, int NJ>
 __global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, int64_t ldv, int64_t n, int M,
                                                     ColPtrs<const void> W, int N, double* __restrict__ part,
@@ -45,7 +50,9 @@ __global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, in
     constexpr int KR = 32;          // complex rows per LDS stage
     constexpr int TA = 64;          // basis columns per block
     constexpr int TJ = 16 * NJ;     // right-hand columns per block
-    __shared__ double vr[KR][TA + 1], vi[KR][TA + 1];
+    constexpr int EV = KR * TA / kBlock;  // V elements per thread per stage
+    constexpr int EW = KR * TJ / kBlock;  // W elements per thread per stage
+    __shared__ VR vr[KR][TA + 1], vi[KR][TA + 1];
     __shared__ double wr[KR][TJ + 1], wi[KR][TJ + 1];
     const int a0 = blockIdx.y * TA;
     const int64_t r0 = blockIdx.x * rows_per_chunk;
@@ -54,38 +61,52 @@ __global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, in
     d4_t accr[NJ], acci[NJ];
 #pragma unroll
     for (int t = 0; t < NJ; ++t) accr[t] = acci[t] = d4_t{0.0, 0.0, 0.0, 0.0};
-    for (int64_t rb = r0; rb < r1; rb += KR) {
-        __syncthreads();
-        // V tile: column a, rows rb..rb+KR; consecutive threads walk down a column
-        for (int e = threadIdx.x; e < KR * TA; e += kBlock) {
-            const int rr = e % KR, aa = e / KR;
-            const int64_t r = rb + rr;
-            const int a = a0 + aa;
-            cplx<double> v{0.0, 0.0};
-            if (r < r1 && a < M) {
-                const cplx<VR> c = ld2(V, (int64_t)a * ldv + r);
-                v = {(double)c.re, (double)c.im};
-            }
-            vr[rr][aa] = v.re;
-            vi[rr][aa] = v.im;
+    cplx<VR> pv[EV];
+    cplx<double> pw[EW];
+    // element e of a stage: V row e % KR of column e / KR; W row e % KR of column e / KR
+    auto fetch = [&](int64_t rb) {
+#pragma unroll
+        for (int q = 0; q < EV; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            const int64_t r = rb + e % KR;
+            const int a = a0 + e / KR;
+            pv[q] = (r < r1 && a < M) ? ld2(V, (int64_t)a * ldv + r) : cplx<VR>{VR(0), VR(0)};
         }
-        for (int e = threadIdx.x; e < KR * TJ; e += kBlock) {
-            const int rr = e % KR, jj = e / KR;
-            const int64_t r = rb + rr;
+#pragma unroll
+        for (int q = 0; q < EW; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            const int64_t r = rb + e % KR;
+            const int jj = e / KR;
             cplx<double> w{0.0, 0.0};
             if (r < r1 && jj < N) {
                 const cplx<WR> c = ld2((const WR*)W.p[jj], r);
                 w = {(double)c.re, (double)c.im};
             }
-            wr[rr][jj] = w.re;
-            wi[rr][jj] = w.im;
+            pw[q] = w;
+        }
+    };
+    if (r0 < r1) fetch(r0);
+    for (int64_t rb = r0; rb < r1; rb += KR) {
+        __syncthreads();  // the previous stage's MFMAs are done with the LDS tiles
+#pragma unroll
+        for (int q = 0; q < EV; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            vr[e % KR][e / KR] = pv[q].re;
+            vi[e % KR][e / KR] = pv[q].im;
+        }
+#pragma unroll
+        for (int q = 0; q < EW; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            wr[e % KR][e / KR] = pw[q].re;
+            wi[e % KR][e / KR] = pw[q].im;
         }
         __syncthreads();
+        if (rb + KR < r1) fetch(rb + KR);  // in flight during this stage's MFMAs
 #pragma unroll
         for (int ks = 0; ks < KR / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
-            const double ar = vr[kr][wv * 16 + (lane & 15)];
-            const double ai = vi[kr][wv * 16 + (lane & 15)];
+            const double ar = (double)vr[kr][wv * 16 + (lane & 15)];
+            const double ai = (double)vi[kr][wv * 16 + (lane & 15)];
 #pragma unroll
             for (int t = 0; t < NJ; ++t) {
                 const double br = wr[kr][t * 16 + (lane & 15)];
@@ -113,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, in
 }
 
 // X_j += scale * V Y_j: block = 4 waves over 64 rows (16 per wave) x 16*NJ
-// columns; LDS stages of 32 basis columns.
+// columns; LDS stages of 32 basis columns, software-pipelined like k_cn_mfma.
 template <typename VR, typename XR, int NJ>
 __global__ __launch_bounds__(kBlock) void k_nn_mfma(const VR* __restrict__ V, int64_t ldv, int64_t n, int M,
                                                     const double* __restrict__ Y, int N, ColPtrs<void> X,
@@ -122,44 +143,59 @@ __global__ __launch_bounds__(kBlock) void k_nn_mfma(const VR* __restrict__ V, in
     constexpr int KA = 32;          // basis columns per LDS stage
     constexpr int TR = 64;          // rows per block
     constexpr int TJ = 16 * NJ;
-    __shared__ double vr[TR][KA + 1], vi[TR][KA + 1];
+    constexpr int EV = TR * KA / kBlock;
+    constexpr int EY = (KA * TJ + kBlock - 1) / kBlock;
+    __shared__ VR vr[TR][KA + 1], vi[TR][KA + 1];
     __shared__ double yr[KA][TJ + 1], yi[KA][TJ + 1];
     const int64_t row0 = (int64_t)blockIdx.x * TR;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     d4_t accr[NJ], acci[NJ];
 #pragma unroll
     for (int t = 0; t < NJ; ++t) accr[t] = acci[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    cplx<VR> pv[EV];
+    cplx<double> py[EY];
+    // element e: V row e % TR of basis column e / TR; Y basis column e / TJ, right-hand column e % TJ
+    auto fetch = [&](int ab) {
+#pragma unroll
+        for (int q = 0; q < EV; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            const int64_t r = row0 + e % TR;
+            const int a = ab + e / TR;
+            pv[q] = (r < n && a < M) ? ld2(V, (int64_t)a * ldv + r) : cplx<VR>{VR(0), VR(0)};
+        }
+#pragma unroll
+        for (int q = 0; q < EY; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            const int a = ab + e / TJ, jj = e % TJ;
+            py[q] = (e < KA * TJ && a < M && jj < N)
+                        ? cplx<double>{Y[((int64_t)a * N + jj) * 2], Y[((int64_t)a * N + jj) * 2 + 1]}
+                        : cplx<double>{0.0, 0.0};
+        }
+    };
+    if (M > 0) fetch(0);
     for (int ab = 0; ab < M; ab += KA) {
         __syncthreads();
-        for (int e = threadIdx.x; e < TR * KA; e += kBlock) {
-            const int rr = e % TR, aa = e / TR;
-            const int64_t r = row0 + rr;
-            const int a = ab + aa;
-            cplx<double> v{0.0, 0.0};
-            if (r < n && a < M) {
-                const cplx<VR> c = ld2(V, (int64_t)a * ldv + r);
-                v = {(double)c.re, (double)c.im};
-            }
-            vr[rr][aa] = v.re;
-            vi[rr][aa] = v.im;
+#pragma unroll
+        for (int q = 0; q < EV; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            vr[e % TR][e / TR] = pv[q].re;
+            vi[e % TR][e / TR] = pv[q].im;
         }
-        for (int e = threadIdx.x; e < KA * TJ; e += kBlock) {
-            const int aa = e / TJ, jj = e % TJ;
-            const int a = ab + aa;
-            double re = 0.0, im = 0.0;
-            if (a < M && jj < N) {
-                re = Y[((int64_t)a * N + jj) * 2];
-                im = Y[((int64_t)a * N + jj) * 2 + 1];
+#pragma unroll
+        for (int q = 0; q < EY; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            if (e < KA * TJ) {
+                yr[e / TJ][e % TJ] = py[q].re;
+                yi[e / TJ][e % TJ] = py[q].im;
             }
-            yr[aa][jj] = re;
-            yi[aa][jj] = im;
         }
         __syncthreads();
+        if (ab + KA < M) fetch(ab + KA);
 #pragma unroll
         for (int ks = 0; ks < KA / 4; ++ks) {
             const int ka = ks * 4 + (lane >> 4);
-            const double ar = vr[wv * 16 + (lane & 15)][ka];
-            const double ai = vi[wv * 16 + (lane & 15)][ka];
+            const double ar = (double)vr[wv * 16 + (lane & 15)][ka];
+            const double ai = (double)vi[wv * 16 + (lane & 15)][ka];
 #pragma unroll
             for (int t = 0; t < NJ; ++t) {
                 const double br = yr[ka][t * 16 + (lane & 15)];
