@@ -45,7 +45,7 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
 template <typename VR, typename WR, int NJ>
 __global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, int64_t ldv, int64_t n, int M,
                                                     ColPtrs<const void> W, int N, double* __restrict__ part,
-                                                    int64_t rows_per_chunk, const int* halt) {
+                                                    int64_t rows_per_chunk, int nchunk, const int* halt) {
     if (halt && *halt) return;
     constexpr int KR = 32;          // complex rows per LDS stage
     constexpr int TA = 64;          // basis columns per block
@@ -54,8 +54,16 @@ __global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, in
     constexpr int EW = KR * TJ / kBlock;  // W elements per thread per stage
     __shared__ VR vr[KR][TA + 1], vi[KR][TA + 1];
     __shared__ double wr[KR][TJ + 1], wi[KR][TJ + 1];
-    const int a0 = blockIdx.y * TA;
-    const int64_t r0 = blockIdx.x * rows_per_chunk;
+    // work item L = (b % 8) * per_xcd + b / 8 over (row chunk, column block),
+    // column blocks fastest: the blocks that read one chunk of W run together
+    // on one XCD and share it through its L2
+    const int mblk = (M + TA - 1) / TA;
+    const int per_xcd = (nchunk * mblk + kXcd - 1) / kXcd;
+    const int L = (blockIdx.x % kXcd) * per_xcd + blockIdx.x / kXcd;
+    if (L >= nchunk * mblk) return;
+    const int chunk = L / mblk;
+    const int a0 = (L % mblk) * TA;
+    const int64_t r0 = chunk * rows_per_chunk;
     const int64_t r1 = min(n, r0 + rows_per_chunk);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     d4_t accr[NJ], acci[NJ];
@@ -125,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, in
         for (int v = 0; v < 4; ++v) {
             const int a = a0 + wv * 16 + (lane >> 4) + 4 * v;
             if (a < M && j < N) {
-                const int64_t o = ((int64_t)blockIdx.x * M + a) * N + j;
+                const int64_t o = ((int64_t)chunk * M + a) * N + j;
                 part[2 * o] = accr[t][v];
                 part[2 * o + 1] = acci[t][v];
             }
@@ -464,12 +472,17 @@ template <typename VR, typename WR>
 static void cn_mfma_launch(const CnPlan& p, const VR* V, int64_t ldv, int64_t n, int M, const ColPtrs<const void>& W,
                            int N, double* part, const int* halt, hipStream_t s) {
     dim3 grid((unsigned)p.nchunk, (unsigned)((M + 63) / 64));
+    const int mblk = (M + 63) / 64;
+    const int per_xcd = (p.nchunk * mblk + kXcd - 1) / kXcd;
+    dim3 grid1((unsigned)(per_xcd * kXcd));
     if (N <= 2)
         hipLaunchKernelGGL((k_cn_small<VR, WR>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
     else if (N <= 16)
-        hipLaunchKernelGGL((k_cn_mfma<VR, WR, 1>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
+        hipLaunchKernelGGL((k_cn_mfma<VR, WR, 1>), grid1, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows,
+                           p.nchunk, halt);
     else
-        hipLaunchKernelGGL((k_cn_mfma<VR, WR, 2>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
+        hipLaunchKernelGGL((k_cn_mfma<VR, WR, 2>), grid1, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows,
+                           p.nchunk, halt);
 }
 
 sc_status gemm_cn(bool cplx, bool vsingle, const void* V, int64_t ldv, int64_t n, int M, bool wsingle,
