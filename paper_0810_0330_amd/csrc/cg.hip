@@ -7,8 +7,11 @@
 //
 // One iteration is four kernels: q = A p (the operator), partials of <p, q>,
 // x += alpha p and r -= alpha q with partials of ||r||^2, and p = r + beta p.
-// For A = D^H D the partials of <p, q> = ||D p||^2 come from the D pass
-// itself when its tuned shape supports it, and the second kernel is skipped.
+// For the Wilson normal operator on a t-march stencil shape it is three: the
+// D pass leaves the partials of <p, q> = ||D p||^2, the D^H pass applies
+// r -= alpha q itself (q is never stored) and leaves those of ||r||^2, and one
+// kernel does x += alpha p and p = r + beta p.  The formulas and their order
+// are the same.
 // Each consumer block re-adds the producer's per-block partials in a fixed
 // order, so every block derives the same scalars.  The per-column state is
 // double-buffered: the last kernel of an iteration reads one copy and writes
@@ -26,19 +29,6 @@
 #include <vector>
 
 namespace sc {
-
-struct CGCol {
-    double rho;      // ||r||^2 of the current recurrence
-    double rho_prev; // rho of the previous iteration
-    double beta;     // rho / rho_prev
-    double bnorm2;   // ||b||^2
-    double tol2;     // tol^2 ||b||^2
-    double rmax2;    // largest ||r||^2 since the last reliable update
-    int active;      // iterating
-    int iters;       // A-applies inside the loop so far
-    int maxit;
-    int flag;        // 1: recursive residual at tol; 2: mixed, reliable update due
-};
 
 __global__ void k_cg_setup(CGCol* st, const double* rho, const double* bn, int k, double tol, int maxit, int first) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -168,6 +158,65 @@ __global__ __launch_bounds__(kBlock) void k_cg_p(R* __restrict__ p, const R* __r
             stp(pc, i0, pv);
         } else {
             for (int64_t j = i0; j < min(N, i0 + W); ++j) pc[j] = rc[j] + b * pc[j];
+        }
+    }
+}
+
+// The fused iteration's last kernel: alpha = rho / <p, q> and the new rho from
+// the stencil passes' partials; x += alpha p for the columns active at the
+// start of the iteration, then the decisions of k_cg_p and p = r + beta p.
+template <typename XT, typename R, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_cg_xp(XT* __restrict__ x, int64_t ldx, R* __restrict__ p,
+                                                  const R* __restrict__ r, int64_t ld, int64_t N, const CGCol* st,
+                                                  CGCol* st_next, const double* part_pq, const double* part_rr, int G,
+                                                  int mixed) {
+    __shared__ double sh[kWaves];
+    const int col = blockIdx.y;
+    CGCol c = st[col];
+    if (!c.active) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st_next[col] = c;
+        return;
+    }
+    constexpr int W = Pack<R>::W;
+    const double a = c.rho / sum_partials(part_pq + (int64_t)col * G, G, sh);
+    const double rr = sum_partials(part_rr + (int64_t)col * G, G, sh);
+    c.iters += 1;
+    c.rho_prev = c.rho;
+    c.rho = rr;
+    c.beta = rr / c.rho_prev;
+    c.rmax2 = fmax(c.rmax2, rr);
+    if (!(rr > c.tol2) || !isfinite(rr)) {
+        c.flag = 1;
+        c.active = 0;
+    } else if (mixed && rr < 0.01 * c.rmax2) {
+        c.flag = 2;  // reliable update due at the next host check; the column keeps iterating
+    }
+    if (c.iters >= c.maxit) c.active = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st_next[col] = c;
+    const bool cont = c.active != 0;
+    const R aR = (R)a, b = (R)c.beta;
+    XT* xc = x + col * ldx;
+    R* pc = p + col * ld;
+    const R* rc = r + col * ld;
+    const int64_t stride = (int64_t)gridDim.x * kBlock * W;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W; i0 < N; i0 += stride) {
+        if (VEC && sizeof(XT) == sizeof(R) && i0 + W <= N) {
+            Pack<R> xv = ldp((R*)xc, i0), pv = ldp(pc, i0);
+#pragma unroll
+            for (int e = 0; e < W; ++e) xv.v[e] = xv.v[e] + aR * pv.v[e];
+            stp((R*)xc, i0, xv);
+            if (cont) {
+                const Pack<R> rv = ldp(rc, i0);
+#pragma unroll
+                for (int e = 0; e < W; ++e) pv.v[e] = rv.v[e] + b * pv.v[e];
+                stp(pc, i0, pv);
+            }
+        } else {
+            for (int64_t j = i0; j < min(N, i0 + W); ++j) {
+                const R pj = pc[j];
+                xc[j] = (XT)(xc[j] + (XT)aR * (XT)pj);
+                if (cont) pc[j] = rc[j] + b * pj;
+            }
         }
     }
 }
@@ -334,6 +383,22 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
         for (int j = 0; j < k; ++j) any |= hst[j].active != 0;
         while (any) {
             for (int it = 0; it < chunk; ++it) {
+                // fused form (Wilson, t-march shape): D pass with <p, A p> partials, D^H pass
+                // finishing r -= alpha A p, then x += alpha p and p = r + beta p
+                int gf = 0;
+                SC_TRY(wilson_cg_fused(op, mixed, p, w.tmp, k, w.st[cur], w.part_pq, r, op->n, w.part_rr,
+                                       kMaxRedBlocks, &gf, s));
+                if (gf > 0) {
+                    if (mixed)
+                        hipLaunchKernelGGL((k_cg_xp<float, R, VEC>), grid, blk, 0, s, (float*)w.xs, N2, p, r, N2, N2,
+                                           w.st[cur], w.st[1 - cur], w.part_pq, w.part_rr, gf, 1);
+                    else
+                        hipLaunchKernelGGL((k_cg_xp<double, R, VEC>), grid, blk, 0, s, X, ldx2, p, r, N2, N2,
+                                           w.st[cur], w.st[1 - cur], w.part_pq, w.part_rr, gf, 0);
+                    SC_LAUNCH_CHECK();
+                    cur = 1 - cur;
+                    continue;
+                }
                 // q = A p; for A = D^H D the D pass can also leave <p, q> = ||D p||^2
                 int gpq = 0;
                 SC_TRY(op_apply_norm(op, mixed, p, op->n, q, op->n, k, w.tmp, w.part_pq, kMaxRedBlocks, &gpq, s));

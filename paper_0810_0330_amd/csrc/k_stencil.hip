@@ -273,14 +273,27 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson_r(R* __restrict__ out, 
 // XCD) or (segment, z, column group) with the column group fastest (CGMINOR =
 // true: all column groups of a plane share its links through one L2).
 //
-// NORM: the block also leaves, per column, the partial sum of |out|^2 over its
-// sites in norm_part[column * (Z * nseg) + (segment * Z + z)] (for A = D^H D,
-// <p, A p> = ||D p||^2, so CG needs no separate reduction over p and A p).
-template <typename R, bool DAG, int MODE, int NC, bool CGMINOR, bool NORM = false>
+// Epilogues (EPI), with the block's partial sums left per column at index
+// column * (Z * nseg) + (segment * Z + z) of e.part:
+//   TM_NORM: out is written and the partials are of |out|^2 (for A = D^H D,
+//     <p, A p> = ||D p||^2, so CG needs no separate reduction over p and A p);
+//   TM_CG: out (= A p of a CG iteration) is not stored; for the columns active
+//     in e.st, r -= alpha out with alpha = rho / (sum of e.pq's partials), and
+//     the partials are of |r|^2.
+enum { TM_PLAIN = 0, TM_NORM = 1, TM_CG = 2 };
+struct TmEpi {
+    double* part;
+    const CGCol* st;
+    const double* pq;
+    void* r;
+    int64_t ldr;  // reals
+};
+
+template <typename R, bool DAG, int MODE, int NC, bool CGMINOR, int EPI = TM_PLAIN>
 __global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64_t ldo, const R* __restrict__ in,
                                                       int64_t ldi, const R* __restrict__ U, Geom g, R kappa,
                                                       R tsign, int k, int ncg, int nseg, int tlen, int per_xcd,
-                                                      double* __restrict__ norm_part = nullptr) {
+                                                      TmEpi e = TmEpi{}) {
     using V2 = typename vec2<R>::type;
     __shared__ V2 pl[NC * 12][kBlock];
     __shared__ double nsh[kWaves];
@@ -312,6 +325,18 @@ __global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64
     for (int c = 0; c < NC; ++c) {
         live[c] = c0 + c < k;
         src[c] = in + (int64_t)(live[c] ? c0 + c : c0) * ldi;
+    }
+    R alpha[NC];
+    bool upd[NC];
+    if constexpr (EPI == TM_CG) {
+        const int G = g.Z * nseg;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int col = live[c] ? c0 + c : c0;
+            const double pq = sum_partials(e.pq + (int64_t)col * G, G, nsh);  // every thread: uniform
+            upd[c] = live[c] && e.st[col].active;
+            alpha[c] = upd[c] ? (R)(e.st[col].rho / pq) : R(0);
+        }
     }
 
     // carry into slice t0 from slice t0 - 1
@@ -403,16 +428,27 @@ __global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64
                 hop<3, SF, false>(acc[c], psi, u, bfp);
                 hop_half<3, SB, true>(cur[c], u, R(1), cr0[c], cr1[c]);
                 // write this slice's result, then advance
-                if (live[c]) {
+                if (EPI == TM_CG ? upd[c] : live[c]) {
                     R* dst = out + (int64_t)(c0 + c) * ldo;
+                    R* rv = (R*)e.r + (int64_t)(c0 + c) * e.ldr;
 #pragma unroll
                     for (int a = 0; a < 4; ++a)
 #pragma unroll
                         for (int cc = 0; cc < 3; ++cc) {
                             cplx<R> r = acc[c][a][cc];
                             if constexpr (MODE == 0) r = {cur[c][a][cc].re - kappa * r.re, cur[c][a][cc].im - kappa * r.im};
-                            reinterpret_cast<V2*>(dst + 2 * (size_t)((a * 3 + cc) * uV))[s] = V2{r.re, r.im};
-                            if constexpr (NORM) nacc[c] += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
+                            const size_t off = 2 * (size_t)((a * 3 + cc) * uV);
+                            if constexpr (EPI == TM_CG) {
+                                V2 rr = reinterpret_cast<V2*>(rv + off)[s];
+                                rr.x = rr.x - alpha[c] * r.re;
+                                rr.y = rr.y - alpha[c] * r.im;
+                                reinterpret_cast<V2*>(rv + off)[s] = rr;
+                                nacc[c] += (double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y;
+                            } else {
+                                reinterpret_cast<V2*>(dst + off)[s] = V2{r.re, r.im};
+                                if constexpr (EPI == TM_NORM)
+                                    nacc[c] += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
+                            }
                         }
                 }
 #pragma unroll
@@ -422,11 +458,11 @@ __global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64
             }
         }
     }
-    if constexpr (NORM) {
+    if constexpr (EPI != TM_PLAIN) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const double tot = block_sum(nacc[c], nsh);
-            if (threadIdx.x == 0 && live[c]) norm_part[(int64_t)(c0 + c) * (g.Z * nseg) + seg * g.Z + z] = tot;
+            if (threadIdx.x == 0 && live[c]) e.part[(int64_t)(c0 + c) * (g.Z * nseg) + seg * g.Z + z] = tot;
         }
     }
 }
@@ -514,7 +550,7 @@ static bool tmarch_ok(const sc_op* op) { return op->dims[0] * op->dims[1] == kBl
 
 template <typename R, int NC, bool CGMINOR>
 static void wilson_launch_tm(const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k,
-                             const R* U, int tlen, hipStream_t s, double* norm_part = nullptr) {
+                             const R* U, int tlen, hipStream_t s, int epi = TM_PLAIN, TmEpi e = TmEpi{}) {
     Geom g{op->dims[0], op->dims[1], op->dims[2], op->dims[3], op->vol};
     tlen = std::max(1, std::min(tlen, g.T));
     const int nseg = (g.T + tlen - 1) / tlen;
@@ -525,10 +561,15 @@ static void wilson_launch_tm(const sc_op* op, int which, const R* X, int64_t ldx
     const R ts = op->antiperiodic ? R(-1) : R(1);
 #define SC_WT(DAG, MODE)                                                                                   \
     hipLaunchKernelGGL((k_wilson_tm<R, DAG, MODE, NC, CGMINOR>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,      \
-                       2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, nullptr);
-    if (norm_part && which == 0) {  // D pass with the |D x|^2 partials
-        hipLaunchKernelGGL((k_wilson_tm<R, false, 0, NC, CGMINOR, true>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,
-                           2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, norm_part);
+                       2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, TmEpi{});
+    if (epi == TM_NORM) {  // D pass with the |D x|^2 partials
+        hipLaunchKernelGGL((k_wilson_tm<R, false, 0, NC, CGMINOR, TM_NORM>), grid, dim3(kBlock), 0, s, Y, 2 * ldy,
+                           X, 2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, e);
+        return;
+    }
+    if (epi == TM_CG) {  // D^H pass finishing r -= alpha A p
+        hipLaunchKernelGGL((k_wilson_tm<R, true, 0, NC, CGMINOR, TM_CG>), grid, dim3(kBlock), 0, s, Y, 2 * ldy,
+                           X, 2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, e);
         return;
     }
     switch (which) {
@@ -780,6 +821,19 @@ static void tm_params(int v, int* tlen, int* form, bool* cgminor) {
 }
 
 template <typename R>
+static void tm_launch(const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k, const R* U,
+                      int tlen, int form, bool cgminor, int epi, const TmEpi& e, hipStream_t s) {
+    constexpr int N2 = sizeof(R) == 4 ? 2 : 1;  // FP64 with 2 columns would spill
+    if (form == 0) {
+        if (cgminor) wilson_launch_tm<R, 1, true>(op, which, X, ldx, Y, ldy, k, U, tlen, s, epi, e);
+        else wilson_launch_tm<R, 1, false>(op, which, X, ldx, Y, ldy, k, U, tlen, s, epi, e);
+    } else {
+        if (cgminor) wilson_launch_tm<R, N2, true>(op, which, X, ldx, Y, ldy, k, U, tlen, s, epi, e);
+        else wilson_launch_tm<R, N2, false>(op, which, X, ldx, Y, ldy, k, U, tlen, s, epi, e);
+    }
+}
+
+template <typename R>
 static sc_status wilson_d_norm(const sc_op* op, const R* X, int64_t ldx, R* Y, int64_t ldy, int k, const R* U,
                                double* part, int max_parts, int* G, hipStream_t s) {
     *G = 0;
@@ -794,17 +848,65 @@ static sc_status wilson_d_norm(const sc_op* op, const R* X, int64_t ldx, R* Y, i
     const double bytes = (48.0 * k + 72.0) * sizeof(R) * (double)op->vol;
     const int cls = sizeof(R) == 4 ? (k == 1 ? TC_WILSON_F32 : TC_WILSON_F32_K) : (k == 1 ? TC_WILSON_F64 : TC_WILSON_F64_K);
     TimerScope ts_(cls, s, bytes, 1368.0 * k * (double)op->vol);
-    constexpr int N2 = sizeof(R) == 4 ? 2 : 1;
-    if (form == 0) {
-        if (cgminor) wilson_launch_tm<R, 1, true>(op, 0, X, ldx, Y, ldy, k, U, tlen, s, part);
-        else wilson_launch_tm<R, 1, false>(op, 0, X, ldx, Y, ldy, k, U, tlen, s, part);
-    } else {
-        if (cgminor) wilson_launch_tm<R, N2, true>(op, 0, X, ldx, Y, ldy, k, U, tlen, s, part);
-        else wilson_launch_tm<R, N2, false>(op, 0, X, ldx, Y, ldy, k, U, tlen, s, part);
-    }
+    TmEpi e{};
+    e.part = part;
+    tm_launch<R>(op, 0, X, ldx, Y, ldy, k, U, tlen, form, cgminor, TM_NORM, e, s);
     SC_LAUNCH_CHECK();
     *G = parts;
     return SC_OK;
+}
+
+template <typename R>
+static sc_status wilson_cg_fused_t(const sc_op* op, const R* p, R* tmp, int k, const R* U, const CGCol* st,
+                                   double* part_pq, R* r, int64_t ldr, double* part_rr, int max_parts, int* G,
+                                   hipStream_t s) {
+    *G = 0;
+    if (!tmarch_ok(op)) return SC_OK;
+    const int v = choose_variant<R>(op, 0, p, op->n, tmp, op->n, k, U, s);
+    if (v < WV_TILED || v >= WV_DIR) return SC_OK;
+    int tlen, form;
+    bool cgminor;
+    tm_params(v, &tlen, &form, &cgminor);
+    tlen = std::max(1, std::min(tlen, op->dims[3]));
+    const int parts = op->dims[2] * ((op->dims[3] + tlen - 1) / tlen);
+    if (parts > max_parts) return SC_OK;
+    const double bytes = (48.0 * k + 72.0) * sizeof(R) * (double)op->vol;
+    const int cls = sizeof(R) == 4 ? (k == 1 ? TC_WILSON_F32 : TC_WILSON_F32_K) : (k == 1 ? TC_WILSON_F64 : TC_WILSON_F64_K);
+    {
+        TimerScope ts_(cls, s, bytes, 1368.0 * k * (double)op->vol);
+        TmEpi e{};
+        e.part = part_pq;
+        tm_launch<R>(op, 0, p, op->n, tmp, op->n, k, U, tlen, form, cgminor, TM_NORM, e, s);
+        SC_LAUNCH_CHECK();
+    }
+    {
+        // D^H pass: reads tmp, reads and writes r (A p is not stored): 72k + 72 reals per site
+        TimerScope ts_(cls, s, (72.0 * k + 72.0) * sizeof(R) * (double)op->vol, 1368.0 * k * (double)op->vol);
+        TmEpi e{};
+        e.part = part_rr;
+        e.st = st;
+        e.pq = part_pq;
+        e.r = r;
+        e.ldr = 2 * ldr;
+        tm_launch<R>(op, 1, tmp, op->n, tmp, op->n, k, U, tlen, form, cgminor, TM_CG, e, s);
+        SC_LAUNCH_CHECK();
+    }
+    *G = parts;
+    return SC_OK;
+}
+
+sc_status wilson_cg_fused(const sc_op* op, bool single, const void* p, void* tmp, int k, const CGCol* st,
+                          double* part_pq, void* r, int64_t ldr, double* part_rr, int max_parts, int* G,
+                          hipStream_t s) {
+    *G = 0;
+    if (op->kind != SC_OPK_WILSON || k <= 0) return SC_OK;
+    if (single) {
+        if (!op->U32) return SC_OK;
+        return wilson_cg_fused_t<float>(op, (const float*)p, (float*)tmp, k, (const float*)op->U32, st, part_pq,
+                                        (float*)r, ldr, part_rr, max_parts, G, s);
+    }
+    return wilson_cg_fused_t<double>(op, (const double*)p, (double*)tmp, k, (const double*)op->U64, st, part_pq,
+                                     (double*)r, ldr, part_rr, max_parts, G, s);
 }
 
 sc_status op_apply_norm(const sc_op* op, bool single, const void* X, int64_t ldx, void* Y, int64_t ldy, int k,

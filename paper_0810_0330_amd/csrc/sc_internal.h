@@ -39,6 +39,32 @@ sc_status op_apply(const sc_op* op, bool single, const void* X, int64_t ldx, voi
                    void* tmp, hipStream_t s);
 // elements of scratch op_apply needs per column
 int64_t op_apply_tmp_elems(const sc_op* op);
+
+// Per-column state of the batched CG (cg.hip), read by the fused stencil epilogue.
+struct CGCol {
+    double rho;      // ||r||^2 of the current recurrence
+    double rho_prev; // rho of the previous iteration
+    double beta;     // rho / rho_prev
+    double bnorm2;   // ||b||^2
+    double tol2;     // tol^2 ||b||^2
+    double rmax2;    // largest ||r||^2 since the last reliable update
+    int active;      // iterating
+    int iters;       // A-applies inside the loop so far
+    int maxit;
+    int flag;        // 1: recursive residual at tol; 2: mixed, reliable update due
+};
+
+// One CG iteration's operator work for the Wilson normal operator, fused,
+// when the tuned stencil shape for (lattice, precision, k) is a t-march one:
+// tmp = D p with partials of ||D p_j||^2 = <p_j, A p_j> in part_pq, then the
+// D^H pass, whose epilogue applies r_j -= alpha_j (A p_j) with alpha_j =
+// rho_j / <p_j, A p_j> for the active columns of st and leaves partials of
+// ||r_j||^2 in part_rr (A p is not stored).  *G = partials per column (both
+// arrays, index j * G + i), or 0 when the fused form does not apply (nothing
+// was launched).
+sc_status wilson_cg_fused(const sc_op* op, bool single, const void* p, void* tmp, int k, const CGCol* st,
+                          double* part_pq, void* r, int64_t ldr, double* part_rr, int max_parts, int* G,
+                          hipStream_t s);
 // Y = A X; for the Wilson normal operator, when the tuned D-pass shape can, it
 // also leaves per-column partial sums of ||D x_j||^2 = <x_j, A x_j> in
 // part[j * G + i] (i < G <= max_parts) and sets G; otherwise G = 0.
