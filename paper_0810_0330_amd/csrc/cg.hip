@@ -26,6 +26,7 @@
 // stops; CG restarts from the true residual if it is still above tol).
 #include "sc_internal.h"
 
+#include <cmath>
 #include <vector>
 
 namespace sc {
@@ -356,7 +357,13 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
     const dim3 grid(g, k);
     std::vector<CGCol> hst(k);
     std::vector<double> hrr(k);
-    const int chunk = 8;
+    // iterations between host checks: at most kChunk, fewer when every active
+    // column's residual decay since the previous check says it will reach tol
+    // sooner (the check then comes when the last column converges)
+    constexpr int kChunk = 8;
+    int chunk = kChunk;
+    std::vector<double> chk_rho(k, 0.0);
+    std::vector<int> chk_it(k, -1);
     int cur = 0;  // index of the state copy the next iteration reads
 
     SC_TRY(dot(0, B, ldb2, 0, B, ldb2, N2, k, w.bn, w.part, nullptr, s));
@@ -423,10 +430,23 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
             SC_HIP(hipStreamSynchronize(s));
             any = false;
             std::vector<int> upd;
+            int need = 0;  // iterations the slowest active column still needs, as estimated
             for (int j = 0; j < k; ++j) {
                 any |= hst[j].active != 0;
                 if (mixed && hst[j].flag != 0 && hst[j].iters < hst[j].maxit) upd.push_back(j);
+                if (hst[j].active) {
+                    const int di = hst[j].iters - chk_it[j];
+                    double est = kChunk;
+                    if (chk_it[j] >= 0 && di > 0 && hst[j].rho < chk_rho[j] && hst[j].rho > hst[j].tol2) {
+                        const double rate = std::log(hst[j].rho / chk_rho[j]) / di;  // < 0
+                        est = std::ceil(std::log(hst[j].tol2 / hst[j].rho) / rate);
+                    }
+                    need = std::max(need, (int)std::min<double>(kChunk, std::max(1.0, est)));
+                }
+                chk_rho[j] = hst[j].rho;
+                chk_it[j] = hst[j].iters;
             }
+            chunk = need > 0 ? need : kChunk;
             if (!upd.empty()) {
                 // reliable update of the flagged columns (batched over the list):
                 // x64 += xs; xs = 0; r64 = b - A64 x64; r = r64; then the direction
@@ -474,6 +494,11 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
                 }
                 SC_HIP(hipMemcpyAsync(w.st[cur], hst.data(), sizeof(CGCol) * k, hipMemcpyHostToDevice, s));
                 SC_HIP(hipStreamSynchronize(s));
+                // the updated columns measure their decay from the true residual on
+                for (int c = 0; c < nu; ++c) {
+                    chk_rho[upd[c]] = hst[upd[c]].rho;
+                    chk_it[upd[c]] = hst[upd[c]].iters;
+                }
             }
         }
         if (mixed) {
