@@ -20,7 +20,7 @@
 // mixed = 1: the vectors and the operator run in FP32; x and the true
 // residual are FP64.  A reliable update (x64 += x32, r = b - A64 x64, r32 =
 // r, x32 = 0) is made for every column whose FP32 residual norm has fallen by
-// 10x since its last update, at the next host check (the column keeps
+// 100x since its last update, at the next host check (the column keeps
 // iterating meanwhile, so no column idles; p is kept and CG continues with
 // the true residual), and when the FP32 residual reaches tol (the column
 // stops; CG restarts from the true residual if it is still above tol).
@@ -30,6 +30,10 @@
 #include <vector>
 
 namespace sc {
+
+// Mixed precision: a column's reliable update is due once its FP32 residual
+// norm is 100x below the largest since its last update (squared: 1e-4).
+constexpr double kRelUpdate2 = 1e-4;
 
 __global__ void k_cg_setup(CGCol* st, const double* rho, const double* bn, int k, double tol, int maxit, int first) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -140,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_p(R* __restrict__ p, const R* __r
     if (!(rr > c.tol2) || !isfinite(rr)) {
         c.flag = 1;
         c.active = 0;
-    } else if (mixed && rr < 0.01 * c.rmax2) {
+    } else if (mixed && rr < kRelUpdate2 * c.rmax2) {
         c.flag = 2;  // reliable update due at the next host check; the column keeps iterating
     }
     if (c.iters >= c.maxit) c.active = 0;
@@ -189,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_xp(XT* __restrict__ x, int64_t ld
     if (!(rr > c.tol2) || !isfinite(rr)) {
         c.flag = 1;
         c.active = 0;
-    } else if (mixed && rr < 0.01 * c.rmax2) {
+    } else if (mixed && rr < kRelUpdate2 * c.rmax2) {
         c.flag = 2;  // reliable update due at the next host check; the column keeps iterating
     }
     if (c.iters >= c.maxit) c.active = 0;
@@ -233,12 +237,12 @@ __global__ __launch_bounds__(kBlock) void k_ru_gather(const int* __restrict__ co
     const int j = cols[c];
     double* x = X + j * ldx;
     float* a = xs + j * N;
-    double* o = xg + c * N;
+    double* o = xg ? xg + c * N : nullptr;  // no copy when every column is updated (A x64 reads X itself)
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock) {
         const double v = x[i] + (double)a[i];
         x[i] = v;
         a[i] = 0.0f;
-        o[i] = v;
+        if (o) o[i] = v;
     }
 }
 
@@ -453,9 +457,12 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
                 const int nu = (int)upd.size();
                 const int gr = red_grid(N2, 4);
                 SC_HIP(hipMemcpyAsync(w.cols, upd.data(), sizeof(int) * nu, hipMemcpyHostToDevice, s));
-                hipLaunchKernelGGL(k_ru_gather, dim3(gr, nu), blk, 0, s, w.cols, X, ldx2, (float*)w.xs, w.xg, N2);
+                const bool all = nu == k;  // the list is then 0..k-1 in order
+                hipLaunchKernelGGL(k_ru_gather, dim3(gr, nu), blk, 0, s, w.cols, X, ldx2, (float*)w.xs,
+                                   all ? nullptr : w.xg, N2);
                 SC_LAUNCH_CHECK();
-                SC_TRY(op_apply(op, false, w.xg, op->n, w.ax64, op->n, nu, w.tmp64, s));
+                if (all) SC_TRY(op_apply(op, false, X, ldx, w.ax64, op->n, nu, w.tmp64, s));
+                else SC_TRY(op_apply(op, false, w.xg, op->n, w.ax64, op->n, nu, w.tmp64, s));
                 hipLaunchKernelGGL(k_ru_resid, dim3(gr, nu), blk, 0, s, w.cols, B, ldb2, w.ax64, w.r64, (float*)r, N2,
                                    w.part);
                 SC_LAUNCH_CHECK();
