@@ -560,15 +560,15 @@ static void wilson_launch_tm(const sc_op* op, int which, const R* X, int64_t ldx
     const R kap = (R)op->kappa;
     const R ts = op->antiperiodic ? R(-1) : R(1);
 #define SC_WT(DAG, MODE)                                                                                   \
-    hipLaunchKernelGGL((k_wilson_tm<R, DAG, MODE, NC, CGMINOR>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,      \
+    SC_TLAUNCH((k_wilson_tm<R, DAG, MODE, NC, CGMINOR>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,      \
                        2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, TmEpi{});
     if (epi == TM_NORM) {  // D pass with the |D x|^2 partials
-        hipLaunchKernelGGL((k_wilson_tm<R, false, 0, NC, CGMINOR, TM_NORM>), grid, dim3(kBlock), 0, s, Y, 2 * ldy,
+        SC_TLAUNCH((k_wilson_tm<R, false, 0, NC, CGMINOR, TM_NORM>), grid, dim3(kBlock), 0, s, Y, 2 * ldy,
                            X, 2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, e);
         return;
     }
     if (epi == TM_CG) {  // D^H pass finishing r -= alpha A p
-        hipLaunchKernelGGL((k_wilson_tm<R, true, 0, NC, CGMINOR, TM_CG>), grid, dim3(kBlock), 0, s, Y, 2 * ldy,
+        SC_TLAUNCH((k_wilson_tm<R, true, 0, NC, CGMINOR, TM_CG>), grid, dim3(kBlock), 0, s, Y, 2 * ldy,
                            X, 2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, e);
         return;
     }
@@ -591,7 +591,7 @@ static void wilson_launch_dir(const sc_op* op, int which, const R* X, int64_t ld
     const R kap = (R)op->kappa;
     const R ts = op->antiperiodic ? R(-1) : R(1);
 #define SC_WD(DAG, MODE)                                                                                         \
-    hipLaunchKernelGGL((k_wilson_dir<R, DAG, MODE>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X, 2 * ldx, U, g, kap, \
+    SC_TLAUNCH((k_wilson_dir<R, DAG, MODE>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X, 2 * ldx, U, g, kap, \
                        ts, k, ntile, per_xcd);
     switch (which) {
         case 0: SC_WD(false, 0) break;
@@ -617,10 +617,10 @@ static void wilson_launch_v(const sc_op* op, int which, const R* X, int64_t ldx,
     // ld arguments are in reals (2 per complex element)
 #define SC_WL(DAG, MODE)                                                                                       \
     if (ROLLED)                                                                                                \
-        hipLaunchKernelGGL((k_wilson_r<R, DAG, MODE, NC, 1>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,         \
+        SC_TLAUNCH((k_wilson_r<R, DAG, MODE, NC, 1>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,         \
                            2 * ldx, U, g, kap, ts, k, ncg, ntiles, per_xcd, G, zb);                            \
     else                                                                                                       \
-        hipLaunchKernelGGL((k_wilson<R, DAG, MODE, NC, 1, false>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,    \
+        SC_TLAUNCH((k_wilson<R, DAG, MODE, NC, 1, false>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,    \
                            2 * ldx, U, g, kap, ts, k, ncg, ntiles, per_xcd, G, zb);
     switch (which) {
         case 0: SC_WL(false, 0) break;

@@ -461,11 +461,11 @@ static void cn_launch(const CnPlan& p, const VR* V, int64_t ldv, int64_t n, int 
                       double* part, const int* halt, hipStream_t s) {
     dim3 grid((unsigned)p.nchunk, (unsigned)((M + p.tm - 1) / p.tm));
     if (N <= 2)
-        hipLaunchKernelGGL((k_cn_partial<VR, WR, CPLX, 128, 1, 16>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
+        SC_TLAUNCH((k_cn_partial<VR, WR, CPLX, 128, 1, 16>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
     else if (N <= 8)
-        hipLaunchKernelGGL((k_cn_partial<VR, WR, CPLX, 32, 1, 64>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
+        SC_TLAUNCH((k_cn_partial<VR, WR, CPLX, 32, 1, 64>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
     else
-        hipLaunchKernelGGL((k_cn_partial<VR, WR, CPLX, 32, 4, 64>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
+        SC_TLAUNCH((k_cn_partial<VR, WR, CPLX, 32, 4, 64>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
 }
 
 template <typename VR, typename WR>
@@ -476,12 +476,12 @@ static void cn_mfma_launch(const CnPlan& p, const VR* V, int64_t ldv, int64_t n,
     const int per_xcd = (p.nchunk * mblk + kXcd - 1) / kXcd;
     dim3 grid1((unsigned)(per_xcd * kXcd));
     if (N <= 2)
-        hipLaunchKernelGGL((k_cn_small<VR, WR>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
+        SC_TLAUNCH((k_cn_small<VR, WR>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
     else if (N <= 16)
-        hipLaunchKernelGGL((k_cn_mfma<VR, WR, 1>), grid1, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows,
+        SC_TLAUNCH((k_cn_mfma<VR, WR, 1>), grid1, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows,
                            p.nchunk, halt);
     else
-        hipLaunchKernelGGL((k_cn_mfma<VR, WR, 2>), grid1, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows,
+        SC_TLAUNCH((k_cn_mfma<VR, WR, 2>), grid1, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows,
                            p.nchunk, halt);
 }
 
@@ -646,23 +646,23 @@ static void nn_launch(const VR* V, int64_t ldv, int64_t n, int M, const double* 
     if (CPLX && N > 2) {
         dim3 gm((unsigned)((n + 63) / 64));
         if (N <= 16)
-            hipLaunchKernelGGL((k_nn_mfma<VR, XR, 1>), gm, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
+            SC_TLAUNCH((k_nn_mfma<VR, XR, 1>), gm, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
         else
-            hipLaunchKernelGGL((k_nn_mfma<VR, XR, 2>), gm, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
+            SC_TLAUNCH((k_nn_mfma<VR, XR, 2>), gm, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
         return;
     }
     if (CPLX && N <= 2) {
         dim3 gs((unsigned)((n + kBlock * kNnRPT - 1) / (kBlock * kNnRPT)));
-        hipLaunchKernelGGL((k_nn_small<VR, XR>), gs, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
+        SC_TLAUNCH((k_nn_small<VR, XR>), gs, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
         return;
     }
     dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
     if (N <= 2)
-        hipLaunchKernelGGL((k_nn<VR, XR, CPLX, 2>), grid, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
+        SC_TLAUNCH((k_nn<VR, XR, CPLX, 2>), grid, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
     else if (N <= 8)
-        hipLaunchKernelGGL((k_nn<VR, XR, CPLX, 8>), grid, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
+        SC_TLAUNCH((k_nn<VR, XR, CPLX, 8>), grid, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
     else
-        hipLaunchKernelGGL((k_nn<VR, XR, CPLX, 32>), grid, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
+        SC_TLAUNCH((k_nn<VR, XR, CPLX, 32>), grid, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
 }
 
 sc_status gemm_nn(bool cplx, bool vsingle, const void* V, int64_t ldv, int64_t n, int M, const double* Y, int N,

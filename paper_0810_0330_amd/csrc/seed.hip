@@ -424,13 +424,13 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
                 SC_TRY(wilson_pass(op, single, 0, vi, ldv, tmpv, op->n, 1, s));
             } else {
                 TimerScope ts_(tcls, s, pass_bytes + 24.0 * sizeof(R) * op->vol, 1368.0 * op->vol);
-                hipLaunchKernelGGL((k_lz_dnext<R, R>), dgrid, blk, 0, s, tmpv, (const R*)f, vi, U, geo, kapR, tsg,
+                SC_TLAUNCH((k_lz_dnext<R, R>), dgrid, blk, 0, s, tmpv, (const R*)f, vi, U, geo, kapR, tsg,
                                    ntile, per_xcd, beta, i - 1, w.st, w.part_f, gf);
                 SC_LAUNCH_CHECK();
             }
             {
                 TimerScope ts_(tcls, s, pass_bytes + 48.0 * sizeof(R) * op->vol, 1368.0 * op->vol);
-                hipLaunchKernelGGL((k_lz_dhalpha<R>), dgrid, blk, 0, s, f, (const R*)tmpv, (const R*)vi,
+                SC_TLAUNCH((k_lz_dhalpha<R>), dgrid, blk, 0, s, f, (const R*)tmpv, (const R*)vi,
                                    (const R*)vprev, U, geo, kapR, tsg, ntile, per_xcd, beta, i, w.st, w.part_a);
                 SC_LAUNCH_CHECK();
             }

@@ -50,24 +50,39 @@ hipEvent_t take_event() {
 
 bool timer_on() { return g_on; }
 
+namespace {
+thread_local TimerScope* t_current = nullptr;
+}
+
+TimerScope* TimerScope::current() { return t_current; }
+
+void TimerScope::launched() {
+    used_ = true;
+    t_current = prev_;
+}
+
 TimerScope::TimerScope(int cls, hipStream_t s, double bytes, double flops)
-    : cls_(cls), s_(s), bytes_(bytes), flops_(flops), a_(nullptr) {
+    : cls_(cls), s_(s), bytes_(bytes), flops_(flops), a_(nullptr), b_(nullptr), used_(false), prev_(t_current) {
     if (!g_on) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;  // not in graphs
     std::lock_guard<std::mutex> lk(g_mu);
     if (cls < 0 || cls >= TC_COUNT || !sampled(cls)) return;
     a_ = take_event();
-    if (a_) hipEventRecord((hipEvent_t)a_, s_);
+    b_ = a_ ? take_event() : nullptr;
+    if (!b_) {
+        a_ = nullptr;
+        return;
+    }
+    t_current = this;
 }
 
 TimerScope::~TimerScope() {
     if (!a_) return;
+    if (t_current == this) t_current = prev_;
+    if (!used_) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    hipEvent_t b = take_event();
-    if (!b) return;
-    hipEventRecord(b, s_);
-    g_recs.push_back({(hipEvent_t)a_, b, cls_, bytes_, flops_});
+    g_recs.push_back({(hipEvent_t)a_, (hipEvent_t)b_, cls_, bytes_, flops_});
 }
 
 sc_status timer_enable(int every) {
