@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--compare-seeding", action="store_true",
                     help="A-applies, vector operations and time of no / multiple / single seeding on the workload "
                          "(Section 2, Table 2.1 analogue) instead of the benchmark")
+    ap.add_argument("--pin-stencil", type=int, default=None, metavar="V",
+                    help="pin the stencil launch shape of the multi-column passes instead of autotuning it "
+                         "(for reproducible counter runs)")
     ap.add_argument("--variant", type=int, default=None,
                     help="--micro wilson_*: pin this stencil launch shape instead of autotuning")
     return ap.parse_args()
@@ -279,8 +282,9 @@ def workload(args):
 def measured_traffic(cls, k, variant, dims):
     """HBM bytes per launch of a stencil class from the committed rocprofv3 counter record.
 
-    None unless the record holds this class, column count, launch shape and
-    lattice, and the stencil source still hashes to what was profiled.
+    None unless the record holds this class, column count, lattice and (where the
+    class depends on it) launch shape, and every source it lists still hashes to
+    what was profiled.  A class's traffic is the mean over its kernels.
     """
     import hashlib
 
@@ -289,13 +293,17 @@ def measured_traffic(cls, k, variant, dims):
         return None
     rec = json.load(open(path))
     cal = rec["calibration"]
-    for e in rec["kernels"]:
-        if (e["class"], e["k"], e["variant"], list(e["dims"])) != (cls, k, variant, list(dims)):
+    for c in rec["classes"]:
+        if (c["class"], c["k"], list(c["dims"])) != (cls, k, list(dims)):
             continue
-        src = open(os.path.join(ROOT, e["source"]), "rb").read()
-        if hashlib.sha256(src).hexdigest() != e["source_sha256"]:
-            return None
-        return e["fetch_kib"] * 1024 * cal["fetch_factor"] + e["write_kib"] * 1024 * cal["write_factor"]
+        if c["variant"] is not None and c["variant"] != variant:
+            continue
+        for src, digest in c["sources"].items():
+            if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != digest:
+                return None
+        ks = c["kernels"]
+        return sum(e["fetch_kib"] * 1024 * cal["fetch_factor"] + e["write_kib"] * 1024 * cal["write_factor"]
+                   for e in ks) / len(ks)
     return None
 
 
@@ -384,6 +392,8 @@ def main():
         B = torch.from_numpy(api.pack_field(np.ascontiguousarray(inp["B"].T))).to(dev)
     torch.cuda.synchronize()
     log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f} s, n = {op.n}")
+    if args.pin_stencil is not None and w.op == "wilson":
+        op.tune_set(w.nrhs, args.pin_stencil, single=w.precision == "mixed")
     mixed = w.precision == "mixed"
 
     def step():

@@ -1,6 +1,7 @@
 // Operator applies: the 2D Laplacian, the diagonal matrix, and the Wilson-Dirac
 // stencil D = 1 - kappa H, its adjoint, and the hopping term alone, in several
 // launch shapes chosen by an autotuner.  The hop arithmetic is in wilson_dev.h.
+#include <algorithm>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -728,13 +729,18 @@ static TuneRec tune_variants(const sc_op* op, int which, const R* X, int64_t ldx
         rec.us[v] = -1.0f;
         if (!variant_applies(op, v, sizeof(R) == 4, k)) continue;
         wilson_launch_variant<R>(v, op, which, X, ldx, Y, ldy, k, U, s);  // warm
-        hipEventRecord(e0, s);
-        for (int r = 0; r < 3; ++r) wilson_launch_variant<R>(v, op, which, X, ldx, Y, ldy, k, U, s);
-        hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) break;
-        float ms = 0.0f;
-        hipEventElapsedTime(&ms, e0, e1);
-        rec.us[v] = ms * 1000.0f / 3.0f;
+        // median of 5 individually timed launches (robust to a stray slow one)
+        float t[5];
+        bool okv = true;
+        for (int r = 0; r < 5 && okv; ++r) {
+            hipEventRecord(e0, s);
+            wilson_launch_variant<R>(v, op, which, X, ldx, Y, ldy, k, U, s);
+            hipEventRecord(e1, s);
+            okv = hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t[r], e0, e1) == hipSuccess;
+        }
+        if (!okv) break;
+        std::sort(t, t + 5);
+        rec.us[v] = t[2] * 1000.0f;
         if (rec.us[v] < best) {
             best = rec.us[v];
             rec.best = v;
