@@ -142,17 +142,22 @@ sc_status sc_wilson_dslash(const sc_op* op, sc_dtype dtype, int which, const voi
  * segments of {4, 8, 16}, c = 1 or 2 columns per thread (2: FP32 only, FP64
  * uses 1), o = 0: the planes of a segment are consecutive work items, 1: the
  * column groups of a plane are.  44: one wave per direction mu and 64
- * sites, the four partial sums added in LDS (for few columns).
+ * sites, the four partial sums added in LDS (for few columns).  45..56 and
+ * 57..68: the t-march shapes of 32..43 (numbered alike from 45 and 57) with
+ * blocks of 2 and 4 consecutive z-planes, whose z neighbours inside the
+ * block are staged in LDS too; where the planes do not fit LDS (4 planes of
+ * 2 columns, FP64 beyond 2 planes) or do not divide Z, the launch uses the
+ * next smaller plane count.
  * us (host, SC_WILSON_VARIANTS floats): measured microseconds per pass of each
  * candidate (-1 if not run). */
-#define SC_WILSON_VARIANTS 45
+#define SC_WILSON_VARIANTS 69
 sc_status sc_wilson_tune_info(const sc_op* op, sc_dtype dtype, int k, int* variant, float* us);
 
 /* Pin the stencil launch shape for (this op's lattice, dtype, k) instead of
  * tuning it (variant as above); variant -1 forgets the choice so the next
  * pass tunes again.  Errors: SC_ERR_ARG for a non-Wilson op, k < 1, a
- * variant outside -1..SC_WILSON_VARIANTS-1, or a t-march variant (32..43) on
- * a lattice with X Y != 256. */
+ * variant outside -1..SC_WILSON_VARIANTS-1, or a t-march variant (32..43,
+ * 45..68) on a lattice with X Y != 256. */
 sc_status sc_wilson_tune_set(const sc_op* op, sc_dtype dtype, int k, int variant);
 
 /* ------------------------------------------------------------------ workspace */

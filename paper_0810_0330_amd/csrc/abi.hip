@@ -377,7 +377,7 @@ sc_status sc_wilson_tune_set(const sc_op* op, sc_dtype dtype, int k, int variant
     SC_GUARD_BEGIN
     SC_ARG(op && op->kind == SC_OPK_WILSON, "not a Wilson op");
     SC_ARG(dtype == SC_C128 || dtype == SC_C64, "dtype must be SC_C128 or SC_C64");
-    SC_ARG(k >= 1 && variant >= -1 && variant < SC_WILSON_VARIANTS, "k must be >= 1 and variant in -1..44");
+    SC_ARG(k >= 1 && variant >= -1 && variant < SC_WILSON_VARIANTS, "k must be >= 1 and variant in -1..68");
     return wilson_tune_pin(op, dtype == SC_C64, k, variant);
     SC_GUARD_END
 }

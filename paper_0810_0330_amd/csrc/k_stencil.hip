@@ -263,16 +263,22 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson_r(R* __restrict__ out, 
 }
 
 // t-march form, for lattices whose xy-plane is one 256-site tile.  A block
-// owns the xy-plane at one z for NC columns and walks t through a segment of
-// tlen time slices.  Per slice its spinors are staged in LDS, so the x and y
-// hops read LDS; the +t neighbour is the same lane's next slice, loaded one
-// slice ahead; the -t hop into the next slice, U_t^H (1 + SB gamma_t) psi(t),
-// is formed while the slice is current (its link is the one the +t hop
-// loads) and carried in registers as a half spinor.  Only the z hops read
-// other planes from L2.  Work items enumerate (column group, segment, z) with
-// z fastest (CGMINOR = false: the Z planes of a segment run together on one
-// XCD) or (segment, z, column group) with the column group fastest (CGMINOR =
-// true: all column groups of a plane share its links through one L2).
+// owns the xy-planes of NZ consecutive z (256 threads per plane) for NC
+// columns and walks t through a segment of tlen time slices.  Per slice its
+// spinors are staged in LDS, so the x and y hops read LDS, and so do the z
+// hops between planes of the block; the +t neighbour is the same lane's next
+// slice, loaded one slice ahead; the -t hop into the next slice,
+// U_t^H (1 + SB gamma_t) psi(t), is formed while the slice is current (its
+// link is the one the +t hop loads) and carried in registers as a half
+// spinor.  Only the z hops out of the block's planes read other planes, from
+// L2 or HBM: with one plane per block they re-read each spinor twice, and as
+// a neighbour plane is next read a slice later by another block it has
+// mostly left L2 by then; NZ planes cut that to 2 / NZ.  Work items
+// enumerate (column group, segment, plane group) with the plane group
+// fastest (CGMINOR = false: the planes of a segment run together on one XCD)
+// or (segment, plane group, column group) with the column group fastest
+// (CGMINOR = true: all column groups of a plane share its links through one
+// L2).
 //
 // Epilogues (EPI), with the block's partial sums left per column at index
 // column * (Z * nseg) + (segment * Z + z) of e.part:
@@ -290,27 +296,50 @@ struct TmEpi {
     int64_t ldr;  // reals
 };
 
-template <typename R, bool DAG, int MODE, int NC, bool CGMINOR, int EPI = TM_PLAIN>
-__global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64_t ldo, const R* __restrict__ in,
-                                                      int64_t ldi, const R* __restrict__ U, Geom g, R kappa,
-                                                      R tsign, int k, int ncg, int nseg, int tlen, int per_xcd,
-                                                      TmEpi e = TmEpi{}) {
+// Sum over the 256 threads of plane zz of a block of NZ planes (the tree of
+// block_sum, so the value is that of a one-plane block), and the index-order
+// sum of a producer's partials taken the same way.
+__device__ __forceinline__ double plane_sum(double v, double* sh /* kWaves per plane */, int zz) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = (threadIdx.x >> 6) & (kWaves - 1);
+    __syncthreads();
+    if (lane == 0) sh[zz * kWaves + w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) t += sh[zz * kWaves + i];
+    return t;
+}
+
+__device__ __forceinline__ double plane_sum_partials(const double* __restrict__ part, int G, double* sh, int zz) {
+    double s = 0.0;
+    for (int i = threadIdx.x & (kBlock - 1); i < G; i += kBlock) s += part[i];
+    return plane_sum(s, sh, zz);
+}
+
+template <typename R, bool DAG, int MODE, int NC, bool CGMINOR, int EPI = TM_PLAIN, int NZ = 1>
+__global__ __launch_bounds__(kBlock * NZ) void k_wilson_tm(R* __restrict__ out, int64_t ldo, const R* __restrict__ in,
+                                                           int64_t ldi, const R* __restrict__ U, Geom g, R kappa,
+                                                           R tsign, int k, int ncg, int nseg, int tlen, int per_xcd,
+                                                           TmEpi e = TmEpi{}) {
     using V2 = typename vec2<R>::type;
-    __shared__ V2 pl[NC * 12][kBlock];
-    __shared__ double nsh[kWaves];
+    __shared__ V2 pl[NZ][NC * 12][kBlock];
+    __shared__ double nsh[kWaves * NZ];
     double nacc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) nacc[c] = 0.0;
     const int b = blockIdx.x;
     const int L = (b % kXcd) * per_xcd + b / kXcd;
-    if (g.X * g.Y != kBlock || L >= ncg * nseg * g.Z) return;  // uniform over the block
-    const int Lp = CGMINOR ? L / ncg : L % (g.Z * nseg);  // (segment, z) pair
-    const int z = Lp % g.Z;
-    const int seg = Lp / g.Z;
-    const int c0 = (CGMINOR ? L % ncg : L / (g.Z * nseg)) * NC;
+    const int nzg = g.Z / NZ;  // groups of NZ consecutive planes
+    if (g.X * g.Y != kBlock || g.Z % NZ != 0 || L >= ncg * nseg * nzg) return;  // uniform over the block
+    const int Lp = CGMINOR ? L / ncg : L % (nzg * nseg);  // (segment, plane group) pair
+    const int zz = threadIdx.x / kBlock;                   // this thread's plane in the group (wave-uniform)
+    const int z = (Lp % nzg) * NZ + zz;
+    const int seg = Lp / nzg;
+    const int c0 = (CGMINOR ? L % ncg : L / (nzg * nseg)) * NC;
     const int t0 = seg * tlen;
     const int t1 = min(g.T, t0 + tlen);
-    const int p = threadIdx.x;  // x + X y
+    const int p = threadIdx.x % kBlock;  // x + X y
     const int x = p % g.X, y = p / g.X;
     const int XY = kBlock, XYZ = XY * g.Z;
     const unsigned uV = (unsigned)g.V;
@@ -334,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const int col = live[c] ? c0 + c : c0;
-            const double pq = sum_partials(e.pq + (int64_t)col * G, G, nsh);  // every thread: uniform
+            const double pq = plane_sum_partials(e.pq + (int64_t)col * G, G, nsh, zz);  // uniform
             upd[c] = live[c] && e.st[col].active;
             alpha[c] = upd[c] ? (R)(e.st[col].rho / pq) : R(0);
         }
@@ -369,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int cc = 0; cc < 3; ++cc) pl[c * 12 + a * 3 + cc][p] = V2{cur[c][a][cc].re, cur[c][a][cc].im};
+                for (int cc = 0; cc < 3; ++cc) pl[zz][c * 12 + a * 3 + cc][p] = V2{cur[c][a][cc].re, cur[c][a][cc].im};
         __syncthreads();
 
         cplx<R> acc[NC][4][3];
@@ -382,8 +411,9 @@ __global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64
             hop_acc<3, SB>(acc[c], cr0[c], cr1[c]);  // -t, carried
         }
         cplx<R> u[3][3], psi[4][3];
-        // x, y hops from the staged slice (d = 0..3), then z hops from L2
-        // (d = 4, 5); a rolled loop keeps one hop's operands live
+        // x, y hops from the staged slice (d = 0..3), then z hops (d = 4, 5)
+        // from the neighbouring plane's staged slice where the block holds it,
+        // else from L2; a rolled loop keeps one hop's operands live
 #pragma unroll 1
         for (int d = 0; d < 6; ++d) {
             const bool fwd = (d & 1) == 0;
@@ -396,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64
                     for (int a = 0; a < 4; ++a)
 #pragma unroll
                         for (int cc = 0; cc < 3; ++cc) {
-                            const V2 v = pl[c * 12 + a * 3 + cc][pn];
+                            const V2 v = pl[zz][c * 12 + a * 3 + cc][pn];
                             psi[a][cc] = {v.x, v.y};
                         }
                     switch (d) {
@@ -408,10 +438,22 @@ __global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64
                 }
             } else {
                 const unsigned sn = (unsigned)((int)s + (fwd ? zoff_p : zoff_m));
+                const int zn = fwd ? zz + 1 : zz - 1;  // the neighbour's plane in the group
+                const bool staged = NZ > 1 && zn >= 0 && zn < NZ;
                 load_link(U, uV, 2, fwd ? s : sn, u);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    load_spinor(src[c], uV, sn, psi);
+                    if (staged) {
+#pragma unroll
+                        for (int a = 0; a < 4; ++a)
+#pragma unroll
+                            for (int cc = 0; cc < 3; ++cc) {
+                                const V2 v = pl[zn][c * 12 + a * 3 + cc][p];
+                                psi[a][cc] = {v.x, v.y};
+                            }
+                    } else {
+                        load_spinor(src[c], uV, sn, psi);
+                    }
                     if (fwd) hop<2, SF, false>(acc[c], psi, u, R(1));
                     else hop<2, SB, true>(acc[c], psi, u, R(1));
                 }
@@ -462,8 +504,8 @@ __global__ __launch_bounds__(kBlock) void k_wilson_tm(R* __restrict__ out, int64
     if constexpr (EPI != TM_PLAIN) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const double tot = block_sum(nacc[c], nsh);
-            if (threadIdx.x == 0 && live[c]) e.part[(int64_t)(c0 + c) * (g.Z * nseg) + seg * g.Z + z] = tot;
+            const double tot = plane_sum(nacc[c], nsh, zz);
+            if (p == 0 && live[c]) e.part[(int64_t)(c0 + c) * (g.Z * nseg) + seg * g.Z + z] = tot;
         }
     }
 }
@@ -522,9 +564,11 @@ __global__ __launch_bounds__(kBlock) void k_wilson_dir(R* __restrict__ out, int6
 // A launch shape is (hop loop form x columns per thread), a column-chunk size
 // G and a tile order; variant id = order * 16 + shape * 4 + chunk with chunk
 // 0: G = all groups, 1: G = 1, 2: G = 2, 3: G = 4, and order 0: site order,
-// 1: z-blocked by 4 tiles.  Ids 32..43 are the t-march form: 32 + 6 * order
-// + 3 * (NC - 1) + {0, 1, 2} for segments of {4, 8, 16} time slices, order 0:
-// column group slowest, 1: fastest.  Id 44 is the direction-split form.
+// 1: z-blocked by 4 tiles.  Ids 32..43 are the t-march form with one plane
+// per block: 32 + 6 * order + 3 * (NC - 1) + {0, 1, 2} for segments of
+// {4, 8, 16} time slices, order 0: column group slowest, 1: fastest.  Id 44
+// is the direction-split form.  Ids 45..56 and 57..68 are the t-march form
+// with 2 and 4 planes per block, numbered as 32..43 from 45 and 57.
 enum WilsonShape { WS_UNROLLED_1 = 0, WS_ROLLED_1 = 1, WS_ROLLED_2 = 2, WS_ROLLED_4 = 3, WS_COUNT = 4 };
 constexpr int kChunks = 4;
 constexpr int kOrders = 2;
@@ -532,7 +576,8 @@ constexpr int kZBlock = 4;
 constexpr int WV_TILED = kOrders * WS_COUNT * kChunks;
 constexpr int WV_TMARCH = 12;
 constexpr int WV_DIR = WV_TILED + WV_TMARCH;  // the direction-split form
-constexpr int WV_COUNT = WV_DIR + 1;
+constexpr int WV_TM2 = WV_DIR + 1;            // t-march, 2 and 4 planes per block
+constexpr int WV_COUNT = WV_TM2 + 2 * WV_TMARCH;
 static_assert(WV_COUNT == SC_WILSON_VARIANTS, "variant count must match the header");
 
 static int chunk_groups(int chunk, int ncg) {
@@ -549,28 +594,28 @@ static bool zblock_ok(const sc_op* op) {
 // the t-march form needs the xy-plane to be exactly one tile
 static bool tmarch_ok(const sc_op* op) { return op->dims[0] * op->dims[1] == kBlock; }
 
-template <typename R, int NC, bool CGMINOR>
+template <typename R, int NC, bool CGMINOR, int NZ>
 static void wilson_launch_tm(const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k,
                              const R* U, int tlen, hipStream_t s, int epi = TM_PLAIN, TmEpi e = TmEpi{}) {
     Geom g{op->dims[0], op->dims[1], op->dims[2], op->dims[3], op->vol};
     tlen = std::max(1, std::min(tlen, g.T));
     const int nseg = (g.T + tlen - 1) / tlen;
     const int ncg = (k + NC - 1) / NC;
-    const int per_xcd = (ncg * nseg * g.Z + kXcd - 1) / kXcd;
-    dim3 grid((unsigned)(per_xcd * kXcd));
+    const int per_xcd = (ncg * nseg * (g.Z / NZ) + kXcd - 1) / kXcd;
+    const dim3 grid((unsigned)(per_xcd * kXcd)), blk(kBlock * NZ);
     const R kap = (R)op->kappa;
     const R ts = op->antiperiodic ? R(-1) : R(1);
 #define SC_WT(DAG, MODE)                                                                                   \
-    SC_TLAUNCH((k_wilson_tm<R, DAG, MODE, NC, CGMINOR>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,      \
-                       2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, TmEpi{});
+    SC_TLAUNCH((k_wilson_tm<R, DAG, MODE, NC, CGMINOR, TM_PLAIN, NZ>), grid, blk, 0, s, Y, 2 * ldy, X, \
+               2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, TmEpi{});
     if (epi == TM_NORM) {  // D pass with the |D x|^2 partials
-        SC_TLAUNCH((k_wilson_tm<R, false, 0, NC, CGMINOR, TM_NORM>), grid, dim3(kBlock), 0, s, Y, 2 * ldy,
-                           X, 2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, e);
+        SC_TLAUNCH((k_wilson_tm<R, false, 0, NC, CGMINOR, TM_NORM, NZ>), grid, blk, 0, s, Y, 2 * ldy, X,
+                   2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, e);
         return;
     }
     if (epi == TM_CG) {  // D^H pass finishing r -= alpha A p
-        SC_TLAUNCH((k_wilson_tm<R, true, 0, NC, CGMINOR, TM_CG>), grid, dim3(kBlock), 0, s, Y, 2 * ldy,
-                           X, 2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, e);
+        SC_TLAUNCH((k_wilson_tm<R, true, 0, NC, CGMINOR, TM_CG, NZ>), grid, blk, 0, s, Y, 2 * ldy, X,
+                   2 * ldx, U, g, kap, ts, k, ncg, nseg, tlen, per_xcd, e);
         return;
     }
     switch (which) {
@@ -580,6 +625,46 @@ static void wilson_launch_tm(const sc_op* op, int which, const R* X, int64_t ldx
         default: SC_WT(true, 1) break;
     }
 #undef SC_WT
+}
+
+// Effective t-march shape of variant v on this lattice and precision.  FP64
+// has 1 column per thread (2 would spill); a block's staged planes must fit
+// the 160 KB of LDS (at most 4 plane-columns of FP32 or 2 of FP64, 24 KB
+// each) and the plane groups must tile Z; a pinned shape that does not fit
+// takes the next smaller plane group.
+struct TmShape {
+    int tlen, nc, nz;
+    bool cgminor;
+};
+static bool is_tmarch(int v) { return (v >= WV_TILED && v < WV_DIR) || (v >= WV_TM2 && v < WV_COUNT); }
+static TmShape tm_shape(int v, bool single, int Z) {
+    const int i = v < WV_DIR ? v - WV_TILED : (v - WV_TM2) % WV_TMARCH;
+    TmShape t;
+    t.nz = v < WV_DIR ? 1 : ((v - WV_TM2) < WV_TMARCH ? 2 : 4);
+    t.tlen = i % 3 == 0 ? 4 : (i % 3 == 1 ? 8 : 16);
+    t.nc = ((i / 3) % 2 == 1 && single) ? 2 : 1;
+    t.cgminor = i >= 6;
+    while (t.nz > 1 && (t.nz * t.nc * (single ? 1 : 2) > 4 || Z % t.nz != 0)) t.nz /= 2;
+    return t;
+}
+
+template <typename R>
+static void tm_launch(const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k, const R* U,
+                      const TmShape& t, int epi, const TmEpi& e, hipStream_t s) {
+#define SC_TMD(NC_, NZ_)                                                                                   \
+    {                                                                                                      \
+        if (t.cgminor) wilson_launch_tm<R, NC_, true, NZ_>(op, which, X, ldx, Y, ldy, k, U, t.tlen, s, epi, e); \
+        else wilson_launch_tm<R, NC_, false, NZ_>(op, which, X, ldx, Y, ldy, k, U, t.tlen, s, epi, e);     \
+    }
+    if (t.nc == 1) {
+        if (t.nz == 1) SC_TMD(1, 1)
+        else if (t.nz == 2) SC_TMD(1, 2)
+        else if constexpr (sizeof(R) == 4) SC_TMD(1, 4)
+    } else if constexpr (sizeof(R) == 4) {
+        if (t.nz == 1) SC_TMD(2, 1)
+        else SC_TMD(2, 2)
+    }
+#undef SC_TMD
 }
 
 template <typename R>
@@ -644,19 +729,10 @@ static void wilson_launch_variant(int v, const sc_op* op, int which, const R* X,
         wilson_launch_dir<R>(op, which, X, ldx, Y, ldy, k, U, s);
         return;
     }
-    if (v >= WV_TILED && !tmarch_ok(op)) v = default_variant(sizeof(R) == 4, k);  // not for this lattice
-    if (v >= WV_TILED) {
-        const int i = v - WV_TILED, tlen = i % 3 == 0 ? 4 : (i % 3 == 1 ? 8 : 16);
-        const int form = (i / 3) % 2;       // 0: 1 column per thread, 1: 2
-        const bool cgminor = i >= 6;
-        constexpr int N2 = sizeof(R) == 4 ? 2 : 1;  // FP64 with 2 columns would spill
-        if (form == 0) {
-            if (cgminor) wilson_launch_tm<R, 1, true>(op, which, X, ldx, Y, ldy, k, U, tlen, s);
-            else wilson_launch_tm<R, 1, false>(op, which, X, ldx, Y, ldy, k, U, tlen, s);
-        } else {
-            if (cgminor) wilson_launch_tm<R, N2, true>(op, which, X, ldx, Y, ldy, k, U, tlen, s);
-            else wilson_launch_tm<R, N2, false>(op, which, X, ldx, Y, ldy, k, U, tlen, s);
-        }
+    if (is_tmarch(v) && !tmarch_ok(op)) v = default_variant(sizeof(R) == 4, k);  // not for this lattice
+    if (is_tmarch(v)) {
+        tm_launch<R>(op, which, X, ldx, Y, ldy, k, U, tm_shape(v, sizeof(R) == 4, op->dims[2]), TM_PLAIN, TmEpi{},
+                     s);
         return;
     }
     constexpr int N4 = sizeof(R) == 4 ? 4 : 2;
@@ -672,12 +748,13 @@ static void wilson_launch_variant(int v, const sc_op* op, int which, const R* X,
 // variants worth timing for this lattice, precision and column count
 static bool variant_applies(const sc_op* op, int v, bool single, int k) {
     if (v == WV_DIR) return k <= 4;
-    if (v >= WV_TILED) {
-        const int i = v - WV_TILED;
+    if (is_tmarch(v)) {
+        const int i = v < WV_DIR ? v - WV_TILED : (v - WV_TM2) % WV_TMARCH;
+        const int nz = v < WV_DIR ? 1 : ((v - WV_TM2) < WV_TMARCH ? 2 : 4);
         if (!tmarch_ok(op)) return false;
         if ((i / 3) % 2 == 1 && (k == 1 || !single)) return false;  // 2 columns: FP64 would spill
         if (i >= 6 && k == 1) return false;                           // one column group: orders agree
-        return true;
+        return tm_shape(v, single, op->dims[2]).nz == nz;             // else the same as a smaller group
     }
     const int shape = (v / kChunks) % WS_COUNT, chunk = v % kChunks, order = v / (WS_COUNT * kChunks);
     if (order == 1 && !zblock_ok(op)) return false;  // same as site order
@@ -771,7 +848,7 @@ static int choose_variant(const sc_op* op, int which, const R* X, int64_t ldx, R
 }
 
 sc_status wilson_tune_pin(const sc_op* op, bool single, int k, int variant) {
-    if (variant >= WV_TILED && variant < WV_DIR && !tmarch_ok(op)) {
+    if (is_tmarch(variant) && !tmarch_ok(op)) {
         set_error("wilson_tune_set: the t-march shapes need an xy-plane of exactly 256 sites");
         return SC_ERR_ARG;
     }
@@ -818,37 +895,14 @@ static sc_status wilson_launch(const sc_op* op, int which, const R* X, int64_t l
     return SC_OK;
 }
 
-// The t-march shape tlen/order/columns of variant v (v >= WV_TILED)
-static void tm_params(int v, int* tlen, int* form, bool* cgminor) {
-    const int i = v - WV_TILED;
-    *tlen = i % 3 == 0 ? 4 : (i % 3 == 1 ? 8 : 16);
-    *form = (i / 3) % 2;
-    *cgminor = i >= 6;
-}
-
-template <typename R>
-static void tm_launch(const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k, const R* U,
-                      int tlen, int form, bool cgminor, int epi, const TmEpi& e, hipStream_t s) {
-    constexpr int N2 = sizeof(R) == 4 ? 2 : 1;  // FP64 with 2 columns would spill
-    if (form == 0) {
-        if (cgminor) wilson_launch_tm<R, 1, true>(op, which, X, ldx, Y, ldy, k, U, tlen, s, epi, e);
-        else wilson_launch_tm<R, 1, false>(op, which, X, ldx, Y, ldy, k, U, tlen, s, epi, e);
-    } else {
-        if (cgminor) wilson_launch_tm<R, N2, true>(op, which, X, ldx, Y, ldy, k, U, tlen, s, epi, e);
-        else wilson_launch_tm<R, N2, false>(op, which, X, ldx, Y, ldy, k, U, tlen, s, epi, e);
-    }
-}
-
 template <typename R>
 static sc_status wilson_d_norm(const sc_op* op, const R* X, int64_t ldx, R* Y, int64_t ldy, int k, const R* U,
                                double* part, int max_parts, int* G, hipStream_t s) {
     *G = 0;
     const int v = choose_variant<R>(op, 0, X, ldx, Y, ldy, k, U, s);
-    if (v < WV_TILED || v >= WV_DIR || !tmarch_ok(op)) return wilson_launch<R>(op, 0, X, ldx, Y, ldy, k, U, s);
-    int tlen, form;
-    bool cgminor;
-    tm_params(v, &tlen, &form, &cgminor);
-    tlen = std::max(1, std::min(tlen, op->dims[3]));
+    if (!is_tmarch(v) || !tmarch_ok(op)) return wilson_launch<R>(op, 0, X, ldx, Y, ldy, k, U, s);
+    const TmShape t = tm_shape(v, sizeof(R) == 4, op->dims[2]);
+    const int tlen = std::max(1, std::min(t.tlen, op->dims[3]));
     const int parts = op->dims[2] * ((op->dims[3] + tlen - 1) / tlen);
     if (parts > max_parts) return wilson_launch<R>(op, 0, X, ldx, Y, ldy, k, U, s);
     const double bytes = (48.0 * k + 72.0) * sizeof(R) * (double)op->vol;
@@ -856,7 +910,7 @@ static sc_status wilson_d_norm(const sc_op* op, const R* X, int64_t ldx, R* Y, i
     TimerScope ts_(cls, s, bytes, 1368.0 * k * (double)op->vol);
     TmEpi e{};
     e.part = part;
-    tm_launch<R>(op, 0, X, ldx, Y, ldy, k, U, tlen, form, cgminor, TM_NORM, e, s);
+    tm_launch<R>(op, 0, X, ldx, Y, ldy, k, U, t, TM_NORM, e, s);
     SC_LAUNCH_CHECK();
     *G = parts;
     return SC_OK;
@@ -869,11 +923,9 @@ static sc_status wilson_cg_fused_t(const sc_op* op, const R* p, R* tmp, int k, c
     *G = 0;
     if (!tmarch_ok(op)) return SC_OK;
     const int v = choose_variant<R>(op, 0, p, op->n, tmp, op->n, k, U, s);
-    if (v < WV_TILED || v >= WV_DIR) return SC_OK;
-    int tlen, form;
-    bool cgminor;
-    tm_params(v, &tlen, &form, &cgminor);
-    tlen = std::max(1, std::min(tlen, op->dims[3]));
+    if (!is_tmarch(v)) return SC_OK;
+    const TmShape t = tm_shape(v, sizeof(R) == 4, op->dims[2]);
+    const int tlen = std::max(1, std::min(t.tlen, op->dims[3]));
     const int parts = op->dims[2] * ((op->dims[3] + tlen - 1) / tlen);
     if (parts > max_parts) return SC_OK;
     const double bytes = (48.0 * k + 72.0) * sizeof(R) * (double)op->vol;
@@ -882,7 +934,7 @@ static sc_status wilson_cg_fused_t(const sc_op* op, const R* p, R* tmp, int k, c
         TimerScope ts_(cls, s, bytes, 1368.0 * k * (double)op->vol);
         TmEpi e{};
         e.part = part_pq;
-        tm_launch<R>(op, 0, p, op->n, tmp, op->n, k, U, tlen, form, cgminor, TM_NORM, e, s);
+        tm_launch<R>(op, 0, p, op->n, tmp, op->n, k, U, t, TM_NORM, e, s);
         SC_LAUNCH_CHECK();
     }
     {
@@ -894,7 +946,7 @@ static sc_status wilson_cg_fused_t(const sc_op* op, const R* p, R* tmp, int k, c
         e.pq = part_pq;
         e.r = r;
         e.ldr = 2 * ldr;
-        tm_launch<R>(op, 1, tmp, op->n, tmp, op->n, k, U, tlen, form, cgminor, TM_CG, e, s);
+        tm_launch<R>(op, 1, tmp, op->n, tmp, op->n, k, U, t, TM_CG, e, s);
         SC_LAUNCH_CHECK();
     }
     *G = parts;

@@ -118,13 +118,16 @@ def test_tune_set_refuses_tmarch_on_other_lattices(lib):
     assert lib.sc_wilson_tune_set(out, 1, 3, 32) == -1
     assert b"256" in lib.sc_last_error()
     assert lib.sc_wilson_tune_set(out, 1, 3, 31) == 0
-    assert lib.sc_wilson_tune_set(out, 1, 3, 45) == -1
+    assert lib.sc_wilson_tune_set(out, 1, 3, 45) == -1  # 2 planes per block
+    assert lib.sc_wilson_tune_set(out, 1, 3, 68) == -1  # 4 planes per block
+    assert lib.sc_wilson_tune_set(out, 1, 3, 69) == -1  # out of range
     assert lib.sc_wilson_tune_set(out, 1, 3, 44) == 0
     assert lib.sc_wilson_tune_set(out, 1, 3, -1) == 0
     assert lib.sc_op_destroy(out) == 0
     dims = (ctypes.c_int * 4)(16, 16, 2, 2)
     assert lib.sc_op_wilson_normal(dims, ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_double(0.12), 1,
                                    ctypes.byref(out)) == 0
-    assert lib.sc_wilson_tune_set(out, 1, 3, 43) == 0
+    for v in (43, 45, 68):
+        assert lib.sc_wilson_tune_set(out, 1, 3, v) == 0
     assert lib.sc_wilson_tune_set(out, 1, 3, -1) == 0
     assert lib.sc_op_destroy(out) == 0

@@ -160,15 +160,18 @@ def test_wilson_passes(dims):
 
 
 @pytest.mark.parametrize("dims,k", [((3, 5, 4, 6), 1), ((3, 5, 4, 6), 3), ((3, 5, 4, 6), 5), ((3, 5, 4, 6), 9),
-                                    ((16, 16, 8, 9), 1), ((16, 16, 8, 9), 5)])
+                                    ((16, 16, 8, 9), 1), ((16, 16, 8, 9), 5), ((16, 16, 6, 5), 3),
+                                    ((16, 16, 3, 4), 2)])
 def test_wilson_every_launch_shape(dims, k):
     # each stencil variant the autotuner may pick, pinned in turn, and k
     # columns (k = 5 and 9 leave partial column chunks): on a ragged lattice
     # (volume not a multiple of the 256-site tile), and on one whose time
     # slices hold 8 whole tiles, where the z-blocked tile order applies, and
     # whose xy-plane is one tile, where the t-march form applies (T = 9: the
-    # last time segment is partial); outputs start as NaN so that a work item
-    # the launch skips cannot pass on stale memory
+    # last time segment is partial; Z = 6 and 3: blocks of 4 and of 2 planes
+    # do not divide Z, so those shapes take smaller plane groups); outputs
+    # start as NaN so that a work item the launch skips cannot pass on stale
+    # memory
     _say("wilson launch shapes", dims, "k", k)
     U, op = _wilson(dims, cfg=8)
     x = synth.complex_gaussian(op.n, k, synth.rng(5, 2))
@@ -179,7 +182,7 @@ def test_wilson_every_launch_shape(dims, k):
         (2, lambda fl: ops.wilson_hop(fl, U)), (3, lambda fl: ops.wilson_hop(fl, U, dagger=True))]}
     tmarch = dims[0] * dims[1] == 256
     for v in range(api.WILSON_VARIANTS):
-        if 32 <= v < 44 and not tmarch:  # the t-march shapes need a 256-site xy-plane: refused
+        if (32 <= v < 44 or v >= 45) and not tmarch:  # the t-march shapes need a 256-site xy-plane: refused
             with pytest.raises(api.SeedCGError):
                 op.tune_set(k, v, single=True)
             continue
@@ -402,7 +405,9 @@ def test_cg_inner_product_from_the_d_pass():
     B = synth.complex_gaussian(op.n, k, synth.rng(9, 1))
     ref = [cg(oop, B[:, j], tol=1e-9) for j in range(k)]
     Bl = _to_lib(B)
-    for variant in (32, 41, 4):  # t-march (1 and 2 columns per thread), tiled
+    # t-march with 1 plane per block (1 and 2 columns per thread), with 2 planes
+    # (2 columns) and 4 planes (1 column), tiled
+    for variant in (32, 41, 54, 57, 4):
         for mixed in (False, True):
             op.tune_set(k, variant, single=mixed)
             X, its, rel = api.solve_cg(op, Bl, 1e-9, mixed=mixed)
