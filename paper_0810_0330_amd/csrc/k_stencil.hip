@@ -410,16 +410,33 @@ __global__ __launch_bounds__(kBlock * NZ) void k_wilson_tm(R* __restrict__ out, 
                 for (int cc = 0; cc < 3; ++cc) acc[c][a][cc] = {R(0), R(0)};
             hop_acc<3, SB>(acc[c], cr0[c], cr1[c]);  // -t, carried
         }
-        cplx<R> u[3][3], psi[4][3];
+        cplx<R> u[3][3], un[3][3], psi[4][3];
         // x, y hops from the staged slice (d = 0..3), then z hops (d = 4, 5)
         // from the neighbouring plane's staged slice where the block holds it,
-        // else from L2; a rolled loop keeps one hop's operands live
+        // else from L2; a rolled loop keeps one hop's operands live.  With
+        // LPF the link of the next hop (after d = 5: of the +t hop) is loaded
+        // while this one is computed (18 more registers per lane; only where
+        // that does not lower the occupancy)
+        constexpr bool LPF = sizeof(R) == 4 && NC == 2;
+        auto lsite = [&](int d) -> unsigned {
+            return (d & 1) == 0 ? s : (unsigned)((int)s + (d == 1 ? pxm - p : (d == 3 ? pym - p : zoff_m)));
+        };
+        if constexpr (LPF) load_link(U, uV, 0, s, un);
 #pragma unroll 1
         for (int d = 0; d < 6; ++d) {
             const bool fwd = (d & 1) == 0;
+            if constexpr (LPF) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int bb = 0; bb < 3; ++bb) u[a][bb] = un[a][bb];
+                if (d < 5) load_link(U, uV, (d + 1) >> 1, lsite(d + 1), un);
+                else load_link(U, uV, 3, s, un);
+            } else {
+                load_link(U, uV, d >> 1, lsite(d), u);
+            }
             if (d < 4) {
                 const int pn = d == 0 ? pxp : (d == 1 ? pxm : (d == 2 ? pyp : pym));
-                load_link(U, uV, d >> 1, fwd ? s : (unsigned)((int)s - p + pn), u);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
 #pragma unroll
@@ -440,7 +457,6 @@ __global__ __launch_bounds__(kBlock * NZ) void k_wilson_tm(R* __restrict__ out, 
                 const unsigned sn = (unsigned)((int)s + (fwd ? zoff_p : zoff_m));
                 const int zn = fwd ? zz + 1 : zz - 1;  // the neighbour's plane in the group
                 const bool staged = NZ > 1 && zn >= 0 && zn < NZ;
-                load_link(U, uV, 2, fwd ? s : sn, u);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     if (staged) {
@@ -464,12 +480,12 @@ __global__ __launch_bounds__(kBlock * NZ) void k_wilson_tm(R* __restrict__ out, 
         {
             const unsigned sp = (unsigned)(t == g.T - 1 ? (int)s - (g.T - 1) * XYZ : (int)s + XYZ);
             const R bfp = (t == g.T - 1) ? tsign : R(1);
-            load_link(U, uV, 3, s, u);
+            if constexpr (!LPF) load_link(U, uV, 3, s, un);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 load_spinor(src[c], uV, sp, psi);
-                hop<3, SF, false>(acc[c], psi, u, bfp);
-                hop_half<3, SB, true>(cur[c], u, R(1), cr0[c], cr1[c]);
+                hop<3, SF, false>(acc[c], psi, un, bfp);
+                hop_half<3, SB, true>(cur[c], un, R(1), cr0[c], cr1[c]);
                 // write this slice's result, then advance
                 if (EPI == TM_CG ? upd[c] : live[c]) {
                     R* dst = out + (int64_t)(c0 + c) * ldo;

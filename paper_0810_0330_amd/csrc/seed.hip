@@ -168,7 +168,30 @@ __global__ __launch_bounds__(kBlock) void k_lz_f(R* __restrict__ f, const R* __r
     const R aR = (R)a;
     double acc = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock * W;
-    for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W; i0 < N; i0 += stride) {
+    int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W;
+    if constexpr (VEC) {
+        // four packs per trip, all loads issued first (more bytes in flight
+        // per wave); the sum runs in the same order as the loop below
+        constexpr int UN = 4;
+        for (; i0 + (UN - 1) * stride + W <= N; i0 += UN * stride) {
+            Pack<R> o[UN], v[UN];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+                o[u] = ldp(f, i0 + u * stride);
+                v[u] = ldp(vi, i0 + u * stride);
+            }
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+#pragma unroll
+                for (int e = 0; e < W; ++e) {
+                    o[u].v[e] = o[u].v[e] - aR * v[u].v[e];
+                    acc += (double)o[u].v[e] * (double)o[u].v[e];
+                }
+                stp(f, i0 + u * stride, o[u]);
+            }
+        }
+    }
+    for (; i0 < N; i0 += stride) {
         if (VEC && i0 + W <= N) {
             Pack<R> o = ldp(f, i0);
             const Pack<R> v = ldp(vi, i0);
