@@ -35,25 +35,42 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// G = V^H W: block = 4 waves over 64 basis columns (16 per wave) x 16*NJ
-// right-hand columns, one row chunk; LDS stages of 32 complex rows.  The
-// stages are software-pipelined: each thread holds its share of the next
-// stage's V and W elements in registers, loaded before the current stage's
-// MFMAs are issued and written to LDS after them, so the global-load latency
-// of a stage hides behind the previous stage's compute.  V stays in its own
-// precision in LDS and is widened when it is fed to the MFMA.
-template <typename VR, typename WR, int NJ>
+// The complex right-hand block enters the MFMAs as one real matrix of 2N
+// columns, [Re W | Im W] (padded with zeros to 16 NT columns, NT = ceil(N/8)),
+// multiplied once by Re V and once by Im V: P = Re(V)^T [Re W | Im W] and
+// Q = Im(V)^T [Re W | Im W].  The complex result is then
+//   Re(V^H W)_j = P_j + Q_{N+j},  Im(V^H W)_j = P_{N+j} - Q_j,
+//   Re(V Y)_j   = P_j - Q_{N+j},  Im(V Y)_j   = P_{N+j} + Q_j,
+// which takes 2 NT MFMAs per 4-row step where four products per 16-column
+// complex tile would take 8 ceil(N/16) (N = 23: 6 against 8).  Q is passed
+// through LDS in the epilogue so that each lane holds one P and the Q it is
+// combined with.
+
+// G = V^H W: block = 4 waves over 64 basis columns (16 per wave), one row
+// chunk; LDS stages of 32 complex rows.  The stages are software-pipelined:
+// each thread holds its share of the next stage's V and W elements in
+// registers, loaded before the current stage's MFMAs are issued and written to
+// LDS after them, so the global-load latency of a stage hides behind the
+// previous stage's compute.  V stays in its own precision in LDS and is
+// widened when it is fed to the MFMA.
+template <typename VR, typename WR, int NT>
 __global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, int64_t ldv, int64_t n, int M,
                                                     ColPtrs<const void> W, int N, double* __restrict__ part,
                                                     int64_t rows_per_chunk, int nchunk, const int* halt) {
     if (halt && *halt) return;
-    constexpr int KR = 32;          // complex rows per LDS stage
-    constexpr int TA = 64;          // basis columns per block
-    constexpr int TJ = 16 * NJ;     // right-hand columns per block
-    constexpr int EV = KR * TA / kBlock;  // V elements per thread per stage
-    constexpr int EW = KR * TJ / kBlock;  // W elements per thread per stage
-    __shared__ VR vr[KR][TA + 1], vi[KR][TA + 1];
-    __shared__ double wr[KR][TJ + 1], wi[KR][TJ + 1];
+    constexpr int KR = 32;               // complex rows per LDS stage
+    constexpr int TA = 64;               // basis columns per block
+    constexpr int TC = 16 * NT;          // real columns of [Re W | Im W], padded
+    constexpr int EV = KR * TA / kBlock; // V elements per thread per stage
+    constexpr int EW = (KR * TC / 2 + kBlock - 1) / kBlock;  // complex W elements per thread per stage
+    union Lds {
+        struct {
+            VR vr[KR][TA + 1], vi[KR][TA + 1];
+            double wb[KR][TC + 1];
+        } st;
+        double qs[TA][TC + 1];
+    };
+    __shared__ Lds lds;
     // work item L = (b % 8) * per_xcd + b / 8 over (row chunk, column block),
     // column blocks fastest: the blocks that read one chunk of W run together
     // on one XCD and share it through its L2
@@ -66,12 +83,17 @@ __global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, in
     const int64_t r0 = chunk * rows_per_chunk;
     const int64_t r1 = min(n, r0 + rows_per_chunk);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    d4_t accr[NJ], acci[NJ];
+    d4_t accp[NT], accq[NT];
 #pragma unroll
-    for (int t = 0; t < NJ; ++t) accr[t] = acci[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NT; ++t) accp[t] = accq[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    // columns 2N .. TC of the staged W block stay zero
+    for (int e = threadIdx.x; e < KR * (TC + 1); e += kBlock) {
+        const int c = e % (TC + 1);
+        if (c >= 2 * N) lds.st.wb[e / (TC + 1)][c] = 0.0;
+    }
     cplx<VR> pv[EV];
     cplx<double> pw[EW];
-    // element e of a stage: V row e % KR of column e / KR; W row e % KR of column e / KR
+    // element e of a stage: V row e % KR of column e / KR; W row e % KR of complex column e / KR
     auto fetch = [&](int64_t rb) {
 #pragma unroll
         for (int q = 0; q < EV; ++q) {
@@ -99,70 +121,90 @@ __global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, in
 #pragma unroll
         for (int q = 0; q < EV; ++q) {
             const int e = threadIdx.x + q * kBlock;
-            vr[e % KR][e / KR] = pv[q].re;
-            vi[e % KR][e / KR] = pv[q].im;
+            lds.st.vr[e % KR][e / KR] = pv[q].re;
+            lds.st.vi[e % KR][e / KR] = pv[q].im;
         }
 #pragma unroll
         for (int q = 0; q < EW; ++q) {
             const int e = threadIdx.x + q * kBlock;
-            wr[e % KR][e / KR] = pw[q].re;
-            wi[e % KR][e / KR] = pw[q].im;
+            const int jj = e / KR;
+            if (jj < N) {
+                lds.st.wb[e % KR][jj] = pw[q].re;
+                lds.st.wb[e % KR][N + jj] = pw[q].im;
+            }
         }
         __syncthreads();
         if (rb + KR < r1) fetch(rb + KR);  // in flight during this stage's MFMAs
 #pragma unroll
         for (int ks = 0; ks < KR / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
-            const double ar = (double)vr[kr][wv * 16 + (lane & 15)];
-            const double ai = (double)vi[kr][wv * 16 + (lane & 15)];
+            const double ar = (double)lds.st.vr[kr][wv * 16 + (lane & 15)];
+            const double ai = (double)lds.st.vi[kr][wv * 16 + (lane & 15)];
 #pragma unroll
-            for (int t = 0; t < NJ; ++t) {
-                const double br = wr[kr][t * 16 + (lane & 15)];
-                const double bi = wi[kr][t * 16 + (lane & 15)];
-                accr[t] = mfma16(ar, br, accr[t]);   // Re += Vr Wr + Vi Wi
-                accr[t] = mfma16(ai, bi, accr[t]);
-                acci[t] = mfma16(ar, bi, acci[t]);   // Im += Vr Wi - Vi Wr
-                acci[t] = mfma16(ai, -br, acci[t]);
+            for (int t = 0; t < NT; ++t) {
+                const double bw = lds.st.wb[kr][t * 16 + (lane & 15)];
+                accp[t] = mfma16(ar, bw, accp[t]);
+                accq[t] = mfma16(ai, bw, accq[t]);
             }
         }
     }
+    __syncthreads();  // the staging tiles are reused for Q
 #pragma unroll
-    for (int t = 0; t < NJ; ++t) {
-        const int j = t * 16 + (lane & 15);
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) lds.qs[wv * 16 + (lane >> 4) + 4 * v][t * 16 + (lane & 15)] = accq[t][v];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int c = t * 16 + (lane & 15);
+        if (c >= 2 * N) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int a = a0 + wv * 16 + (lane >> 4) + 4 * v;
-            if (a < M && j < N) {
-                const int64_t o = ((int64_t)chunk * M + a) * N + j;
-                part[2 * o] = accr[t][v];
-                part[2 * o + 1] = acci[t][v];
+            const int al = wv * 16 + (lane >> 4) + 4 * v;
+            const int a = a0 + al;
+            if (a >= M) continue;
+            if (c < N) {  // Re G_{a,c}
+                part[2 * (((int64_t)chunk * M + a) * N + c)] = accp[t][v] + lds.qs[al][N + c];
+            } else {      // Im G_{a,c-N}
+                part[2 * (((int64_t)chunk * M + a) * N + (c - N)) + 1] = accp[t][v] - lds.qs[al][c - N];
             }
         }
     }
 }
 
-// X_j += scale * V Y_j: block = 4 waves over 64 rows (16 per wave) x 16*NJ
-// columns; LDS stages of 32 basis columns, software-pipelined like k_cn_mfma.
-template <typename VR, typename XR, int NJ>
+// X_j += scale * V Y_j: block = 4 waves over 64 rows (16 per wave); LDS
+// stages of 32 basis columns, software-pipelined like k_cn_mfma.
+template <typename VR, typename XR, int NT>
 __global__ __launch_bounds__(kBlock) void k_nn_mfma(const VR* __restrict__ V, int64_t ldv, int64_t n, int M,
                                                     const double* __restrict__ Y, int N, ColPtrs<void> X,
                                                     double scale, const int* halt) {
     if (halt && *halt) return;
     constexpr int KA = 32;          // basis columns per LDS stage
     constexpr int TR = 64;          // rows per block
-    constexpr int TJ = 16 * NJ;
+    constexpr int TC = 16 * NT;     // real columns of [Re Y | Im Y], padded
     constexpr int EV = TR * KA / kBlock;
-    constexpr int EY = (KA * TJ + kBlock - 1) / kBlock;
-    __shared__ VR vr[TR][KA + 1], vi[TR][KA + 1];
-    __shared__ double yr[KA][TJ + 1], yi[KA][TJ + 1];
+    constexpr int EY = (KA * TC / 2 + kBlock - 1) / kBlock;  // complex Y elements per thread per stage
+    union Lds {
+        struct {
+            VR vr[TR][KA + 1], vi[TR][KA + 1];
+            double yb[KA][TC + 1];
+        } st;
+        double qs[TR][TC + 1];
+    };
+    __shared__ Lds lds;
     const int64_t row0 = (int64_t)blockIdx.x * TR;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    d4_t accr[NJ], acci[NJ];
+    d4_t accp[NT], accq[NT];
 #pragma unroll
-    for (int t = 0; t < NJ; ++t) accr[t] = acci[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NT; ++t) accp[t] = accq[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int e = threadIdx.x; e < KA * (TC + 1); e += kBlock) {
+        const int c = e % (TC + 1);
+        if (c >= 2 * N) lds.st.yb[e / (TC + 1)][c] = 0.0;
+    }
     cplx<VR> pv[EV];
     cplx<double> py[EY];
-    // element e: V row e % TR of basis column e / TR; Y basis column e / TJ, right-hand column e % TJ
+    constexpr int YJ = TC / 2;  // complex Y columns a stage covers (>= N)
+    // element e: V row e % TR of basis column e / TR; Y basis column e / YJ, right-hand column e % YJ
     auto fetch = [&](int ab) {
 #pragma unroll
         for (int q = 0; q < EV; ++q) {
@@ -174,8 +216,8 @@ __global__ __launch_bounds__(kBlock) void k_nn_mfma(const VR* __restrict__ V, in
 #pragma unroll
         for (int q = 0; q < EY; ++q) {
             const int e = threadIdx.x + q * kBlock;
-            const int a = ab + e / TJ, jj = e % TJ;
-            py[q] = (e < KA * TJ && a < M && jj < N)
+            const int a = ab + e / YJ, jj = e % YJ;
+            py[q] = (e < KA * YJ && a < M && jj < N)
                         ? cplx<double>{Y[((int64_t)a * N + jj) * 2], Y[((int64_t)a * N + jj) * 2 + 1]}
                         : cplx<double>{0.0, 0.0};
         }
@@ -186,15 +228,16 @@ __global__ __launch_bounds__(kBlock) void k_nn_mfma(const VR* __restrict__ V, in
 #pragma unroll
         for (int q = 0; q < EV; ++q) {
             const int e = threadIdx.x + q * kBlock;
-            vr[e % TR][e / TR] = pv[q].re;
-            vi[e % TR][e / TR] = pv[q].im;
+            lds.st.vr[e % TR][e / TR] = pv[q].re;
+            lds.st.vi[e % TR][e / TR] = pv[q].im;
         }
 #pragma unroll
         for (int q = 0; q < EY; ++q) {
             const int e = threadIdx.x + q * kBlock;
-            if (e < KA * TJ) {
-                yr[e / TJ][e % TJ] = py[q].re;
-                yi[e / TJ][e % TJ] = py[q].im;
+            const int jj = e % YJ;
+            if (e < KA * YJ && jj < N) {
+                lds.st.yb[e / YJ][jj] = py[q].re;
+                lds.st.yb[e / YJ][N + jj] = py[q].im;
             }
         }
         __syncthreads();
@@ -202,32 +245,36 @@ __global__ __launch_bounds__(kBlock) void k_nn_mfma(const VR* __restrict__ V, in
 #pragma unroll
         for (int ks = 0; ks < KA / 4; ++ks) {
             const int ka = ks * 4 + (lane >> 4);
-            const double ar = (double)vr[wv * 16 + (lane & 15)][ka];
-            const double ai = (double)vi[wv * 16 + (lane & 15)][ka];
+            const double ar = (double)lds.st.vr[wv * 16 + (lane & 15)][ka];
+            const double ai = (double)lds.st.vi[wv * 16 + (lane & 15)][ka];
 #pragma unroll
-            for (int t = 0; t < NJ; ++t) {
-                const double br = yr[ka][t * 16 + (lane & 15)];
-                const double bi = yi[ka][t * 16 + (lane & 15)];
-                accr[t] = mfma16(ar, br, accr[t]);   // Re += Vr Yr - Vi Yi
-                accr[t] = mfma16(ai, -bi, accr[t]);
-                acci[t] = mfma16(ar, bi, acci[t]);   // Im += Vr Yi + Vi Yr
-                acci[t] = mfma16(ai, br, acci[t]);
+            for (int t = 0; t < NT; ++t) {
+                const double by = lds.st.yb[ka][t * 16 + (lane & 15)];
+                accp[t] = mfma16(ar, by, accp[t]);
+                accq[t] = mfma16(ai, by, accq[t]);
             }
         }
     }
+    __syncthreads();  // the staging tiles are reused for Q
 #pragma unroll
-    for (int t = 0; t < NJ; ++t) {
-        const int j = t * 16 + (lane & 15);
-        if (j >= N) continue;
-        XR* x = (XR*)X.p[j];
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) lds.qs[wv * 16 + (lane >> 4) + 4 * v][t * 16 + (lane & 15)] = accq[t][v];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int c = t * 16 + (lane & 15);
+        if (c >= 2 * N) continue;
+        const bool re = c < N;
+        const int j = re ? c : c - N;
+        XR* x = (XR*)X.p[j] + (re ? 0 : 1);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t r = row0 + wv * 16 + (lane >> 4) + 4 * v;
+            const int rl = wv * 16 + (lane >> 4) + 4 * v;
+            const int64_t r = row0 + rl;
             if (r < n) {
-                cplx<XR> c = ld2(x, r);
-                c.re = (XR)((double)c.re + scale * accr[t][v]);
-                c.im = (XR)((double)c.im + scale * acci[t][v]);
-                st2(x, r, c);
+                const double d = re ? accp[t][v] - lds.qs[rl][N + c] : accp[t][v] + lds.qs[rl][j];
+                x[2 * r] = (XR)((double)x[2 * r] + scale * d);
             }
         }
     }
@@ -475,14 +522,19 @@ static void cn_mfma_launch(const CnPlan& p, const VR* V, int64_t ldv, int64_t n,
     const int mblk = (M + 63) / 64;
     const int per_xcd = (p.nchunk * mblk + kXcd - 1) / kXcd;
     dim3 grid1((unsigned)(per_xcd * kXcd));
+#define SC_CNT(NT_) \
+    SC_TLAUNCH((k_cn_mfma<VR, WR, NT_>), grid1, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, p.nchunk, halt)
     if (N <= 2)
         SC_TLAUNCH((k_cn_small<VR, WR>), grid, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows, halt);
+    else if (N <= 8)
+        SC_CNT(1);
     else if (N <= 16)
-        SC_TLAUNCH((k_cn_mfma<VR, WR, 1>), grid1, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows,
-                           p.nchunk, halt);
+        SC_CNT(2);
+    else if (N <= 24)
+        SC_CNT(3);
     else
-        SC_TLAUNCH((k_cn_mfma<VR, WR, 2>), grid1, dim3(kBlock), 0, s, V, ldv, n, M, W, N, part, p.rows,
-                           p.nchunk, halt);
+        SC_CNT(4);
+#undef SC_CNT
 }
 
 sc_status gemm_cn(bool cplx, bool vsingle, const void* V, int64_t ldv, int64_t n, int M, bool wsingle,
@@ -645,10 +697,16 @@ static void nn_launch(const VR* V, int64_t ldv, int64_t n, int M, const double* 
                       double scale, const int* halt, hipStream_t s) {
     if (CPLX && N > 2) {
         dim3 gm((unsigned)((n + 63) / 64));
-        if (N <= 16)
-            SC_TLAUNCH((k_nn_mfma<VR, XR, 1>), gm, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
+#define SC_NNT(NT_) SC_TLAUNCH((k_nn_mfma<VR, XR, NT_>), gm, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt)
+        if (N <= 8)
+            SC_NNT(1);
+        else if (N <= 16)
+            SC_NNT(2);
+        else if (N <= 24)
+            SC_NNT(3);
         else
-            SC_TLAUNCH((k_nn_mfma<VR, XR, 2>), gm, dim3(kBlock), 0, s, V, ldv, n, M, Y, N, X, scale, halt);
+            SC_NNT(4);
+#undef SC_NNT
         return;
     }
     if (CPLX && N <= 2) {
@@ -690,38 +748,100 @@ sc_status gemm_nn(bool cplx, bool vsingle, const void* V, int64_t ldv, int64_t n
 
 // ---------------------------------------------------------------- T^{-1}
 // T is real, so a complex right-hand side is two real ones: Y is an M x nc
-// row-major real matrix (nc = N or 2N) and thread t sweeps column t.
-__global__ void k_tridiag(const double* __restrict__ alpha, const double* __restrict__ beta, int M,
-                          double* __restrict__ Y, int nc, const double* e1_beta0, double* __restrict__ work,
-                          const int* halt) {
+// row-major real matrix (nc = N or 2N, at most 2 kMaxCols).  One block: the
+// pivots of T = L U (step 6) are formed on thread 0 from tiles of alpha and
+// beta staged in LDS; then the forward and backward sweeps run with thread t
+// on column t over tiles of kTriT rows staged in LDS (one coalesced load and
+// store per tile instead of a global round trip per row).  The arithmetic and
+// its order are those of the plain sweeps.
+constexpr int kTriT = 128;
+
+__global__ __launch_bounds__(kBlock) void k_tridiag(const double* __restrict__ alpha, const double* __restrict__ beta,
+                                                    int M, double* __restrict__ Y, int nc, const double* e1_beta0,
+                                                    double* __restrict__ work, const int* halt) {
     if (halt && *halt) return;
+    __shared__ double yt[kTriT][2 * kMaxCols + 1];
+    __shared__ double at[kTriT], bt[kTriT];
     double* gam = work;
     double* del = work + M;
-    if (threadIdx.x == 0) {
-        del[0] = alpha[0];
-        for (int i = 1; i < M; ++i) {
-            gam[i] = beta[i] / del[i - 1];
-            del[i] = alpha[i] - gam[i] * beta[i];
+    const int t = threadIdx.x;
+    double dprev = 0.0;
+    for (int a0 = 0; a0 < M; a0 += kTriT) {
+        const int na = min(kTriT, M - a0);
+        __syncthreads();
+        for (int i = t; i < na; i += blockDim.x) {
+            at[i] = alpha[a0 + i];
+            bt[i] = beta[a0 + i];
+        }
+        __syncthreads();
+        if (t == 0) {
+            for (int i = 0; i < na; ++i) {
+                const int a = a0 + i;
+                if (a == 0) {
+                    del[0] = at[0];
+                    dprev = at[0];
+                } else {
+                    const double g = bt[i] / dprev;
+                    const double d = at[i] - g * bt[i];
+                    gam[a] = g;
+                    del[a] = d;
+                    dprev = d;
+                }
+            }
         }
     }
     if (e1_beta0) {
-        for (int64_t e = threadIdx.x; e < (int64_t)M * nc; e += blockDim.x) Y[e] = (e == 0) ? *e1_beta0 : 0.0;
+        for (int64_t e = t; e < (int64_t)M * nc; e += blockDim.x) Y[e] = (e == 0) ? *e1_beta0 : 0.0;
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < nc; t += blockDim.x) {
-        double prev = Y[t];
-        for (int a = 1; a < M; ++a) {
-            const double y = Y[(int64_t)a * nc + t] - gam[a] * prev;
-            Y[(int64_t)a * nc + t] = y;
-            prev = y;
+    // forward: y_a -= gam_a y_{a-1}
+    double prev = 0.0;
+    for (int a0 = 0; a0 < M; a0 += kTriT) {
+        const int na = min(kTriT, M - a0);
+        __syncthreads();
+        for (int e = t; e < na * nc; e += blockDim.x) yt[e / nc][e % nc] = Y[(int64_t)a0 * nc + e];
+        for (int i = t; i < na; i += blockDim.x) at[i] = gam[a0 + i];
+        __syncthreads();
+        if (t < nc) {
+            int i = 0;
+            if (a0 == 0) {
+                prev = yt[0][t];
+                i = 1;
+            }
+            for (; i < na; ++i) {
+                const double y = yt[i][t] - at[i] * prev;
+                yt[i][t] = y;
+                prev = y;
+            }
         }
-        double next = Y[(int64_t)(M - 1) * nc + t] / del[M - 1];
-        Y[(int64_t)(M - 1) * nc + t] = next;
-        for (int a = M - 2; a >= 0; --a) {
-            const double y = (Y[(int64_t)a * nc + t] - beta[a + 1] * next) / del[a];
-            Y[(int64_t)a * nc + t] = y;
-            next = y;
+        __syncthreads();
+        for (int e = t; e < na * nc; e += blockDim.x) Y[(int64_t)a0 * nc + e] = yt[e / nc][e % nc];
+    }
+    // backward: y_a = (y_a - beta_{a+1} y_{a+1}) / del_a
+    double next = 0.0;
+    for (int a1 = M; a1 > 0; a1 -= kTriT) {
+        const int a0 = max(0, a1 - kTriT), na = a1 - a0;
+        __syncthreads();
+        for (int e = t; e < na * nc; e += blockDim.x) yt[e / nc][e % nc] = Y[(int64_t)a0 * nc + e];
+        for (int i = t; i < na; i += blockDim.x) {
+            at[i] = del[a0 + i];
+            bt[i] = (a0 + i + 1 < M) ? beta[a0 + i + 1] : 0.0;
         }
+        __syncthreads();
+        if (t < nc) {
+            int i = na - 1;
+            if (a1 == M) {
+                next = yt[i][t] / at[i];
+                yt[i][t] = next;
+                --i;
+            }
+            for (; i >= 0; --i) {
+                const double y = (yt[i][t] - bt[i] * next) / at[i];
+                yt[i][t] = y;
+                next = y;
+            }
+        }
+        __syncthreads();
+        for (int e = t; e < na * nc; e += blockDim.x) Y[(int64_t)a0 * nc + e] = yt[e / nc][e % nc];
     }
 }
 
@@ -729,7 +849,11 @@ sc_status tridiag_solve(const double* alpha, const double* beta, int M, double* 
                         const double* e1_beta0, double* work, const int* halt, hipStream_t s) {
     if (M <= 0 || N <= 0) return SC_OK;
     const int nc = N * (cplx ? 2 : 1);
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, s, alpha, beta, M, Y, nc, e1_beta0, work, halt);
+    if (nc > 2 * kMaxCols) {
+        set_error("tridiag_solve: too many columns");
+        return SC_ERR_ARG;
+    }
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kBlock), 0, s, alpha, beta, M, Y, nc, e1_beta0, work, halt);
     SC_LAUNCH_CHECK();
     return SC_OK;
 }
