@@ -397,7 +397,7 @@ def main():
     mixed = w.precision == "mixed"
 
     def step():
-        return api.seeded_solve(op, B, w.m, w.freq, w.tol, mixed=mixed)
+        return api.single_seed_solve(op, B, w.m, w.freq, w.tol, mixed=mixed)
 
     for i in range(args.warmup):
         out = step()
@@ -484,8 +484,8 @@ def main():
     # ---- oracle on the host
     cpu = None
     if not args.no_cpu_baseline:
-        n_seed = out["basis"].m_done
-        cg_its = sum(out["cg_iters"])
+        n_seed = out["m_done"]
+        cg_its = sum(out["iters"]) - n_seed
         freq = max(w.freq, 1)
         reorth_vecs = sum(2 * (i - 1) for i in range(freq, n_seed + 1, freq)) if w.freq > 0 else 0
         counts = {"applies": n_seed + 1 + cg_its + 2 * w.nrhs,

@@ -168,7 +168,8 @@ typedef enum {
     SC_CALL_CG = 3,
     SC_CALL_KAPPA_GRAD = 4,
     SC_CALL_RELATED = 5,
-    SC_CALL_MULTISEED = 6
+    SC_CALL_MULTISEED = 6,
+    SC_CALL_SEEDED = 7
 } sc_call;
 
 /* Bytes of `work` needed by a call.  k: right-hand sides per call; m: basis
@@ -225,7 +226,7 @@ sc_status sc_project(int64_t n, const void* V_dev, int64_t ldv, sc_dtype v_dtype
  * it is above tol.  One iteration = one A-apply.
  * mixed = 0: FP64 throughout.  mixed = 1: FP32 vectors and operator with FP64
  * reliable updates: x and the true residual b - A x are kept in FP64 and
- * recomputed whenever the FP32 residual has fallen by 10x since the last
+ * recomputed whenever the FP32 residual has fallen by 100x since the last
  * update, and at FP32 convergence; a column is converged only when its FP64
  * true residual is <= tol.  (Wilson needs U32_dev.)
  * iters (host, k ints), relres (host, k doubles: true relative residuals).
@@ -234,6 +235,29 @@ sc_status sc_project(int64_t n, const void* V_dev, int64_t ldv, sc_dtype v_dtype
 sc_status sc_solve_cg(const sc_op* op, int mixed, const void* B_dev, int64_t ldb, void* X_dev,
                       int64_t ldx, int k, double tol, int maxit, int* iters, double* relres,
                       void* work_dev, size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------ the single-seed method as one call
+ * The seed algorithm of Section 3 (steps 1-9) on system 1 (column 0 of B)
+ * from x = 0, m Lanczos steps with reorthogonalization every reorth_freq
+ * (0: never; the basis is complex64 / FP32 when mixed = 1); columns 1..k-1
+ * seeded by the projection over its basis (steps 4 and 7, batched:
+ * x^j = V_m T_m^{-1} V_m^H b^j); then CG (Section 2.2, as sc_solve_cg with the
+ * same mixed) finishes every column from its guess.  The result is that of
+ * sc_seed_lanczos, sc_project and sc_solve_cg called in turn from zero
+ * guesses (up to rounding order); here x^1 and the other guesses are formed
+ * in one pass over the basis.  The basis is not returned.
+ *   B_dev: n x k (ldb), the op's dtype, read only.  X_dev: n x k (ldx),
+ *   written.  iters (host, k): A-applies per system (system 1 counts its m_done
+ *   seed steps).  relres (host, k): true relative residuals.  m_done (host).
+ * Needs sc_workspace_size(op, SC_CALL_SEEDED, k, m, dtype) bytes (dtype: the
+ * op's dtype, or its single-precision dtype when mixed = 1).  Synchronises
+ * the host once after the seed phase and once per chunk of CG iterations.
+ * Returns SC_OK, SC_NOT_CONVERGED, SC_BREAKDOWN (seed phase stopped early at
+ * an invariant subspace), or an error (SC_ERR_NOT_PD, SC_ERR_NONFINITE from
+ * the seed phase; SC_ERR_ARG, SC_ERR_WORKSPACE, SC_ERR_HIP). */
+sc_status sc_seeded_solve(const sc_op* op, int mixed, const void* B_dev, int64_t ldb, void* X_dev,
+                          int64_t ldx, int k, int m, int reorth_freq, double tol, int maxit, int* iters,
+                          double* relres, int* m_done, void* work_dev, size_t work_bytes, void* stream);
 
 /* ------------------------------------------------------------------ related right-hand sides
  * Single seeding of related systems (Section 2.3, the algorithm for related

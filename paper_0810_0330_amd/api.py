@@ -28,7 +28,7 @@ LIB_PATH = os.path.join(_HERE, "libseedcg.so")
 
 SC_R64, SC_C64, SC_C128, SC_R32 = 0, 1, 2, 3
 (SC_CALL_APPLY, SC_CALL_SEED, SC_CALL_PROJECT, SC_CALL_CG, SC_CALL_KAPPA_GRAD, SC_CALL_RELATED,
- SC_CALL_MULTISEED) = 0, 1, 2, 3, 4, 5, 6
+ SC_CALL_MULTISEED, SC_CALL_SEEDED) = 0, 1, 2, 3, 4, 5, 6, 7
 STATUS = {0: "SC_OK", 1: "SC_NOT_CONVERGED", 2: "SC_BREAKDOWN", -1: "SC_ERR_ARG", -2: "SC_ERR_HIP",
           -3: "SC_ERR_NOT_PD", -4: "SC_ERR_NONFINITE", -5: "SC_ERR_WORKSPACE", -6: "SC_ERR_UNSUPPORTED"}
 
@@ -65,6 +65,8 @@ _PROTOS = {
                                _P, _SZ, _P],
     "sc_related_solve": [_P, _INT, _P, _I64, _P, _I64, _INT, _INT, _INT, _DBL, _INT, ctypes.POINTER(_INT),
                          ctypes.POINTER(_DBL), ctypes.POINTER(_INT), _P, _SZ, _P],
+    "sc_seeded_solve": [_P, _INT, _P, _I64, _P, _I64, _INT, _INT, _INT, _DBL, _INT, ctypes.POINTER(_INT),
+                        ctypes.POINTER(_DBL), ctypes.POINTER(_INT), _P, _SZ, _P],
     "sc_last_error": [],
 }
 
@@ -399,6 +401,28 @@ def multiple_seed_solve(op, B, tol, maxit=100000):
                                       _ptr(w), w.numel(), _stream())
     _check(st, ok=(0, 1))
     return {"X": X, "iters": list(iters), "relres": list(rel), "status": st}
+
+
+def single_seed_solve(op, B, m, freq, tol, mixed=False, maxit=100000):
+    """The single-seed method in one library call (sc_seeded_solve): seed on row 0 of B from zero,
+    project rows 1.. over its basis, finish every row with CG.  Same result as seeded_solve (up to rounding
+    order), with x^1 formed together with the other guesses in one pass over the basis; the basis is not
+    returned.
+    Returns dict(X, iters (row 0 counts the seed steps), relres, m_done, status)."""
+    B = op._vec(B, op.dtype)
+    k = B.shape[0]
+    X = torch.empty_like(B)
+    nb = _SZ()
+    dt = op.sc_dtype if not mixed else _DT_OF[op.single_dtype]
+    _check(lib().sc_workspace_size(op.handle, SC_CALL_SEEDED, k, int(m), dt, ctypes.byref(nb)))
+    w = _work(nb.value, op.device)
+    iters = (ctypes.c_int * k)()
+    rel = (ctypes.c_double * k)()
+    md = _INT()
+    st = lib().sc_seeded_solve(op.handle, 1 if mixed else 0, _ptr(B), op.n, _ptr(X), op.n, k, int(m), int(freq),
+                               float(tol), int(maxit), iters, rel, ctypes.byref(md), _ptr(w), w.numel(), _stream())
+    _check(st, ok=(0, 1, 2))
+    return {"X": X, "iters": list(iters), "relres": list(rel), "m_done": md.value, "status": st}
 
 
 def related_rhs_solve(op, B, m, freq, tol, mixed=False, maxit=100000):

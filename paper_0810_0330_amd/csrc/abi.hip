@@ -197,6 +197,10 @@ sc_status sc_workspace_size(const sc_op* op, int call, int k, int m, sc_dtype dt
             SC_ARG(op && dtype_ok_for(op, dtype), "op NULL or dtype not valid for the op");
             *bytes = related_workspace(op, std::max(k, 1), std::max(m, 1), is_single(dtype));
             return SC_OK;
+        case SC_CALL_SEEDED:
+            SC_ARG(op && dtype_ok_for(op, dtype), "op NULL or dtype not valid for the op");
+            *bytes = seeded_workspace(op, std::max(k, 1), std::max(m, 1), is_single(dtype));
+            return SC_OK;
         default:
             SC_ARG(false, "unknown call id");
     }
@@ -402,6 +406,29 @@ sc_status sc_related_solve(const sc_op* op, int mixed, const void* B_dev, int64_
     *m_done = 0;
     return related_solve(op, mixed, B_dev, ldb, X_dev, ldx, k, m, reorth_freq, tol, maxit, iters, relres, m_done,
                          work_dev, work_bytes, (hipStream_t)stream);
+    SC_GUARD_END
+}
+
+sc_status sc_seeded_solve(const sc_op* op, int mixed, const void* B_dev, int64_t ldb, void* X_dev, int64_t ldx,
+                          int k, int m, int reorth_freq, double tol, int maxit, int* iters, double* relres,
+                          int* m_done, void* work_dev, size_t work_bytes, void* stream) {
+    SC_GUARD_BEGIN
+    SC_ARG(op, "op is NULL");
+    SC_ARG(k >= 1 && m >= 1 && reorth_freq >= 0 && maxit >= 1, "need k >= 1, m >= 1, reorth_freq >= 0, maxit >= 1");
+    SC_ARG(tol > 0.0 && std::isfinite(tol), "tol must be positive and finite");
+    SC_ARG(B_dev && X_dev && work_dev, "NULL device pointer");
+    SC_ARG(iters && relres && m_done, "NULL host pointer");
+    SC_ARG(!(mixed && op->kind == SC_OPK_WILSON && !op->U32), "mixed precision needs U32 links");
+    SC_ARG(ldb >= op->n && ldx >= op->n, "ldb or ldx smaller than n");
+    SC_ARG(aligned(B_dev, dtype_bytes(op->dtype)) && aligned(X_dev, dtype_bytes(op->dtype)),
+           "misaligned device pointer");
+    if (work_bytes < seeded_workspace(op, k, m, mixed != 0) - 256) {
+        set_error("seeded_solve: work buffer too small");
+        return SC_ERR_WORKSPACE;
+    }
+    *m_done = 0;
+    return seeded_solve(op, mixed, B_dev, ldb, X_dev, ldx, k, m, reorth_freq, tol, maxit, iters, relres, m_done,
+                        work_dev, work_bytes, (hipStream_t)stream);
     SC_GUARD_END
 }
 

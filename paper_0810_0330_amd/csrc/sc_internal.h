@@ -134,9 +134,10 @@ sc_status seed_pretune(const sc_op* op, bool single, const SeedWork& w, hipStrea
 // steps 1-9 enqueued with no host synchronisation (capturable)
 sc_status seed_enqueue_any(const sc_op* op, const void* b1, void* x1, int m, int freq, void* V, int64_t ldv,
                            sc_dtype vdt, double* alpha, double* beta, const SeedWork& w, hipStream_t s);
-// one synchronisation: final state, then x^1
+// one synchronisation: final state, then x^1 (unless form_x1 is false)
 sc_status seed_finalize_any(const sc_op* op, void* x1, void* V, int64_t ldv, sc_dtype vdt, double* alpha,
-                            double* beta, int* m_done, const SeedWork& w, hipStream_t s, sc_status* result);
+                            double* beta, int* m_done, const SeedWork& w, hipStream_t s, sc_status* result,
+                            bool form_x1 = true);
 
 // ---------------------------------------------------------------- projection and CG
 size_t project_workspace(int64_t n, int m, bool cpl);
@@ -151,6 +152,12 @@ sc_status solve_cg(const sc_op* op, int mixed, const void* B, int64_t ldb, void*
 size_t multiseed_workspace(const sc_op* op, int k);
 sc_status multiseed_solve(const sc_op* op, const void* B, int64_t ldb, void* X, int64_t ldx, int k, double tol,
                           int maxit, int* iters, double* relres, void* work, size_t work_bytes, hipStream_t s);
+
+// ---------------------------------------------------------------- the single-seed method as one call (seeded.hip)
+size_t seeded_workspace(const sc_op* op, int k, int m, bool mixed);
+sc_status seeded_solve(const sc_op* op, int mixed, const void* B, int64_t ldb, void* X, int64_t ldx, int k, int m,
+                       int freq, double tol, int maxit, int* iters, double* relres, int* m_done, void* work,
+                       size_t work_bytes, hipStream_t s);
 
 // ---------------------------------------------------------------- related right-hand sides (related.hip)
 size_t related_workspace(const sc_op* op, int k, int m, bool mixed);

@@ -507,7 +507,7 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
 // Reads the phase's final state (one synchronisation) and forms x^1.
 template <typename R>
 static sc_status seed_finalize(const sc_op* op, void* x1, R* V, int64_t ldv, double* alpha, double* beta,
-                               int* m_done, const SeedWork& w, hipStream_t s, sc_status* result) {
+                               int* m_done, const SeedWork& w, hipStream_t s, sc_status* result, bool form_x1) {
     const bool single = sizeof(R) == 4;
     const bool cpl = is_complex(op->dtype);
     SeedState hst;
@@ -516,7 +516,7 @@ static sc_status seed_finalize(const sc_op* op, void* x1, R* V, int64_t ldv, dou
     *m_done = hst.m_done;
     *result = (sc_status)hst.status;
     // x^1 = x0 + V_md T_md^{-1} (beta_0 e_1)
-    if (hst.m_done >= 1 && hst.status != SC_ERR_NONFINITE) {
+    if (form_x1 && hst.m_done >= 1 && hst.status != SC_ERR_NONFINITE) {
         SC_TRY(tridiag_solve(alpha, beta, hst.m_done, w.y, 1, cpl, beta, w.trid, nullptr, s));
         ColPtrs<void> xc{};
         xc.p[0] = x1;
@@ -542,9 +542,11 @@ sc_status seed_enqueue_any(const sc_op* op, const void* b1, void* x1, int m, int
 }
 
 sc_status seed_finalize_any(const sc_op* op, void* x1, void* V, int64_t ldv, sc_dtype vdt, double* alpha,
-                            double* beta, int* m_done, const SeedWork& w, hipStream_t s, sc_status* result) {
-    if (is_single(vdt)) return seed_finalize<float>(op, x1, (float*)V, ldv, alpha, beta, m_done, w, s, result);
-    return seed_finalize<double>(op, x1, (double*)V, ldv, alpha, beta, m_done, w, s, result);
+                            double* beta, int* m_done, const SeedWork& w, hipStream_t s, sc_status* result,
+                            bool form_x1) {
+    if (is_single(vdt))
+        return seed_finalize<float>(op, x1, (float*)V, ldv, alpha, beta, m_done, w, s, result, form_x1);
+    return seed_finalize<double>(op, x1, (double*)V, ldv, alpha, beta, m_done, w, s, result, form_x1);
 }
 
 SeedWork seed_carve(void* work, size_t work_bytes, const sc_op* op, int m, bool single, bool* ok) {
@@ -572,8 +574,8 @@ sc_status seed_lanczos(const sc_op* op, const void* b1, void* x1, int m, int fre
     }
     sc_status result = SC_OK;
     SC_TRY(seed_enqueue_any(op, b1, x1, m, freq, V, ldv, vdt, alpha, beta, w, s));
-    if (single) SC_TRY(seed_finalize<float>(op, x1, (float*)V, ldv, alpha, beta, m_done, w, s, &result));
-    else SC_TRY(seed_finalize<double>(op, x1, (double*)V, ldv, alpha, beta, m_done, w, s, &result));
+    if (single) SC_TRY(seed_finalize<float>(op, x1, (float*)V, ldv, alpha, beta, m_done, w, s, &result, true));
+    else SC_TRY(seed_finalize<double>(op, x1, (double*)V, ldv, alpha, beta, m_done, w, s, &result, true));
     if (result == SC_ERR_NOT_PD) set_error("seed_lanczos: non-positive pivot, A is not positive definite");
     if (result == SC_ERR_NONFINITE) set_error("seed_lanczos: non-finite value in the Lanczos recurrence");
     return result;

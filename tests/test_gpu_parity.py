@@ -309,6 +309,93 @@ def test_seeded_solve_wilson_8x4(wilson8):
         assert np.linalg.norm(X[:, j] - ref["X"][:, j]) / np.linalg.norm(ref["X"][:, j]) <= 2 * 320 * w.tol
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_single_seed_driver_wilson_8x4(wilson8, mixed):
+    # the one-call driver (sc_seeded_solve): x^1 formed with the other
+    # guesses in one pass over the basis
+    w, inp, oop, ref = wilson8
+    _say("single-seed driver wilson 8^4 m=150 freq=1 mixed", mixed)
+    op = api.Op.wilson(w.dims, torch.from_numpy(api.pack_links(inp["U"])).to(DEV), w.kappa)
+    out = api.single_seed_solve(op, _to_lib(inp["B"]), w.m, w.freq, w.tol, mixed=mixed)
+    assert out["status"] == 0 and out["m_done"] == ref["seed"].m_done
+    assert max(out["relres"]) <= w.tol
+    hor = _horizon(oop, inp["B"][:, :1], w.m, w.freq, ref["seed"])
+    lo, hi = _oracle_iter_range(oop, inp["B"], w.m, w.freq, w.tol, ref["iters"], hor)
+    if mixed:
+        # FP32 recurrences with FP64 reliable updates: counts of systems 2.. within
+        # +-4 of the FP64 oracle; system 1's x^1 comes from a complex64 basis, so
+        # its CG needs a few iterations the FP64 oracle does not: held to the
+        # three separate calls (same arithmetic) instead
+        three = api.seeded_solve(op, _to_lib(inp["B"]), w.m, w.freq, w.tol, mixed=True)
+        for a, b in zip(out["iters"], three["iters"]):
+            assert abs(a - b) <= 1, (out["iters"], three["iters"])
+        lo, hi = [a - 2 for a in lo[1:]], [b + 2 for b in hi[1:]]
+        _check_iters(out["iters"][1:], lo, hi)
+    else:
+        _check_iters(out["iters"], lo, hi)
+    X = _to_nat(out["X"])
+    for j in range(w.nrhs):
+        r = inp["B"][:, j] - oop(X[:, j])
+        assert np.linalg.norm(r) / np.linalg.norm(inp["B"][:, j]) <= w.tol
+        assert np.linalg.norm(X[:, j] - ref["X"][:, j]) / np.linalg.norm(ref["X"][:, j]) <= 2 * 320 * w.tol
+
+
+def test_single_seed_driver_column_groups():
+    # 40 right-hand sides: two column groups of the coefficient block (the
+    # first holding beta_0 e_1), against the oracle's seeded solve and the
+    # three separate calls
+    _say("single-seed driver laplace 32x32 k=40 m=300 freq=10")
+    oop = ops.Laplace2DOp(32, 32)
+    B = synth.real_gaussian(1024, 40, synth.rng(41, 1))
+    tol = 1e-10
+    ref = o_seeded_solve(oop, B, 300, 10, tol)
+    op = api.Op.laplace2d(32, 32)
+    Bl = torch.from_numpy(B.T.copy()).to(DEV)
+    out = api.single_seed_solve(op, Bl, 300, 10, tol)
+    three = api.seeded_solve(op, Bl, 300, 10, tol)
+    assert out["m_done"] == three["basis"].m_done == ref["seed"].m_done
+    assert max(out["relres"]) <= tol
+    for a, b in zip(out["iters"], three["iters"]):
+        assert abs(a - b) <= 1, (out["iters"], three["iters"])
+    X = out["X"].cpu().numpy().T
+    cond = (4 + 4 * np.cos(np.pi / 33)) / (4 - 4 * np.cos(np.pi / 33))
+    for j in range(40):
+        r = B[:, j] - oop(X[:, j])
+        assert np.linalg.norm(r) / np.linalg.norm(B[:, j]) <= tol
+        assert np.linalg.norm(X[:, j] - ref["X"][:, j]) / np.linalg.norm(ref["X"][:, j]) <= 2 * cond * tol
+
+
+def test_single_seed_driver_breakdown():
+    # b^1 supported on 150 of the 600 coordinates of a diagonal A: its Krylov
+    # space is exhausted at step 150 of m = 300, so only 150 basis vectors
+    # enter the projection
+    _say("single-seed driver: breakdown at 150 of m = 300")
+    g = np.random.default_rng(3)
+    d = np.linspace(1.0, 3.0, 600)
+    B = g.standard_normal((600, 3))
+    B[:, 0] = 0.0
+    B[g.choice(600, 150, replace=False), 0] = g.standard_normal(150)
+    ores = o_seed(ops.DiagOp(d), B[:, :1], m=300, freq=1)
+    op = api.Op.diag(torch.from_numpy(d).to(DEV))
+    out = api.single_seed_solve(op, torch.from_numpy(B.T.copy()).to(DEV), 300, 1, 1e-12)
+    assert out["status"] == 2 and out["m_done"] == ores.m_done == 150
+    assert out["iters"][0] <= 150 + 2  # x^1 solves system 1 on its invariant subspace
+    assert max(out["relres"]) <= 1e-12
+    np.testing.assert_allclose(out["X"].cpu().numpy().T, B / d[:, None], rtol=1e-9, atol=1e-12)
+
+
+def test_single_seed_driver_zero_seed_rhs():
+    _say("single-seed driver: b^1 = 0")
+    op = api.Op.laplace2d(16, 16)
+    B = torch.zeros((3, 256), dtype=torch.float64, device=DEV)
+    B[1] = 1.0
+    B[2, ::3] = -2.0
+    out = api.single_seed_solve(op, B, 20, 5, 1e-10)
+    assert out["status"] == 2 and out["m_done"] == 0
+    assert float(out["X"][0].abs().max()) == 0.0 and out["iters"][0] == 0
+    assert max(out["relres"][1:]) <= 1e-10
+
+
 def test_mixed_cg_wilson_8x4(wilson8):
     w, inp, oop, ref = wilson8
     _say("mixed cg wilson 8^4")
