@@ -24,7 +24,9 @@ template sc_status fill<unsigned>(unsigned*, int64_t, unsigned, hipStream_t);
 template sc_status fill<int>(int*, int64_t, int, hipStream_t);
 template sc_status fill<float>(float*, int64_t, float, hipStream_t);
 
-// z = a x + b y (4 elements per thread-iteration)
+// z = a x + b y: four elements per thread and trip, a grid stride apart, so
+// every load instruction of a wave covers 64 consecutive elements and four of
+// them are in flight before the first is used
 template <typename ZT, typename XT, typename YT>
 __global__ __launch_bounds__(kBlock) void k_lincomb(ZT* __restrict__ z, int64_t ldz, const XT* __restrict__ x,
                                                     int64_t ldx, const YT* __restrict__ y, int64_t ldy, int64_t N,
@@ -33,17 +35,27 @@ __global__ __launch_bounds__(kBlock) void k_lincomb(ZT* __restrict__ z, int64_t 
     ZT* zc = z + col * ldz;
     const XT* xc = x + col * ldx;
     const YT* yc = y ? y + col * ldy : nullptr;
-    const int64_t stride = (int64_t)gridDim.x * kBlock * 4;
-    for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 4; i0 < N; i0 += stride) {
-        const int64_t i1 = min(N, i0 + 4);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + 3 * stride < N; i += 4 * stride) {
+        double xv[4], yv[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int64_t i = i0; i < i0 + 4; ++i) {
-            if (i < i1) {
-                double v = a * (double)xc[i];
-                if (yc) v += b * (double)yc[i];
-                zc[i] = (ZT)v;
-            }
+        for (int u = 0; u < 4; ++u) xv[u] = (double)xc[i + u * stride];
+        if (yc) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) yv[u] = (double)yc[i + u * stride];
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double v = a * xv[u];
+            if (yc) v += b * yv[u];
+            zc[i + u * stride] = (ZT)v;
+        }
+    }
+    for (; i < N; i += stride) {
+        double v = a * (double)xc[i];
+        if (yc) v += b * (double)yc[i];
+        zc[i] = (ZT)v;
     }
 }
 
