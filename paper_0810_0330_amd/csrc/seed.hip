@@ -149,6 +149,20 @@ __global__ __launch_bounds__(kBlock) void k_lz_f(R* __restrict__ f, const R* __r
     __shared__ double sh[kWaves];
     if (st->halt) return;
     constexpr int W = Pack<R>::W;
+    constexpr int UN = 8;  // packs per thread whose loads are issued before alpha is summed
+    const int64_t stride = (int64_t)gridDim.x * kBlock * W;
+    const int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W;
+    Pack<R> o[UN], v[UN];
+    if constexpr (VEC) {
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const int64_t j = i0 + u * stride;
+            if (j + W <= N) {
+                o[u] = ldp(f, j);
+                v[u] = ldp(vi, j);
+            }
+        }
+    }
     const double a = sum_partials(part_a, G, sh);
     const double d = (i == 1) ? a : a - beta[i - 1] * beta[i - 1] / delta[i - 1];
     const bool bad = !isfinite(a) || !(d > 0.0);
@@ -167,44 +181,34 @@ __global__ __launch_bounds__(kBlock) void k_lz_f(R* __restrict__ f, const R* __r
     if (bad) return;
     const R aR = (R)a;
     double acc = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * kBlock * W;
-    int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W;
+    int64_t j = i0;
     if constexpr (VEC) {
-        // four packs per trip, all loads issued first (more bytes in flight
-        // per wave); the sum runs in the same order as the loop below
-        constexpr int UN = 4;
-        for (; i0 + (UN - 1) * stride + W <= N; i0 += UN * stride) {
-            Pack<R> o[UN], v[UN];
+        // the prefetched packs, in the order of the loop below
 #pragma unroll
-            for (int u = 0; u < UN; ++u) {
-                o[u] = ldp(f, i0 + u * stride);
-                v[u] = ldp(vi, i0 + u * stride);
-            }
-#pragma unroll
-            for (int u = 0; u < UN; ++u) {
-#pragma unroll
-                for (int e = 0; e < W; ++e) {
-                    o[u].v[e] = o[u].v[e] - aR * v[u].v[e];
-                    acc += (double)o[u].v[e] * (double)o[u].v[e];
-                }
-                stp(f, i0 + u * stride, o[u]);
-            }
-        }
-    }
-    for (; i0 < N; i0 += stride) {
-        if (VEC && i0 + W <= N) {
-            Pack<R> o = ldp(f, i0);
-            const Pack<R> v = ldp(vi, i0);
+        for (int u = 0; u < UN; ++u, j += stride) {
+            if (j + W > N) break;
 #pragma unroll
             for (int e = 0; e < W; ++e) {
-                o.v[e] = o.v[e] - aR * v.v[e];
-                acc += (double)o.v[e] * (double)o.v[e];
+                o[u].v[e] = o[u].v[e] - aR * v[u].v[e];
+                acc += (double)o[u].v[e] * (double)o[u].v[e];
             }
-            stp(f, i0, o);
+            stp(f, j, o[u]);
+        }
+    }
+    for (; j < N; j += stride) {
+        if (VEC && j + W <= N) {
+            Pack<R> ov = ldp(f, j);
+            const Pack<R> vv = ldp(vi, j);
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                ov.v[e] = ov.v[e] - aR * vv.v[e];
+                acc += (double)ov.v[e] * (double)ov.v[e];
+            }
+            stp(f, j, ov);
         } else {
-            for (int64_t j = i0; j < min(N, i0 + W); ++j) {
-                const R fv = f[j] - aR * vi[j];
-                f[j] = fv;
+            for (int64_t q = j; q < min(N, j + W); ++q) {
+                const R fv = f[q] - aR * vi[q];
+                f[q] = fv;
                 acc += (double)fv * (double)fv;
             }
         }
@@ -255,7 +259,20 @@ __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const 
     const int b = blockIdx.x;
     const int L = (b % kXcd) * per_xcd + b / kXcd;
     if (L >= ntile) return;  // uniform over the block
-    const double bn = sqrt(sum_partials(part, G, sh));
+    const int mu = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int s = L * 64 + l;
+    const bool ok = s < (int)g.V;
+    const unsigned uV = (unsigned)g.V;
+    // the hops of D f first (they do not need beta), so that the latency of
+    // the partial sum below overlaps their loads
+    cplx<R> acc[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
+    if (ok) dir_hops<false, R>(acc, f, U, g, uV, s, mu, tsign);
+    dir_stash(red, mu, l, acc);
+    const double bn = sqrt(sum_partials(part, G, sh));  // its barriers also order the stash
     const bool fin = isfinite(bn);
     const bool brk = fin && !(bn > kBreakdownTol * st->amax);
     if (b == 0 && threadIdx.x == 0) {  // block 0 always holds a tile
@@ -274,10 +291,6 @@ __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const 
             st->m_done = im1;
         }
     }
-    const int mu = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int s = L * 64 + l;
-    const bool ok = s < (int)g.V;
-    const unsigned uV = (unsigned)g.V;
     if (brk || !fin) {  // the basis ends here: v_i = 0, as the separate step 9 stores
         if (ok)
 #pragma unroll
@@ -286,14 +299,6 @@ __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const 
                     typename vec2<VT>::type{VT(0), VT(0)};
         return;
     }
-    cplx<R> acc[4][3];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
-    if (ok) dir_hops<false, R>(acc, f, U, g, uV, s, mu, tsign);
-    dir_stash(red, mu, l, acc);
-    __syncthreads();
     if (!ok) return;
     const R bR = (R)bn;
 #pragma unroll
