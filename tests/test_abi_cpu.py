@@ -91,6 +91,34 @@ def test_op_create_info_destroy_on_host(lib):
     assert lib.sc_op_destroy(out) == 0
 
 
+def test_seeded_driver_argument_errors(lib):
+    # sc_seeded_solve validates on the host before any device call
+    out = ctypes.c_void_p()
+    assert lib.sc_op_laplace2d(32, 16, ctypes.byref(out)) == 0
+    nb = ctypes.c_size_t()
+    assert lib.sc_workspace_size(out, 7, 3, 50, 0, ctypes.byref(nb)) == 0 and nb.value > 51 * 512 * 8
+    p = ctypes.c_void_p(4096)
+    it = (ctypes.c_int * 3)()
+    rr = (ctypes.c_double * 3)()
+    md = ctypes.c_int()
+
+    def call(op=out, k=3, m=50, freq=10, tol=1e-8, maxit=100, ldb=512, work=1 << 30, mdp=ctypes.byref(md)):
+        return lib.sc_seeded_solve(op, 0, p, ctypes.c_int64(ldb), p, ctypes.c_int64(512), k, m, freq,
+                                   ctypes.c_double(tol), maxit, it, rr, mdp, p, ctypes.c_size_t(work), None)
+
+    assert call(op=None) == -1
+    assert call(k=0) == -1
+    assert call(m=0) == -1
+    assert call(freq=-1) == -1
+    assert call(tol=0.0) == -1 and b"tol" in lib.sc_last_error()
+    assert call(tol=float("inf")) == -1
+    assert call(maxit=0) == -1
+    assert call(ldb=511) == -1 and b"ldb" in lib.sc_last_error()
+    assert call(mdp=None) == -1
+    assert call(work=16) == -5
+    assert lib.sc_op_destroy(out) == 0
+
+
 def test_timer_host_side(lib):
     # enabling, reading with no recorded launches and the class check need no device
     ms, nl, by, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
