@@ -28,6 +28,9 @@ seeded     -- the whole single-seed driver (seed, project, CG), the related
 mixed      -- a float32 emulation of CG with FP64 reliable updates (used to
               state expected mixed-precision behaviour; parity unpinned).
 grad       -- gradients of L = sum_j Re<eta_j, x_j> with respect to b and kappa.
+indefinite -- the indefinite variant: gamma_5 D, the Lanczos seed without LU,
+              minimum-residual guesses through the (m+1) x m tridiagonal matrix,
+              and MINRES to finish each system.
 
 Parity status of each function is stated in its module header.
 """
