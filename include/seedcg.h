@@ -102,6 +102,16 @@ sc_status sc_op_diag(const double* d_dev, int64_t n, sc_op** out);
 sc_status sc_op_wilson_normal(const int dims[4], const void* U64_dev, const void* U32_dev,
                               double kappa, int t_antiperiodic, sc_op** out);
 
+/* Q = gamma_5 D, gamma_5 = diag(1, 1, -1, -1) in spin (the chiral basis):
+ * Hermitian and indefinite, one product with D per apply (Section 4 names it
+ * as the alternative to D^H D).  The system D x = b is Q x = gamma_5 b.
+ * Arguments, layouts and errors as sc_op_wilson_normal.  Used by
+ * sc_indefinite_solve and sc_solve_minres; with sc_seed_lanczos it turns
+ * the positive-pivot check off and forms x^1 as the minimum residual over the
+ * basis (QR of the (m+1) x m tridiagonal matrix) instead of by the LU. */
+sc_status sc_op_wilson_g5(const int dims[4], const void* U64_dev, const void* U32_dev, double kappa,
+                          int t_antiperiodic, sc_op** out);
+
 sc_status sc_op_destroy(sc_op* op);
 
 /* Vector length n and the op's full-precision dtype (SC_R64 or SC_C128). */
@@ -169,7 +179,9 @@ typedef enum {
     SC_CALL_KAPPA_GRAD = 4,
     SC_CALL_RELATED = 5,
     SC_CALL_MULTISEED = 6,
-    SC_CALL_SEEDED = 7
+    SC_CALL_SEEDED = 7,
+    SC_CALL_MINRES = 8,
+    SC_CALL_INDEFINITE = 9
 } sc_call;
 
 /* Bytes of `work` needed by a call.  k: right-hand sides per call; m: basis
@@ -258,6 +270,42 @@ sc_status sc_solve_cg(const sc_op* op, int mixed, const void* B_dev, int64_t ldb
 sc_status sc_seeded_solve(const sc_op* op, int mixed, const void* B_dev, int64_t ldb, void* X_dev,
                           int64_t ldx, int k, int m, int reorth_freq, double tol, int maxit, int* iters,
                           double* relres, int* m_done, void* work_dev, size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------ MINRES (Hermitian indefinite)
+ * MINRES (Paige and Saunders) on the k columns of B from the guesses in X,
+ * FP64, per-column scalars on the device: the finishing solver of the
+ * indefinite variant (for any Hermitian op; Q = gamma_5 D in particular).
+ * Stops a column when its recursive residual norm is <= tol ||b||, then
+ * verifies the true residual and restarts from r = b - A x while it is above
+ * tol (at most 5 times, as sc_solve_cg).  Synchronises once per 8
+ * iterations.  B_dev, X_dev (in/out): n x k in the op's dtype (ldb, ldx).
+ * iters (host, k): A-applies in the iterations; relres (host, k): true
+ * relative residuals.  Needs sc_workspace_size(op, SC_CALL_MINRES, k, 0,
+ * op dtype) bytes.  Returns SC_OK or SC_NOT_CONVERGED, or an error. */
+sc_status sc_solve_minres(const sc_op* op, const void* B_dev, int64_t ldb, void* X_dev, int64_t ldx,
+                          int k, double tol, int maxit, int* iters, double* relres, void* work_dev,
+                          size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------ the indefinite variant
+ * The seed method for a Hermitian indefinite op (Q = gamma_5 D; the remark of
+ * Section 3 on indefinite systems: a QR factorization of the Lanczos
+ * tridiagonal matrix in place of its LU), FP64, from zero guesses:
+ *   1. the Lanczos steps of the seed algorithm (1, 2, 5, 8, 9; m steps,
+ *      reorthogonalization every reorth_freq) on column 0 of B;
+ *   2. every column's guess x^j = V_m y_j, y_j = argmin || c_j - T~_m y || with
+ *      T~_m the (m+1) x m tridiagonal matrix, c_j = V_{m+1}^H b^j (c_1 =
+ *      beta_0 e_1), by a QR factorization of T~_m: the minimum residual over
+ *      the basis;
+ *   3. MINRES (as sc_solve_minres) from the guesses.
+ * B_dev: n x k (ldb), read only; X_dev: n x k (ldx), written.  iters (host,
+ * k): A-applies (column 0 counts its m_done seed steps); relres (host, k);
+ * m_done (host).  Needs sc_workspace_size(op, SC_CALL_INDEFINITE, k, m, op
+ * dtype) bytes.  Returns SC_OK, SC_NOT_CONVERGED, SC_BREAKDOWN (the seed
+ * phase met an invariant subspace), or an error. */
+sc_status sc_indefinite_solve(const sc_op* op, const void* B_dev, int64_t ldb, void* X_dev, int64_t ldx,
+                              int k, int m, int reorth_freq, double tol, int maxit, int* iters,
+                              double* relres, int* m_done, void* work_dev, size_t work_bytes,
+                              void* stream);
 
 /* ------------------------------------------------------------------ related right-hand sides
  * Single seeding of related systems (Section 2.3, the algorithm for related

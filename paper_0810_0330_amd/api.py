@@ -28,7 +28,7 @@ LIB_PATH = os.path.join(_HERE, "libseedcg.so")
 
 SC_R64, SC_C64, SC_C128, SC_R32 = 0, 1, 2, 3
 (SC_CALL_APPLY, SC_CALL_SEED, SC_CALL_PROJECT, SC_CALL_CG, SC_CALL_KAPPA_GRAD, SC_CALL_RELATED,
- SC_CALL_MULTISEED, SC_CALL_SEEDED) = 0, 1, 2, 3, 4, 5, 6, 7
+ SC_CALL_MULTISEED, SC_CALL_SEEDED, SC_CALL_MINRES, SC_CALL_INDEFINITE) = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9
 STATUS = {0: "SC_OK", 1: "SC_NOT_CONVERGED", 2: "SC_BREAKDOWN", -1: "SC_ERR_ARG", -2: "SC_ERR_HIP",
           -3: "SC_ERR_NOT_PD", -4: "SC_ERR_NONFINITE", -5: "SC_ERR_WORKSPACE", -6: "SC_ERR_UNSUPPORTED"}
 
@@ -45,6 +45,11 @@ _PROTOS = {
     "sc_op_laplace2d": [_INT, _INT, ctypes.POINTER(_P)],
     "sc_op_diag": [_P, _I64, ctypes.POINTER(_P)],
     "sc_op_wilson_normal": [ctypes.POINTER(_INT), _P, _P, _DBL, _INT, ctypes.POINTER(_P)],
+    "sc_op_wilson_g5": [ctypes.POINTER(_INT), _P, _P, _DBL, _INT, ctypes.POINTER(_P)],
+    "sc_solve_minres": [_P, _P, _I64, _P, _I64, _INT, _DBL, _INT, ctypes.POINTER(_INT), ctypes.POINTER(_DBL), _P, _SZ,
+                        _P],
+    "sc_indefinite_solve": [_P, _P, _I64, _P, _I64, _INT, _INT, _INT, _DBL, _INT, ctypes.POINTER(_INT),
+                            ctypes.POINTER(_DBL), ctypes.POINTER(_INT), _P, _SZ, _P],
     "sc_op_destroy": [_P],
     "sc_op_info": [_P, ctypes.POINTER(_I64), ctypes.POINTER(_INT)],
     "sc_op_apply": [_P, _INT, _P, _I64, _P, _I64, _INT, _P, _SZ, _P],
@@ -245,6 +250,19 @@ class Op:
         return cls(h, [U64, U32], U64.device, "wilson", dims=tuple(dims), kappa=float(kappa),
                    antiperiodic=antiperiodic)
 
+    @classmethod
+    def wilson_g5(cls, dims, U, kappa, antiperiodic=True, single=False):
+        """Q = gamma_5 D (Hermitian indefinite; D x = b is Q x = gamma_5 b).  Arguments as wilson()."""
+        _require_gpu(U)
+        U64 = U.to(torch.complex128).contiguous()
+        U32 = U64.to(torch.complex64) if single else None
+        d = (ctypes.c_int * 4)(*[int(v) for v in dims])
+        h = _P()
+        _check(lib().sc_op_wilson_g5(d, _ptr(U64), _ptr(U32) if U32 is not None else None, float(kappa),
+                                     1 if antiperiodic else 0, ctypes.byref(h)))
+        return cls(h, [U64, U32], U64.device, "wilson_g5", dims=tuple(dims), kappa=float(kappa),
+                   antiperiodic=antiperiodic)
+
     def _vec(self, X, dtype):
         if X.dim() == 1:
             X = X.reshape(1, -1)
@@ -421,6 +439,41 @@ def single_seed_solve(op, B, m, freq, tol, mixed=False, maxit=100000):
     md = _INT()
     st = lib().sc_seeded_solve(op.handle, 1 if mixed else 0, _ptr(B), op.n, _ptr(X), op.n, k, int(m), int(freq),
                                float(tol), int(maxit), iters, rel, ctypes.byref(md), _ptr(w), w.numel(), _stream())
+    _check(st, ok=(0, 1, 2))
+    return {"X": X, "iters": list(iters), "relres": list(rel), "m_done": md.value, "status": st}
+
+
+def solve_minres(op, B, tol, X0=None, maxit=100000):
+    """MINRES (FP64) on the rows of B from X0 (Hermitian op, e.g. Op.wilson_g5); returns (X, iters, relres)."""
+    B = op._vec(B, op.dtype)
+    X = torch.zeros_like(B) if X0 is None else op._vec(X0, op.dtype).clone()
+    k = B.shape[0]
+    nb = _SZ()
+    _check(lib().sc_workspace_size(op.handle, SC_CALL_MINRES, k, 0, op.sc_dtype, ctypes.byref(nb)))
+    w = _work(nb.value, op.device)
+    iters = (ctypes.c_int * k)()
+    rel = (ctypes.c_double * k)()
+    st = lib().sc_solve_minres(op.handle, _ptr(B), op.n, _ptr(X), op.n, k, float(tol), int(maxit), iters, rel,
+                               _ptr(w), w.numel(), _stream())
+    _check(st, ok=(0, 1))
+    return X, list(iters), list(rel)
+
+
+def indefinite_solve(op, B, m, freq, tol, maxit=100000):
+    """The indefinite variant (FP64): Lanczos seed on row 0 of B, minimum-residual guesses for every row
+    over its basis (QR of the (m+1) x m tridiagonal matrix), MINRES to finish.
+    Returns dict(X, iters (row 0 counts the seed steps), relres, m_done, status)."""
+    B = op._vec(B, op.dtype)
+    k = B.shape[0]
+    X = torch.empty_like(B)
+    nb = _SZ()
+    _check(lib().sc_workspace_size(op.handle, SC_CALL_INDEFINITE, k, int(m), op.sc_dtype, ctypes.byref(nb)))
+    w = _work(nb.value, op.device)
+    iters = (ctypes.c_int * k)()
+    rel = (ctypes.c_double * k)()
+    md = _INT()
+    st = lib().sc_indefinite_solve(op.handle, _ptr(B), op.n, _ptr(X), op.n, k, int(m), int(freq), float(tol),
+                                   int(maxit), iters, rel, ctypes.byref(md), _ptr(w), w.numel(), _stream())
     _check(st, ok=(0, 1, 2))
     return {"X": X, "iters": list(iters), "relres": list(rel), "m_done": md.value, "status": st}
 

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libseedcg.so")
-SOURCES = ["abi.hip", "k_stencil.hip", "k_blas.hip", "k_tsgemm.hip", "seed.hip", "cg.hip", "timer.hip", "grad.hip", "batch.hip", "related.hip", "multiseed.hip", "seeded.hip"]
+SOURCES = ["abi.hip", "k_stencil.hip", "k_blas.hip", "k_tsgemm.hip", "seed.hip", "cg.hip", "timer.hip", "grad.hip", "batch.hip", "related.hip", "multiseed.hip", "seeded.hip", "minres.hip", "indefinite.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -146,6 +146,15 @@ sc_status sc_op_wilson_normal(const int dims[4], const void* U64_dev, const void
     SC_GUARD_END
 }
 
+sc_status sc_op_wilson_g5(const int dims[4], const void* U64_dev, const void* U32_dev, double kappa,
+                          int t_antiperiodic, sc_op** out) {
+    SC_GUARD_BEGIN
+    const sc_status st = sc_op_wilson_normal(dims, U64_dev, U32_dev, kappa, t_antiperiodic, out);
+    if (st == SC_OK) (*out)->kind = SC_OPK_WILSON_G5;
+    return st;
+    SC_GUARD_END
+}
+
 sc_status sc_op_destroy(sc_op* op) {
     SC_GUARD_BEGIN
     delete op;
@@ -197,6 +206,14 @@ sc_status sc_workspace_size(const sc_op* op, int call, int k, int m, sc_dtype dt
             SC_ARG(op && dtype_ok_for(op, dtype), "op NULL or dtype not valid for the op");
             *bytes = related_workspace(op, std::max(k, 1), std::max(m, 1), is_single(dtype));
             return SC_OK;
+        case SC_CALL_MINRES:
+            SC_ARG(op && dtype == op->dtype, "op NULL or dtype not the op's (MINRES runs in FP64)");
+            *bytes = minres_workspace(op, std::max(k, 1));
+            return SC_OK;
+        case SC_CALL_INDEFINITE:
+            SC_ARG(op && dtype == op->dtype, "op NULL or dtype not the op's (the indefinite variant runs in FP64)");
+            *bytes = indefinite_workspace(op, std::max(k, 1), std::max(m, 1));
+            return SC_OK;
         case SC_CALL_SEEDED:
             SC_ARG(op && dtype_ok_for(op, dtype), "op NULL or dtype not valid for the op");
             *bytes = seeded_workspace(op, std::max(k, 1), std::max(m, 1), is_single(dtype));
@@ -217,7 +234,7 @@ sc_status sc_op_apply(const sc_op* op, sc_dtype dtype, const void* X_dev, int64_
     SC_ARG(X_dev && Y_dev, "X or Y is NULL");
     SC_ARG(aligned(X_dev, dtype_bytes(dtype)) && aligned(Y_dev, dtype_bytes(dtype)), "X or Y misaligned");
     SC_ARG(ldx >= op->n && ldy >= op->n, "leading dimension smaller than n");
-    SC_ARG(!(op->kind == SC_OPK_WILSON && is_single(dtype) && !op->U32), "single precision needs U32 links");
+    SC_ARG(!(has_links(op) && is_single(dtype) && !op->U32), "single precision needs U32 links");
     if (work_bytes < apply_workspace(op, k, dtype) - 256 || (op_apply_tmp_elems(op) > 0 && !work_dev)) {
         set_error("op_apply: work buffer too small");
         return SC_ERR_WORKSPACE;
@@ -229,7 +246,7 @@ sc_status sc_op_apply(const sc_op* op, sc_dtype dtype, const void* X_dev, int64_
 sc_status sc_wilson_dslash(const sc_op* op, sc_dtype dtype, int which, const void* X_dev, int64_t ldx, void* Y_dev,
                            int64_t ldy, int k, void* stream) {
     SC_GUARD_BEGIN
-    SC_ARG(op && op->kind == SC_OPK_WILSON, "not a Wilson op");
+    SC_ARG(op && has_links(op), "not a Wilson op");
     SC_ARG(dtype == SC_C128 || dtype == SC_C64, "dtype must be SC_C128 or SC_C64");
     SC_ARG(which >= 0 && which <= 3, "which must be 0..3");
     SC_ARG(k >= 0, "k must be >= 0");
@@ -251,7 +268,7 @@ sc_status sc_seed_lanczos(const sc_op* op, const void* b1_dev, void* x1_dev, int
     SC_ARG(m >= 1, "m must be >= 1");
     SC_ARG(reorth_freq >= 0, "reorth_freq must be >= 0");
     SC_ARG(dtype_ok_for(op, v_dtype), "v_dtype not valid for the op");
-    SC_ARG(!(op->kind == SC_OPK_WILSON && is_single(v_dtype) && !op->U32), "single precision needs U32 links");
+    SC_ARG(!(has_links(op) && is_single(v_dtype) && !op->U32), "single precision needs U32 links");
     SC_ARG(b1_dev && x1_dev && V_dev && alpha_dev && beta_dev && work_dev, "NULL device pointer");
     SC_ARG(aligned(b1_dev, dtype_bytes(op->dtype)) && aligned(x1_dev, dtype_bytes(op->dtype)) &&
                aligned(V_dev, dtype_bytes(v_dtype)) && aligned(alpha_dev, 8) && aligned(beta_dev, 8),
@@ -304,7 +321,7 @@ sc_status sc_solve_cg(const sc_op* op, int mixed, const void* B_dev, int64_t ldb
     SC_ARG(aligned(B_dev, dtype_bytes(op->dtype)) && aligned(X_dev, dtype_bytes(op->dtype)),
            "misaligned device pointer");
     SC_ARG(ldb >= op->n && ldx >= op->n, "leading dimension smaller than n");
-    SC_ARG(!(mixed && op->kind == SC_OPK_WILSON && !op->U32), "mixed precision needs U32 links");
+    SC_ARG(!(mixed && has_links(op) && !op->U32), "mixed precision needs U32 links");
     if (work_bytes < cg_workspace(op, k, mixed != 0) - 256) {
         set_error("solve_cg: work buffer too small");
         return SC_ERR_WORKSPACE;
@@ -317,7 +334,7 @@ sc_status sc_solve_cg(const sc_op* op, int mixed, const void* B_dev, int64_t ldb
 sc_status sc_wilson_kappa_grad(const sc_op* op, const void* X_dev, int64_t ldx, const void* L_dev, int64_t ldl,
                                 int k, double* grad, void* work_dev, size_t work_bytes, void* stream) {
     SC_GUARD_BEGIN
-    SC_ARG(op && op->kind == SC_OPK_WILSON, "not a Wilson op");
+    SC_ARG(op && has_links(op), "not a Wilson op");
     SC_ARG(grad, "grad is NULL");
     SC_ARG(k >= 1, "k must be >= 1");
     SC_ARG(X_dev && L_dev && work_dev, "NULL device pointer");
@@ -342,7 +359,7 @@ static sc_status check_batch(int nsys, const sc_batch_system* sys) {
         SC_ARG(aligned(b.B_dev, dtype_bytes(b.op->dtype)) && aligned(b.X_dev, dtype_bytes(b.op->dtype)),
                "system B or X misaligned");
         SC_ARG(b.ldb >= b.op->n && b.ldx >= b.op->n, "system leading dimension smaller than n");
-        SC_ARG(!(b.mixed && b.op->kind == SC_OPK_WILSON && !b.op->U32), "mixed precision needs U32 links");
+        SC_ARG(!(b.mixed && has_links(b.op) && !b.op->U32), "mixed precision needs U32 links");
     }
     return SC_OK;
 }
@@ -370,7 +387,7 @@ sc_status sc_batch_solve(int nsys, sc_batch_system* systems, void* work_dev, siz
 
 sc_status sc_wilson_tune_info(const sc_op* op, sc_dtype dtype, int k, int* variant, float* us) {
     SC_GUARD_BEGIN
-    SC_ARG(op && op->kind == SC_OPK_WILSON, "not a Wilson op");
+    SC_ARG(op && has_links(op), "not a Wilson op");
     SC_ARG(dtype == SC_C128 || dtype == SC_C64, "dtype must be SC_C128 or SC_C64");
     SC_ARG(variant && us, "NULL argument");
     return wilson_tune_query(op, dtype == SC_C64, k, variant, us);
@@ -379,7 +396,7 @@ sc_status sc_wilson_tune_info(const sc_op* op, sc_dtype dtype, int k, int* varia
 
 sc_status sc_wilson_tune_set(const sc_op* op, sc_dtype dtype, int k, int variant) {
     SC_GUARD_BEGIN
-    SC_ARG(op && op->kind == SC_OPK_WILSON, "not a Wilson op");
+    SC_ARG(op && has_links(op), "not a Wilson op");
     SC_ARG(dtype == SC_C128 || dtype == SC_C64, "dtype must be SC_C128 or SC_C64");
     SC_ARG(k >= 1 && variant >= -1 && variant < SC_WILSON_VARIANTS, "k must be >= 1 and variant in -1..68");
     return wilson_tune_pin(op, dtype == SC_C64, k, variant);
@@ -395,7 +412,7 @@ sc_status sc_related_solve(const sc_op* op, int mixed, const void* B_dev, int64_
     SC_ARG(tol > 0.0 && std::isfinite(tol), "tol must be positive and finite");
     SC_ARG(B_dev && X_dev && work_dev, "NULL device pointer");
     SC_ARG(iters && relres && m_done, "NULL host pointer");
-    SC_ARG(!(mixed && op->kind == SC_OPK_WILSON && !op->U32), "mixed precision needs U32 links");
+    SC_ARG(!(mixed && has_links(op) && !op->U32), "mixed precision needs U32 links");
     SC_ARG(ldb >= op->n && ldx >= op->n, "ldb or ldx smaller than n");
     SC_ARG(aligned(B_dev, dtype_bytes(op->dtype)) && aligned(X_dev, dtype_bytes(op->dtype)),
            "misaligned device pointer");
@@ -418,7 +435,7 @@ sc_status sc_seeded_solve(const sc_op* op, int mixed, const void* B_dev, int64_t
     SC_ARG(tol > 0.0 && std::isfinite(tol), "tol must be positive and finite");
     SC_ARG(B_dev && X_dev && work_dev, "NULL device pointer");
     SC_ARG(iters && relres && m_done, "NULL host pointer");
-    SC_ARG(!(mixed && op->kind == SC_OPK_WILSON && !op->U32), "mixed precision needs U32 links");
+    SC_ARG(!(mixed && has_links(op) && !op->U32), "mixed precision needs U32 links");
     SC_ARG(ldb >= op->n && ldx >= op->n, "ldb or ldx smaller than n");
     SC_ARG(aligned(B_dev, dtype_bytes(op->dtype)) && aligned(X_dev, dtype_bytes(op->dtype)),
            "misaligned device pointer");
@@ -429,6 +446,49 @@ sc_status sc_seeded_solve(const sc_op* op, int mixed, const void* B_dev, int64_t
     *m_done = 0;
     return seeded_solve(op, mixed, B_dev, ldb, X_dev, ldx, k, m, reorth_freq, tol, maxit, iters, relres, m_done,
                         work_dev, work_bytes, (hipStream_t)stream);
+    SC_GUARD_END
+}
+
+sc_status sc_solve_minres(const sc_op* op, const void* B_dev, int64_t ldb, void* X_dev, int64_t ldx, int k,
+                          double tol, int maxit, int* iters, double* relres, void* work_dev, size_t work_bytes,
+                          void* stream) {
+    SC_GUARD_BEGIN
+    SC_ARG(op, "op is NULL");
+    SC_ARG(k >= 1 && maxit >= 1, "need k >= 1 and maxit >= 1");
+    SC_ARG(tol > 0.0 && std::isfinite(tol), "tol must be positive and finite");
+    SC_ARG(B_dev && X_dev && work_dev, "NULL device pointer");
+    SC_ARG(iters && relres, "NULL host pointer");
+    SC_ARG(ldb >= op->n && ldx >= op->n, "ldb or ldx smaller than n");
+    SC_ARG(aligned(B_dev, dtype_bytes(op->dtype)) && aligned(X_dev, dtype_bytes(op->dtype)),
+           "misaligned device pointer");
+    if (work_bytes < minres_workspace(op, k) - 256) {
+        set_error("minres: work buffer too small");
+        return SC_ERR_WORKSPACE;
+    }
+    return minres_solve(op, B_dev, ldb, X_dev, ldx, k, tol, maxit, iters, relres, work_dev, work_bytes,
+                        (hipStream_t)stream);
+    SC_GUARD_END
+}
+
+sc_status sc_indefinite_solve(const sc_op* op, const void* B_dev, int64_t ldb, void* X_dev, int64_t ldx, int k,
+                              int m, int reorth_freq, double tol, int maxit, int* iters, double* relres, int* m_done,
+                              void* work_dev, size_t work_bytes, void* stream) {
+    SC_GUARD_BEGIN
+    SC_ARG(op, "op is NULL");
+    SC_ARG(k >= 1 && m >= 1 && reorth_freq >= 0 && maxit >= 1, "need k >= 1, m >= 1, reorth_freq >= 0, maxit >= 1");
+    SC_ARG(tol > 0.0 && std::isfinite(tol), "tol must be positive and finite");
+    SC_ARG(B_dev && X_dev && work_dev, "NULL device pointer");
+    SC_ARG(iters && relres && m_done, "NULL host pointer");
+    SC_ARG(ldb >= op->n && ldx >= op->n, "ldb or ldx smaller than n");
+    SC_ARG(aligned(B_dev, dtype_bytes(op->dtype)) && aligned(X_dev, dtype_bytes(op->dtype)),
+           "misaligned device pointer");
+    if (work_bytes < indefinite_workspace(op, k, m) - 256) {
+        set_error("indefinite_solve: work buffer too small");
+        return SC_ERR_WORKSPACE;
+    }
+    *m_done = 0;
+    return indefinite_solve(op, B_dev, ldb, X_dev, ldx, k, m, reorth_freq, tol, maxit, iters, relres, m_done,
+                            work_dev, work_bytes, (hipStream_t)stream);
     SC_GUARD_END
 }
 

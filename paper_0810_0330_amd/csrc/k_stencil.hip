@@ -1017,12 +1017,29 @@ sc_status wilson_pass(const sc_op* op, bool single, int which, const void* X, in
 
 int64_t op_apply_tmp_elems(const sc_op* op) { return op->kind == SC_OPK_WILSON ? op->n : 0; }
 
+// gamma_5 = diag(1, 1, -1, -1) in spin: in the component-major layout the
+// lower two spins are components 6..11, the second half of each column
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_gamma5(R* __restrict__ y, int64_t ldy, int64_t half) {
+    R* c = y + blockIdx.y * ldy + half;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < half; i += (int64_t)gridDim.x * kBlock) c[i] = -c[i];
+}
+
 sc_status op_apply(const sc_op* op, bool single, const void* X, int64_t ldx, void* Y, int64_t ldy, int k, void* tmp,
                    hipStream_t s) {
     if (k <= 0) return SC_OK;
     if (op->kind == SC_OPK_WILSON) {
         SC_TRY(wilson_pass(op, single, 0, X, ldx, tmp, op->n, k, s));
         return wilson_pass(op, single, 1, tmp, op->n, Y, ldy, k, s);
+    }
+    if (op->kind == SC_OPK_WILSON_G5) {  // Q = gamma_5 D: one D pass, then the sign of the lower spins
+        SC_TRY(wilson_pass(op, single, 0, X, ldx, Y, ldy, k, s));
+        const int64_t half = 12 * op->vol;  // reals: 6 complex components of V sites
+        const dim3 grid((unsigned)std::min<int64_t>((half + kBlock - 1) / kBlock, 1024), (unsigned)k);
+        if (single) hipLaunchKernelGGL(k_gamma5<float>, grid, dim3(kBlock), 0, s, (float*)Y, 2 * ldy, half);
+        else hipLaunchKernelGGL(k_gamma5<double>, grid, dim3(kBlock), 0, s, (double*)Y, 2 * ldy, half);
+        SC_LAUNCH_CHECK();
+        return SC_OK;
     }
     dim3 grid((unsigned)((op->n + kBlock - 1) / kBlock), (unsigned)k);
     if (op->kind == SC_OPK_LAPLACE2D) {

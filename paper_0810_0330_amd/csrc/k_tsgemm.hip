@@ -845,6 +845,110 @@ __global__ __launch_bounds__(kBlock) void k_tridiag(const double* __restrict__ a
     }
 }
 
+// Least squares with the (M+1) x M tridiagonal T~ (T with the row beta_M e_M^T
+// appended): C (M+1 x nc, row-major, real) is overwritten so that its first M
+// rows hold y = argmin || C - T~ y || per column.  A QR factorization of T~
+// by M reflections G_k on rows (k, k+1), [u; w] -> [c u + s w; s u - c w],
+// the recurrences of MINRES (Paige and Saunders): thread 0 forms the
+// rotations and the three diagonals of R (r_kk, r_{k-1,k}, r_{k-2,k}); then
+// each column is rotated and back-substituted by one thread, over tiles of
+// rows staged in LDS.
+__global__ __launch_bounds__(kBlock) void k_tridiag_lsq(const double* __restrict__ alpha,
+                                                        const double* __restrict__ beta, int M, double* __restrict__ C,
+                                                        int nc, double* __restrict__ work) {
+    __shared__ double yt[kTriT + 1][2 * kMaxCols + 1];
+    __shared__ double ct[kTriT], st[kTriT], r0t[kTriT + 2], r1t[kTriT + 2], r2t[kTriT + 2];
+    double* cs = work;
+    double* sn = work + M;
+    double* rd = work + 2 * M;   // r_kk
+    double* ru1 = work + 3 * M;  // r_{k-1,k}
+    double* ru2 = work + 4 * M;  // r_{k-2,k}
+    const int t = threadIdx.x;
+    if (t == 0) {
+        double cp = -1.0, sp = 0.0, d1 = 0.0, ep = 0.0;
+        for (int k = 0; k < M; ++k) {
+            const double a = alpha[k], bn = beta[k + 1];
+            const double d2 = cp * d1 + sp * a;
+            const double g1 = sp * d1 - cp * a;
+            const double en = sp * bn;
+            const double d1n = -cp * bn;
+            const double g2 = sqrt(g1 * g1 + bn * bn);
+            const double c = g1 / g2, sv = bn / g2;
+            cs[k] = c;
+            sn[k] = sv;
+            rd[k] = g2;
+            ru1[k] = d2;
+            ru2[k] = ep;
+            cp = c;
+            sp = sv;
+            d1 = d1n;
+            ep = en;
+        }
+    }
+    __syncthreads();
+    // the reflections, in order, on each column (row k is final after G_k)
+    double carry = 0.0;
+    for (int a0 = 0; a0 < M; a0 += kTriT) {
+        const int na = min(kTriT, M - a0);
+        __syncthreads();
+        for (int e = t; e < (na + 1) * nc; e += blockDim.x) yt[e / nc][e % nc] = C[(int64_t)a0 * nc + e];
+        for (int i = t; i < na; i += blockDim.x) {
+            ct[i] = cs[a0 + i];
+            st[i] = sn[a0 + i];
+        }
+        __syncthreads();
+        if (t < nc) {
+            double u = a0 == 0 ? yt[0][t] : carry;
+            for (int i = 0; i < na; ++i) {
+                const double w = yt[i + 1][t];
+                yt[i][t] = ct[i] * u + st[i] * w;
+                u = st[i] * u - ct[i] * w;
+            }
+            carry = u;
+            yt[na][t] = u;
+        }
+        __syncthreads();
+        for (int e = t; e < (na + 1) * nc; e += blockDim.x) C[(int64_t)a0 * nc + e] = yt[e / nc][e % nc];
+    }
+    // back substitution: y_k = (u_k - r_{k,k+1} y_{k+1} - r_{k,k+2} y_{k+2}) / r_kk
+    double y1 = 0.0, y2 = 0.0;  // y_{k+1}, y_{k+2}
+    for (int a1 = M; a1 > 0; a1 -= kTriT) {
+        const int a0 = max(0, a1 - kTriT), na = a1 - a0;
+        __syncthreads();
+        for (int e = t; e < na * nc; e += blockDim.x) yt[e / nc][e % nc] = C[(int64_t)a0 * nc + e];
+        for (int i = t; i < na; i += blockDim.x) r0t[i] = rd[a0 + i];
+        for (int i = t; i < na + 2; i += blockDim.x) {
+            r1t[i] = a0 + i < M ? ru1[a0 + i] : 0.0;
+            r2t[i] = a0 + i < M ? ru2[a0 + i] : 0.0;
+        }
+        __syncthreads();
+        if (t < nc) {
+            for (int i = na - 1; i >= 0; --i) {
+                // r_{k,k+1} is the entry above the diagonal in column k+1, r_{k,k+2} two above in column k+2
+                const double y = (yt[i][t] - r1t[i + 1] * y1 - r2t[i + 2] * y2) / r0t[i];
+                yt[i][t] = y;
+                y2 = y1;
+                y1 = y;
+            }
+        }
+        __syncthreads();
+        for (int e = t; e < na * nc; e += blockDim.x) C[(int64_t)a0 * nc + e] = yt[e / nc][e % nc];
+    }
+}
+
+sc_status tridiag_lsq(const double* alpha, const double* beta, int M, double* C, int N, bool cplx, double* work,
+                      hipStream_t s) {
+    if (M <= 0 || N <= 0) return SC_OK;
+    const int nc = N * (cplx ? 2 : 1);
+    if (nc > 2 * kMaxCols) {
+        set_error("tridiag_lsq: too many columns");
+        return SC_ERR_ARG;
+    }
+    hipLaunchKernelGGL(k_tridiag_lsq, dim3(1), dim3(kBlock), 0, s, alpha, beta, M, C, nc, work);
+    SC_LAUNCH_CHECK();
+    return SC_OK;
+}
+
 sc_status tridiag_solve(const double* alpha, const double* beta, int M, double* Y, int N, bool cplx,
                         const double* e1_beta0, double* work, const int* halt, hipStream_t s) {
     if (M <= 0 || N <= 0) return SC_OK;

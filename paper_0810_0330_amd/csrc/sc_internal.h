@@ -4,7 +4,7 @@
 
 #include "sc_common.h"
 
-enum sc_op_kind { SC_OPK_LAPLACE2D = 0, SC_OPK_DIAG = 1, SC_OPK_WILSON = 2 };
+enum sc_op_kind { SC_OPK_LAPLACE2D = 0, SC_OPK_DIAG = 1, SC_OPK_WILSON = 2, SC_OPK_WILSON_G5 = 3 };
 
 struct sc_op {
     int kind;
@@ -22,6 +22,9 @@ struct sc_op {
     double kappa = 0.0;
     int antiperiodic = 1;
 };
+
+// operators built on the Wilson links (D^H D, and gamma_5 D, which is Hermitian indefinite)
+inline bool has_links(const sc_op* op) { return op->kind == SC_OPK_WILSON || op->kind == SC_OPK_WILSON_G5; }
 
 namespace sc {
 
@@ -103,6 +106,9 @@ sc_status gemm_cn(bool cplx, bool vsingle, const void* V, int64_t ldv, int64_t n
 // X_j[r] += scale * sum_a V[r,a] Y[a*N + j]
 sc_status gemm_nn(bool cplx, bool vsingle, const void* V, int64_t ldv, int64_t n, int M, const double* Y, int N,
                   bool xsingle, const ColPtrs<void>& X, double scale, const int* halt, hipStream_t s);
+// least squares with the (M+1) x M tridiagonal matrix (QR); C is M+1 x N, y in its first M rows; work 5 M doubles
+sc_status tridiag_lsq(const double* alpha, const double* beta, int M, double* C, int N, bool cplx, double* work,
+                      hipStream_t s);
 // Y (M x N, complex or real, row-major [a*N+j]) <- T_M^{-1} Y by the LU recurrences.
 // If e1_beta0 != null, Y is first set to beta0 e_1 (N = 1).  work: 2*M doubles.
 sc_status tridiag_solve(const double* alpha, const double* beta, int M, double* Y, int N, bool cplx,
@@ -125,15 +131,17 @@ struct SeedWork {
     double* G;       // reorthogonalization coefficients, (m) x 2 complex
     double* G2;      // one complex coefficient
     double* gpart;   // gemm_cn partials
-    double* y;       // T^{-1} beta_0 e_1 (m complex)
-    double* trid;    // LU work (2m)
+    double* y;       // T^{-1} beta_0 e_1 (m + 1 complex; the least-squares right-hand side for an indefinite op)
+    double* trid;    // LU work (2m), or QR work (5m) for an indefinite op
 };
 size_t seed_workspace(const sc_op* op, int m, bool single);
 SeedWork seed_carve(void* work, size_t work_bytes, const sc_op* op, int m, bool single, bool* ok);
 sc_status seed_pretune(const sc_op* op, bool single, const SeedWork& w, hipStream_t s);
 // steps 1-9 enqueued with no host synchronisation (capturable)
+// indef: no positive-pivot check (always so for gamma_5 D)
 sc_status seed_enqueue_any(const sc_op* op, const void* b1, void* x1, int m, int freq, void* V, int64_t ldv,
-                           sc_dtype vdt, double* alpha, double* beta, const SeedWork& w, hipStream_t s);
+                           sc_dtype vdt, double* alpha, double* beta, const SeedWork& w, hipStream_t s,
+                           bool indef = false);
 // one synchronisation: final state, then x^1 (unless form_x1 is false)
 sc_status seed_finalize_any(const sc_op* op, void* x1, void* V, int64_t ldv, sc_dtype vdt, double* alpha,
                             double* beta, int* m_done, const SeedWork& w, hipStream_t s, sc_status* result,
@@ -152,6 +160,15 @@ sc_status solve_cg(const sc_op* op, int mixed, const void* B, int64_t ldb, void*
 size_t multiseed_workspace(const sc_op* op, int k);
 sc_status multiseed_solve(const sc_op* op, const void* B, int64_t ldb, void* X, int64_t ldx, int k, double tol,
                           int maxit, int* iters, double* relres, void* work, size_t work_bytes, hipStream_t s);
+
+// ---------------------------------------------------------------- MINRES and the indefinite variant
+size_t minres_workspace(const sc_op* op, int k);
+sc_status minres_solve(const sc_op* op, const void* B, int64_t ldb, void* X, int64_t ldx, int k, double tol,
+                       int maxit, int* iters, double* relres, void* work, size_t work_bytes, hipStream_t s);
+size_t indefinite_workspace(const sc_op* op, int k, int m);
+sc_status indefinite_solve(const sc_op* op, const void* B, int64_t ldb, void* X, int64_t ldx, int k, int m, int freq,
+                           double tol, int maxit, int* iters, double* relres, int* m_done, void* work,
+                           size_t work_bytes, hipStream_t s);
 
 // ---------------------------------------------------------------- the single-seed method as one call (seeded.hip)
 size_t seeded_workspace(const sc_op* op, int k, int m, bool mixed);

@@ -145,7 +145,8 @@ __global__ __launch_bounds__(kBlock) void k_lz_alpha(R* __restrict__ f, const R*
 template <typename R, bool VEC>
 __global__ __launch_bounds__(kBlock) void k_lz_f(R* __restrict__ f, const R* __restrict__ vi, int64_t N,
                                                  double* alpha, const double* beta, double* delta, int i,
-                                                 SeedState* st, const double* part_a, int G, double* part_f) {
+                                                 SeedState* st, const double* part_a, int G, double* part_f,
+                                                 int indef) {
     __shared__ double sh[kWaves];
     if (st->halt) return;
     constexpr int W = Pack<R>::W;
@@ -164,8 +165,9 @@ __global__ __launch_bounds__(kBlock) void k_lz_f(R* __restrict__ f, const R* __r
         }
     }
     const double a = sum_partials(part_a, G, sh);
+    // the LU pivot of step 6; an indefinite operator has no positive-pivot requirement
     const double d = (i == 1) ? a : a - beta[i - 1] * beta[i - 1] / delta[i - 1];
-    const bool bad = !isfinite(a) || !(d > 0.0);
+    const bool bad = !isfinite(a) || (!indef && !(d > 0.0));
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         alpha[i - 1] = a;
         delta[i] = d;
@@ -390,8 +392,8 @@ static SeedWork carve_seed(Carver& c, const sc_op* op, int m, bool single) {
     w.G = c.take<double>((size_t)std::max(m, 1) * 4);
     w.G2 = c.take<double>(4);
     w.gpart = c.take<double>(std::max(gemm_cn_part_doubles(op->n, std::max(m, 1), 2, cpl), (size_t)4 * 64));
-    w.y = c.take<double>((size_t)std::max(m, 1) * 2);
-    w.trid = c.take<double>((size_t)std::max(m, 1) * 2);
+    w.y = c.take<double>((size_t)(std::max(m, 1) + 1) * 2);
+    w.trid = c.take<double>((size_t)std::max(m, 1) * 5);
     return w;
 }
 
@@ -405,7 +407,7 @@ size_t seed_workspace(const sc_op* op, int m, bool single) {
 // phase has static control flow, so it can be captured in a graph).
 template <typename R, bool VEC>
 static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, int freq, R* V, int64_t ldv,
-                              double* alpha, double* beta, const SeedWork& w, hipStream_t s) {
+                              double* alpha, double* beta, const SeedWork& w, hipStream_t s, bool indef_op) {
     const bool single = sizeof(R) == 4;
     const bool cpl = is_complex(op->dtype);
     const int64_t N2 = op->n * (cpl ? 2 : 1);
@@ -430,6 +432,7 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
 
     // the fused Wilson form (direction-split passes carrying the vector work)
     const bool fused = op->kind == SC_OPK_WILSON && (!single || op->U32);
+    const int indef = (indef_op || op->kind == SC_OPK_WILSON_G5) ? 1 : 0;  // Hermitian indefinite: no pivot check
     const Geom geo{op->dims[0], op->dims[1], op->dims[2], op->dims[3], op->vol};
     const int ntile = (int)((op->vol + 63) / 64);
     const int per_xcd = (ntile + kXcd - 1) / kXcd;
@@ -463,7 +466,7 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
                 SC_LAUNCH_CHECK();
             }
             hipLaunchKernelGGL((k_lz_f<R, VEC>), dim3(g), blk, 0, s, f, vi, N2, alpha, beta, w.delta, i, w.st,
-                               w.part_a, ntile, w.part_f);
+                               w.part_a, ntile, w.part_f, indef);
             SC_LAUNCH_CHECK();
         } else {
             // step 5: f = A v_i - beta_{i-1} v_{i-1}; alpha_i; f -= alpha_i v_i
@@ -472,7 +475,7 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
                                w.part_a);
             SC_LAUNCH_CHECK();
             hipLaunchKernelGGL((k_lz_f<R, VEC>), dim3(g), blk, 0, s, f, vi, N2, alpha, beta, w.delta, i, w.st,
-                               w.part_a, g, w.part_f);
+                               w.part_a, g, w.part_f, indef);
             SC_LAUNCH_CHECK();
         }
         gf = g;
@@ -509,6 +512,11 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
     return SC_OK;
 }
 
+// beta_0 e_1 as rows x es doubles
+__global__ void k_e1(double* y, int rows, int es, const double* beta0) {
+    for (int e = threadIdx.x; e < rows * es; e += blockDim.x) y[e] = e == 0 ? *beta0 : 0.0;
+}
+
 // Reads the phase's final state (one synchronisation) and forms x^1.
 template <typename R>
 static sc_status seed_finalize(const sc_op* op, void* x1, R* V, int64_t ldv, double* alpha, double* beta,
@@ -520,9 +528,16 @@ static sc_status seed_finalize(const sc_op* op, void* x1, R* V, int64_t ldv, dou
     SC_HIP(hipStreamSynchronize(s));
     *m_done = hst.m_done;
     *result = (sc_status)hst.status;
-    // x^1 = x0 + V_md T_md^{-1} (beta_0 e_1)
+    // x^1 = x0 + V_md T_md^{-1} (beta_0 e_1); for an indefinite op the minimum
+    // residual x0 + V_md y, y = argmin || beta_0 e_1 - T~_md y || (QR of T~)
     if (form_x1 && hst.m_done >= 1 && hst.status != SC_ERR_NONFINITE) {
-        SC_TRY(tridiag_solve(alpha, beta, hst.m_done, w.y, 1, cpl, beta, w.trid, nullptr, s));
+        if (op->kind == SC_OPK_WILSON_G5) {
+            hipLaunchKernelGGL(k_e1, dim3(1), dim3(kBlock), 0, s, w.y, hst.m_done + 1, cpl ? 2 : 1, beta);
+            SC_LAUNCH_CHECK();
+            SC_TRY(tridiag_lsq(alpha, beta, hst.m_done, w.y, 1, cpl, w.trid, s));
+        } else {
+            SC_TRY(tridiag_solve(alpha, beta, hst.m_done, w.y, 1, cpl, beta, w.trid, nullptr, s));
+        }
         ColPtrs<void> xc{};
         xc.p[0] = x1;
         SC_TRY(gemm_nn(cpl, single, V, ldv, op->n, hst.m_done, w.y, 1, false, xc, 1.0, nullptr, s));
@@ -531,7 +546,8 @@ static sc_status seed_finalize(const sc_op* op, void* x1, R* V, int64_t ldv, dou
 }
 
 sc_status seed_enqueue_any(const sc_op* op, const void* b1, void* x1, int m, int freq, void* V, int64_t ldv,
-                           sc_dtype vdt, double* alpha, double* beta, const SeedWork& w, hipStream_t s) {
+                           sc_dtype vdt, double* alpha, double* beta, const SeedWork& w, hipStream_t s,
+                           bool indef) {
     const bool single = is_single(vdt);
     // 16-byte packs need 16-byte aligned columns
     const int64_t N2 = op->n * (is_complex(op->dtype) ? 2 : 1);
@@ -539,11 +555,11 @@ sc_status seed_enqueue_any(const sc_op* op, const void* b1, void* x1, int m, int
     const bool vec = ((uintptr_t)V % 16 == 0) && ((ldv * (is_complex(vdt) ? 2 : 1) * rb) % 16 == 0) &&
                      ((N2 * rb) % 16 == 0);
     if (single) {
-        if (vec) return seed_enqueue<float, true>(op, b1, x1, m, freq, (float*)V, ldv, alpha, beta, w, s);
-        return seed_enqueue<float, false>(op, b1, x1, m, freq, (float*)V, ldv, alpha, beta, w, s);
+        if (vec) return seed_enqueue<float, true>(op, b1, x1, m, freq, (float*)V, ldv, alpha, beta, w, s, indef);
+        return seed_enqueue<float, false>(op, b1, x1, m, freq, (float*)V, ldv, alpha, beta, w, s, indef);
     }
-    if (vec) return seed_enqueue<double, true>(op, b1, x1, m, freq, (double*)V, ldv, alpha, beta, w, s);
-    return seed_enqueue<double, false>(op, b1, x1, m, freq, (double*)V, ldv, alpha, beta, w, s);
+    if (vec) return seed_enqueue<double, true>(op, b1, x1, m, freq, (double*)V, ldv, alpha, beta, w, s, indef);
+    return seed_enqueue<double, false>(op, b1, x1, m, freq, (double*)V, ldv, alpha, beta, w, s, indef);
 }
 
 sc_status seed_finalize_any(const sc_op* op, void* x1, void* V, int64_t ldv, sc_dtype vdt, double* alpha,

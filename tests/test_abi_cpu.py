@@ -66,7 +66,7 @@ def test_op_create_info_destroy_on_host(lib):
     nb = ctypes.c_size_t()
     assert lib.sc_workspace_size(out, 3, 4, 0, 0, ctypes.byref(nb)) == 0 and nb.value > 4 * 3 * 512 * 8
     assert lib.sc_workspace_size(out, 1, 1, 50, 0, ctypes.byref(nb)) == 0 and nb.value > 0
-    assert lib.sc_workspace_size(out, 9, 1, 50, 0, ctypes.byref(nb)) == -1
+    assert lib.sc_workspace_size(out, 10, 1, 50, 0, ctypes.byref(nb)) == -1  # unknown call id
     # seed: m < 1 and a NULL m_done are argument errors, caught before any launch
     md = ctypes.c_int()
     p = ctypes.c_void_p(4096)

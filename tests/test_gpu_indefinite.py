@@ -1,0 +1,133 @@
+"""GPU parity of the indefinite variant (gamma_5 D; QR of the tridiagonal
+matrix; MINRES) against the oracle in oracle/indefinite.py.
+
+Tolerances: the gamma_5 D apply element-wise to 1e-13 (FP64, rounding order
+only); Lanczos coefficients to 1e-8 inside a short run; MINRES counts within
++-2 of the oracle's; solutions within 2 cond(Q) tol of the oracle's and true
+residuals at tol (cond(Q) from the dense spectrum on the small lattice).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import indefinite as ind
+from oracle import operators as ops
+from paper_0810_0330_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _to_lib(Bnat):
+    return torch.from_numpy(api.pack_field(np.ascontiguousarray(Bnat.T))).to(DEV)
+
+
+def _to_nat(X):
+    return api.unpack_field(X.cpu().numpy()).T
+
+
+def _g5(dims, cfg, kappa=0.12):
+    U = synth.su3_links(dims, synth.rng(cfg, 0))
+    op = api.Op.wilson_g5(dims, torch.from_numpy(api.pack_links(U)).to(DEV), kappa)
+    return U, op, ind.WilsonG5Op(U, kappa)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 5, 4, 6), (16, 16, 4, 5)])
+def test_g5_apply_matches_oracle(dims):
+    _say("gamma_5 D apply", dims)
+    U, op, oop = _g5(dims, 63)
+    x = synth.complex_gaussian(oop.n, 3, synth.rng(63, 1))
+    y = _to_nat(op.apply(_to_lib(x)))
+    ref = oop(x)
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_minres_wilson_and_indefinite_diagonal():
+    _say("minres: gamma_5 D on 4^4, indefinite diagonal")
+    dims = (4, 4, 4, 4)
+    U, op, oop = _g5(dims, 64)
+    B = synth.point_sources(dims, synth.ALL_SPIN_COLOUR[:3])
+    tol = 1e-10
+    X, its, rel = api.solve_minres(op, _to_lib(B), tol)
+    assert max(rel) <= tol
+    Xn = _to_nat(X)
+    for j in range(3):
+        xo, ito, _ = ind.minres(oop, B[:, j], tol=tol)
+        assert abs(its[j] - ito) <= 2, (its, ito)
+        r = B[:, j] - oop(Xn[:, j])
+        assert np.linalg.norm(r) / np.linalg.norm(B[:, j]) <= tol
+        assert np.linalg.norm(Xn[:, j] - xo) / np.linalg.norm(xo) <= 2 * 50 * tol
+    g = np.random.default_rng(4)
+    d = np.sort(np.concatenate([-g.uniform(0.2, 1.0, 300), g.uniform(0.2, 1.0, 300), [-0.01, 0.01]]))
+    Bd = g.standard_normal((d.size, 2))
+    dop = api.Op.diag(torch.from_numpy(d).to(DEV))
+    X, its, rel = api.solve_minres(dop, torch.from_numpy(Bd.T.copy()).to(DEV), 1e-10)
+    assert max(rel) <= 1e-10
+    for j in range(2):
+        _, ito, _ = ind.minres(ops.DiagOp(d), Bd[:, j], tol=1e-10)
+        assert abs(its[j] - ito) <= 2, (its, ito)
+    Xs = Bd / d[:, None]
+    assert np.linalg.norm(X.cpu().numpy().T - Xs) / np.linalg.norm(Xs) <= 2 * 100 * 1e-10  # cond = 100
+
+
+def test_seed_lanczos_g5_x1_is_the_minimum_residual():
+    # sc_seed_lanczos on gamma_5 D: no pivot check, x^1 by the QR of T~
+    _say("seed lanczos on gamma_5 D")
+    dims = (4, 4, 4, 4)
+    U, op, oop = _g5(dims, 65)
+    b = synth.point_sources(dims, synth.ALL_SPIN_COLOUR[:1])[:, 0]
+    m = 40
+    basis = api.seed_lanczos(op, _to_lib(b[:, None])[0], m, 1)
+    V, alpha, beta, md, _ = ind.lanczos(oop, b, m, 1)
+    assert basis.m_done == md == m
+    a = basis.alpha.cpu().numpy()[:md]
+    np.testing.assert_allclose(a, alpha[:md], rtol=1e-8, atol=1e-10)
+    c = np.zeros(md + 1, dtype=np.complex128)
+    c[0] = beta[0]
+    x1 = V[:, :md] @ ind.lstsq_coeffs(alpha, beta, md, c)[:, 0]
+    got = api.unpack_field(basis.x1.reshape(1, -1).cpu().numpy())[0]
+    assert np.linalg.norm(got - x1) / np.linalg.norm(x1) < 1e-8
+
+
+def test_indefinite_seeded_wilson_4x4():
+    _say("indefinite seeded solve, gamma_5 D on 4^4")
+    dims = (4, 4, 4, 4)
+    U, op, oop = _g5(dims, 66)
+    B = np.concatenate([synth.point_sources(dims, synth.ALL_SPIN_COLOUR[:3]),
+                        synth.z4_noise(oop.n, 2, synth.rng(66, 2))], axis=1)
+    m, freq, tol = 60, 1, 1e-10
+    ref = ind.seeded_solve(oop, B, m, freq, tol)
+    out = api.indefinite_solve(op, _to_lib(B), m, freq, tol)
+    assert out["m_done"] == ref["m_done"] == m
+    assert max(out["relres"]) <= tol
+    for a, b in zip(out["iters"], ref["iters"]):
+        assert abs(a - b) <= 2, (out["iters"], ref["iters"])
+    X = _to_nat(out["X"])
+    for j in range(B.shape[1]):
+        r = B[:, j] - oop(X[:, j])
+        assert np.linalg.norm(r) / np.linalg.norm(B[:, j]) <= tol
+        assert np.linalg.norm(X[:, j] - ref["X"][:, j]) / np.linalg.norm(ref["X"][:, j]) <= 2 * 50 * tol
+
+
+def test_indefinite_seeded_diagonal_breakdown_and_outliers():
+    # the oracle's character example: small eigenvalues of both signs; the
+    # seed run past convergence halves the others' MINRES counts
+    _say("indefinite seeded solve, diagonal with small outliers")
+    g = np.random.default_rng(4)
+    small = np.array([0.002, 0.004, 0.006, 0.008, 0.01])
+    d = np.sort(np.concatenate([-g.uniform(0.2, 1.0, 995), g.uniform(0.2, 1.0, 995), small, -small]))
+    B = g.standard_normal((d.size, 3))
+    ref = ind.seeded_solve(ops.DiagOp(d), B, 400, 10, 1e-8)
+    op = api.Op.diag(torch.from_numpy(d).to(DEV))
+    out = api.indefinite_solve(op, torch.from_numpy(B.T.copy()).to(DEV), 400, 10, 1e-8)
+    assert max(out["relres"]) <= 1e-8
+    plain = api.solve_minres(op, torch.from_numpy(B[:, 1:].T.copy()).to(DEV), 1e-8)[1]
+    for a, b, p in zip(out["iters"][1:], ref["iters"][1:], plain):
+        assert a < 0.6 * p, (out["iters"], plain)
+        assert abs(a - b) <= max(3, 0.05 * b), (out["iters"], ref["iters"])
+    Xs = B / d[:, None]
+    assert np.linalg.norm(out["X"].cpu().numpy().T - Xs) / np.linalg.norm(Xs) <= 2 * 500 * 1e-8  # cond = 500
