@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--related", type=int, default=None, metavar="NRHS",
                     help="time single seeding of NRHS related right-hand sides b^j = b^(j-1) + 0.2^(j-1) u^j "
                          "(Section 2.3, Example 3) on the workload's lattice instead of the benchmark")
+    ap.add_argument("--indefinite", action="store_true",
+                    help="time the indefinite variant (gamma_5 D, QR of T, MINRES; FP64) against the normal-equations "
+                         "path on the workload instead of the benchmark (Sections 3 and 4)")
     ap.add_argument("--compare-seeding", action="store_true",
                     help="A-applies, vector operations and time of no / multiple / single seeding on the workload "
                          "(Section 2, Table 2.1 analogue) instead of the benchmark")
@@ -198,6 +201,51 @@ def related_bench(args, w):
         assert max(out["relres"]) <= w.tol
         res[name] = {"ms": round(dt * 1e3, 2), "rhs_per_s": round(k / dt, 3), "iters": list(out["iters"])}
         log(f"[related] {name}: {dt * 1e3:.1f} ms, iters {list(out['iters'])}")
+    print(json.dumps(res), flush=True)
+
+
+def indefinite_bench(args, w):
+    """The indefinite variant (gamma_5 D, QR of the tridiagonal matrix, MINRES; FP64) against the
+    normal-equations path, on the workload's lattice and right-hand sides.
+
+    Both solve the Wilson system of the workload: the normal-equations path solves D^H D x = b, the
+    indefinite one gamma_5 D x = b (for D x = gamma_5 b); the comparison is the number of products with
+    D and the time to reach the same relative residual.  Section 4 notes that the gamma_5 form needs one
+    product with D per iteration instead of two.
+    """
+    import numpy as np
+    import torch
+
+    from paper_0810_0330_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    inp = synth.make_inputs(w)
+    U = torch.from_numpy(api.pack_links(inp["U"])).to(dev)
+    opq = api.Op.wilson_g5(w.dims, U, w.kappa)
+    opn = api.Op.wilson(w.dims, U, w.kappa)
+    B = torch.from_numpy(api.pack_field(np.ascontiguousarray(inp["B"].T))).to(dev)
+    k = B.shape[0]
+    mixed = w.precision == "mixed"
+    # warm every path on the full right-hand-side block (stencil tuning per column count, allocations)
+    api.indefinite_solve(opq, B, 50, 10, w.tol)
+    api.solve_minres(opq, B, w.tol)
+    api.single_seed_solve(opn, B, 50, 10, w.tol, mixed=mixed)
+    res = {"indefinite": True, "workload": w.name, "m": w.m, "freq": w.freq, "tol": w.tol, "nrhs": k}
+    runs = [("indefinite_seeded_f64", 1, lambda: api.indefinite_solve(opq, B, w.m, w.freq, w.tol)),
+            ("minres_unseeded_f64", 1, lambda: dict(zip(("X", "iters", "relres"), api.solve_minres(opq, B, w.tol)))),
+            ("normal_seeded_" + ("mixed" if mixed else "f64"), 2,
+             lambda: api.single_seed_solve(opn, B, w.m, w.freq, w.tol, mixed=mixed))]
+    for name, d_per_it, fn in runs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert max(out["relres"]) <= w.tol
+        its = list(out["iters"])
+        res[name] = {"ms": round(dt * 1e3, 2), "rhs_per_s": round(k / dt, 3), "iters": its,
+                     "d_products": int(sum(its) * d_per_it)}
+        log(f"[indefinite] {name}: {dt * 1e3:.1f} ms, D-products {sum(its) * d_per_it}, iters {its[:4]}...")
     print(json.dumps(res), flush=True)
 
 
@@ -374,6 +422,8 @@ def main():
         return micro(args, w)
     if args.sweep_freq:
         return sweep_freq(args, w)
+    if args.indefinite:
+        return indefinite_bench(args, w)
     if args.related:
         return related_bench(args, w)
     if args.compare_seeding:
