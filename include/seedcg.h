@@ -224,7 +224,9 @@ sc_status sc_seed_lanczos(const sc_op* op, const void* b1_dev, void* x1_dev, int
  * and is solved with the LU recurrences of step 6 (no pivoting).
  * V_dev: n x m, ldv, v_dtype (SC_C128/SC_C64 or SC_R64/SC_R32).
  * R0_dev, X_dev: n x k in vec_dtype (SC_C128 or SC_R64; the full-precision
- * type matching V).  Sums are accumulated in FP64.  Asynchronous. */
+ * type matching V).  Sums are accumulated in FP64.  Asynchronous.  For the
+ * basis of an indefinite op the LU of T_m need not exist: sc_indefinite_solve
+ * forms minimum-residual guesses through the (m+1) x m matrix instead. */
 sc_status sc_project(int64_t n, const void* V_dev, int64_t ldv, sc_dtype v_dtype, int m,
                      const double* alpha_dev, const double* beta_dev, sc_dtype vec_dtype,
                      const void* R0_dev, int64_t ldr, int k, void* X_dev, int64_t ldx,
