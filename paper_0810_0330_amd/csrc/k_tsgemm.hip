@@ -47,18 +47,19 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
 // combined with.
 
 // G = V^H W: block = 4 waves over 64 basis columns (16 per wave), one row
-// chunk; LDS stages of 32 complex rows.  The stages are software-pipelined:
+// chunk; LDS stages of KR = 64 complex rows (measured 8% faster than 32 on
+// the projection of the benchmark workload; the X += V Y kernel below keeps
+// 32-column stages, which measured faster there).  The stages are software-pipelined:
 // each thread holds its share of the next stage's V and W elements in
 // registers, loaded before the current stage's MFMAs are issued and written to
 // LDS after them, so the global-load latency of a stage hides behind the
 // previous stage's compute.  V stays in its own precision in LDS and is
 // widened when it is fed to the MFMA.
-template <typename VR, typename WR, int NT>
+template <typename VR, typename WR, int NT, int KR = 64>
 __global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, int64_t ldv, int64_t n, int M,
                                                     ColPtrs<const void> W, int N, double* __restrict__ part,
                                                     int64_t rows_per_chunk, int nchunk, const int* halt) {
     if (halt && *halt) return;
-    constexpr int KR = 32;               // complex rows per LDS stage
     constexpr int TA = 64;               // basis columns per block
     constexpr int TC = 16 * NT;          // real columns of [Re W | Im W], padded
     constexpr int EV = KR * TA / kBlock; // V elements per thread per stage
@@ -174,12 +175,11 @@ __global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, in
 
 // X_j += scale * V Y_j: block = 4 waves over 64 rows (16 per wave); LDS
 // stages of 32 basis columns, software-pipelined like k_cn_mfma.
-template <typename VR, typename XR, int NT>
+template <typename VR, typename XR, int NT, int KA = 32>
 __global__ __launch_bounds__(kBlock) void k_nn_mfma(const VR* __restrict__ V, int64_t ldv, int64_t n, int M,
                                                     const double* __restrict__ Y, int N, ColPtrs<void> X,
                                                     double scale, const int* halt) {
     if (halt && *halt) return;
-    constexpr int KA = 32;          // basis columns per LDS stage
     constexpr int TR = 64;          // rows per block
     constexpr int TC = 16 * NT;     // real columns of [Re Y | Im Y], padded
     constexpr int EV = TR * KA / kBlock;
@@ -479,7 +479,7 @@ static CnPlan cn_plan(int64_t n, int M, int N, bool cplx = false) {
         return p;
     }
     p.tm = cplx ? 64 : (N <= 2 ? 128 : 32);
-    p.kt = cplx ? 32 : (N <= 2 ? 16 : 64);
+    p.kt = cplx ? 64 : (N <= 2 ? 16 : 64);  // the complex MFMA kernel's stage depth (KR)
     const int mt = (M + p.tm - 1) / p.tm;
     int64_t want = std::max<int64_t>(1, (2048 + mt - 1) / mt);
     const int64_t maxchunk = std::max<int64_t>(1, (n + p.kt - 1) / p.kt);
