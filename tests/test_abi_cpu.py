@@ -119,6 +119,59 @@ def test_seeded_driver_argument_errors(lib):
     assert lib.sc_op_destroy(out) == 0
 
 
+def test_indefinite_and_minres_argument_errors(lib):
+    # the gamma_5 D constructor validates like the normal-operator one; the
+    # MINRES and indefinite-variant calls validate on the host before any
+    # device call
+    out = ctypes.c_void_p()
+    dims = (ctypes.c_int * 4)(4, 4, 0, 4)
+    assert lib.sc_op_wilson_g5(dims, ctypes.c_void_p(256), None, ctypes.c_double(0.12), 1, ctypes.byref(out)) == -1
+    dims = (ctypes.c_int * 4)(4, 4, 4, 4)
+    assert lib.sc_op_wilson_g5(dims, None, None, ctypes.c_double(0.12), 1, ctypes.byref(out)) == -1
+    assert lib.sc_op_wilson_g5(dims, ctypes.c_void_p(264), None, ctypes.c_double(0.12), 1, ctypes.byref(out)) == -1
+    assert b"aligned" in lib.sc_last_error()
+    assert lib.sc_op_wilson_g5(dims, ctypes.c_void_p(256), None, ctypes.c_double(0.12), 1, ctypes.byref(out)) == 0
+    n = ctypes.c_int64()
+    dt = ctypes.c_int()
+    assert lib.sc_op_info(out, ctypes.byref(n), ctypes.byref(dt)) == 0 and n.value == 4 ** 4 * 12
+    nb = ctypes.c_size_t()
+    assert lib.sc_workspace_size(out, 8, 3, 0, dt.value, ctypes.byref(nb)) == 0 and nb.value > 3 * n.value * 16
+    assert lib.sc_workspace_size(out, 9, 3, 40, dt.value, ctypes.byref(nb)) == 0 and nb.value > 41 * n.value * 16
+    # both run in the op's own (FP64) type only
+    assert lib.sc_workspace_size(out, 8, 3, 0, dt.value - 1, ctypes.byref(nb)) == -1
+    p = ctypes.c_void_p(4096)
+    it = (ctypes.c_int * 3)()
+    rr = (ctypes.c_double * 3)()
+    md = ctypes.c_int()
+    ld = n.value
+
+    def minres(k=3, tol=1e-8, maxit=100, ldb=ld, work=1 << 30, itp=it):
+        return lib.sc_solve_minres(out, p, ctypes.c_int64(ldb), p, ctypes.c_int64(ld), k, ctypes.c_double(tol), maxit,
+                                   itp, rr, p, ctypes.c_size_t(work), None)
+
+    assert minres(k=0) == -1
+    assert minres(tol=0.0) == -1 and b"tol" in lib.sc_last_error()
+    assert minres(tol=float("nan")) == -1
+    assert minres(maxit=0) == -1
+    assert minres(ldb=ld - 1) == -1 and b"ldb" in lib.sc_last_error()
+    assert minres(itp=None) == -1
+    assert minres(work=16) == -5
+
+    def indef(k=3, m=40, freq=10, tol=1e-8, maxit=100, ldb=ld, work=1 << 30, mdp=ctypes.byref(md)):
+        return lib.sc_indefinite_solve(out, p, ctypes.c_int64(ldb), p, ctypes.c_int64(ld), k, m, freq,
+                                       ctypes.c_double(tol), maxit, it, rr, mdp, p, ctypes.c_size_t(work), None)
+
+    assert indef(k=0) == -1
+    assert indef(m=0) == -1
+    assert indef(freq=-1) == -1
+    assert indef(tol=-1.0) == -1
+    assert indef(maxit=0) == -1
+    assert indef(ldb=ld - 1) == -1
+    assert indef(mdp=None) == -1
+    assert indef(work=16) == -5
+    assert lib.sc_op_destroy(out) == 0
+
+
 def test_timer_host_side(lib):
     # enabling, reading with no recorded launches and the class check need no device
     ms, nl, by, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
