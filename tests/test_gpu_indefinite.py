@@ -131,3 +131,22 @@ def test_indefinite_seeded_diagonal_breakdown_and_outliers():
         assert abs(a - b) <= max(3, 0.05 * b), (out["iters"], ref["iters"])
     Xs = B / d[:, None]
     assert np.linalg.norm(out["X"].cpu().numpy().T - Xs) / np.linalg.norm(Xs) <= 2 * 500 * 1e-8  # cond = 500
+
+
+def test_indefinite_seeded_column_groups():
+    # 34 right-hand sides: the projection and the guesses take two column
+    # groups (32 + 2); the seed runs to its system's convergence
+    _say("indefinite seeded solve, 34 right-hand sides")
+    g = np.random.default_rng(7)
+    small = np.array([0.003, 0.006, 0.009])
+    d = np.sort(np.concatenate([-g.uniform(0.2, 1.0, 497), g.uniform(0.2, 1.0, 497), small, -small]))
+    B = g.standard_normal((d.size, 34))
+    ref = ind.seeded_solve(ops.DiagOp(d), B, 300, 10, 1e-8)
+    op = api.Op.diag(torch.from_numpy(d).to(DEV))
+    out = api.indefinite_solve(op, torch.from_numpy(B.T.copy()).to(DEV), 300, 10, 1e-8)
+    assert out["m_done"] == ref["m_done"] == 300
+    assert max(out["relres"]) <= 1e-8
+    for a, b in zip(out["iters"], ref["iters"]):
+        assert abs(a - b) <= max(3, 0.05 * b), (out["iters"], ref["iters"])
+    Xs = B / d[:, None]
+    assert np.linalg.norm(out["X"].cpu().numpy().T - Xs) / np.linalg.norm(Xs) <= 2 * 334 * 1e-8  # cond = 1/0.003

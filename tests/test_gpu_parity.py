@@ -264,6 +264,31 @@ def test_seeded_solve_laplace(laplace_case):
         assert np.linalg.norm(X[:, j] - ref["X"][:, j]) / np.linalg.norm(ref["X"][:, j]) <= 2 * cond * w.tol
 
 
+def test_single_seed_driver_laplace(laplace_case):
+    # the one-call driver on the real 32x32 Laplacian (5 RHS, m = 200, full
+    # reorthogonalization, tol 1e-10): counts inside the oracle's perturbation
+    # range at m = 200 and +-2 of one oracle run with m inside the horizon
+    w, B, oop, ores = laplace_case
+    _say("single-seed driver laplace m=200 freq=1")
+    op = api.Op.laplace2d(32, 32)
+    Bt = torch.from_numpy(B.T.copy()).to(DEV)
+    ref = o_seeded_solve(oop, B, w.m, w.freq, w.tol)
+    out = api.single_seed_solve(op, Bt, w.m, w.freq, w.tol)
+    assert out["status"] == 0 and out["m_done"] == w.m
+    assert max(out["relres"]) <= w.tol
+    hor = _horizon(oop, B[:, :1], w.m, w.freq, ores)
+    _check_iters(out["iters"], *_oracle_iter_range(oop, B, w.m, w.freq, w.tol, ref["iters"], hor, pool=True))
+    m_in = hor - 10
+    ref_in = o_seeded_solve(oop, B, m_in, w.freq, w.tol)
+    out_in = api.single_seed_solve(op, Bt, m_in, w.freq, w.tol)
+    assert out_in["m_done"] == m_in and max(out_in["relres"]) <= w.tol
+    _check_iters(out_in["iters"], ref_in["iters"], ref_in["iters"])
+    X = out["X"].cpu().numpy().T
+    cond = (4 + 4 * np.cos(np.pi / 33)) / (4 - 4 * np.cos(np.pi / 33))
+    for j in range(w.nrhs):
+        assert np.linalg.norm(X[:, j] - ref["X"][:, j]) / np.linalg.norm(ref["X"][:, j]) <= 2 * cond * w.tol
+
+
 def test_plain_cg_laplace():
     _say("plain cg laplace")
     B = synth.make_inputs(synth.laplace_32x32())["B"]
