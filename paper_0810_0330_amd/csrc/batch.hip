@@ -126,9 +126,9 @@ sc_status batch_solve(int nsys, sc_batch_system* sys, void* work, size_t work_by
     std::vector<hipEvent_t> ev(nsys + 1, nullptr);
     auto cleanup = [&]() {
         for (auto& x : ss)
-            if (x) hipStreamDestroy(x);
+            if (x) (void)hipStreamDestroy(x);
         for (auto& e : ev)
-            if (e) hipEventDestroy(e);
+            if (e) (void)hipEventDestroy(e);
     };
     for (int i = 0; i <= nsys; ++i)
         if (hipStreamCreateWithFlags(&ss[i], hipStreamNonBlocking) != hipSuccess) {
@@ -173,10 +173,14 @@ sc_status batch_solve(int nsys, sc_batch_system* sys, void* work, size_t work_by
             set_error("batch_solve: stream capture could not start");
             return SC_ERR_HIP;
         }
-        hipEventRecord(ev[nsys], cap);
-        for (int i = 0; i < nsys && st == SC_OK; ++i) {
+        // a failed record or wait ends the capture with an error (checked below)
+        bool evfail = hipEventRecord(ev[nsys], cap) != hipSuccess;
+        for (int i = 0; i < nsys && st == SC_OK && !evfail; ++i) {
             const sc_batch_system& b = sys[i];
-            hipStreamWaitEvent(ss[i], ev[nsys], 0);
+            if (hipStreamWaitEvent(ss[i], ev[nsys], 0) != hipSuccess) {
+                evfail = true;
+                break;
+            }
             const int64_t N2 = b.op->n * (is_complex(b.op->dtype) ? 2 : 1);
             // X = 0: the seed refines column 0 in place (x0 = 0)
             st = fill<double>((double*)b.X_dev, (b.k - 1) * b.ldx * (is_complex(b.op->dtype) ? 2 : 1) + N2, 0.0,
@@ -185,21 +189,24 @@ sc_status batch_solve(int nsys, sc_batch_system* sys, void* work, size_t work_by
                 st = seed_enqueue_any(b.op, b.B_dev, b.X_dev, b.m, b.reorth_freq, base + plan[i].v_off, b.op->n,
                                       plan[i].vdt, (double*)(base + plan[i].a_off), (double*)(base + plan[i].b_off),
                                       sw[i], ss[i]);
-            hipEventRecord(ev[i], ss[i]);
-            hipStreamWaitEvent(cap, ev[i], 0);
+            if (hipEventRecord(ev[i], ss[i]) != hipSuccess || hipStreamWaitEvent(cap, ev[i], 0) != hipSuccess)
+                evfail = true;
         }
         const hipError_t ce = hipStreamEndCapture(cap, &graph);
-        if (st != SC_OK || ce != hipSuccess) {
-            if (graph) hipGraphDestroy(graph);
+        if (st != SC_OK || evfail || ce != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
             cleanup();
-            if (st == SC_OK) {
+            if (st == SC_OK && evfail) {
+                set_error("batch_solve: event record or wait failed during capture");
+                st = SC_ERR_HIP;
+            } else if (st == SC_OK) {
                 set_error(std::string("batch_solve: capture failed: ") + hipGetErrorString(ce));
                 st = SC_ERR_HIP;
             }
             return st;
         }
         const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         if (ie != hipSuccess) {
             cleanup();
             set_error(std::string("batch_solve: graph instantiation failed: ") + hipGetErrorString(ie));
@@ -207,7 +214,7 @@ sc_status batch_solve(int nsys, sc_batch_system* sys, void* work, size_t work_by
         }
         std::lock_guard<std::mutex> lk(g_graph_mu);
         if (g_graphs.size() >= kGraphCache) {
-            hipGraphExecDestroy(g_graphs.front().exec);
+            (void)hipGraphExecDestroy(g_graphs.front().exec);
             g_graphs.erase(g_graphs.begin());
         }
         g_graphs.push_back({key, exec});
@@ -246,11 +253,17 @@ sc_status batch_solve(int nsys, sc_batch_system* sys, void* work, size_t work_by
     for (int i = 1; i < nsys; ++i) th.emplace_back(finish, i);
     finish(0);
     for (auto& t : th) t.join();
-    for (int i = 0; i < nsys; ++i) {
-        hipEventRecord(ev[i], ss[i]);
-        hipStreamWaitEvent(s, ev[i], 0);
+    // join: the caller's stream waits for every system's stream
+    bool joined = true;
+    for (int i = 0; i < nsys; ++i)
+        joined = joined && hipEventRecord(ev[i], ss[i]) == hipSuccess && hipStreamWaitEvent(s, ev[i], 0) == hipSuccess;
+    joined = joined && hipStreamSynchronize(s) == hipSuccess;
+    if (!joined) {
+        for (auto& x : ss) (void)hipStreamSynchronize(x);
+        cleanup();
+        set_error("batch_solve: joining the per-system streams failed");
+        return SC_ERR_HIP;
     }
-    hipStreamSynchronize(s);
     cleanup();
     sc_status out = SC_OK;
     for (int i = 0; i < nsys; ++i) {

@@ -806,32 +806,34 @@ int g_tune_mode = -1;  // -1: read SEEDCG_TUNE on first use; 0: defaults only; 1
 
 // Time every variant on the caller's buffers (the output is rewritten by the
 // real launch that follows) and keep the fastest for (lattice, precision, k).
+// Returns false, with rec holding the default shape and no timings, when a HIP
+// call fails; the caller does not cache that result.
 template <typename R>
-static TuneRec tune_variants(const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k, const R* U,
-                             hipStream_t s) {
-    TuneRec rec;
-    rec.best = default_variant(sizeof(R) == 4, k);
+static bool tune_variants(const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k, const R* U,
+                          hipStream_t s, TuneRec& rec) {
+    const int dflt = default_variant(sizeof(R) == 4, k);
+    rec.best = dflt;
+    for (int v = 0; v < WV_COUNT; ++v) rec.us[v] = -1.0f;
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return rec;
+    if (hipEventCreate(&e0) != hipSuccess) return false;
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
-        return rec;
+        (void)hipEventDestroy(e0);
+        return false;
     }
     float best = 1e30f;
-    for (int v = 0; v < WV_COUNT; ++v) {
-        rec.us[v] = -1.0f;
+    bool ok = true;
+    for (int v = 0; v < WV_COUNT && ok; ++v) {
         if (!variant_applies(op, v, sizeof(R) == 4, k)) continue;
         wilson_launch_variant<R>(v, op, which, X, ldx, Y, ldy, k, U, s);  // warm
         // median of 5 individually timed launches (robust to a stray slow one)
         float t[5];
-        bool okv = true;
-        for (int r = 0; r < 5 && okv; ++r) {
-            hipEventRecord(e0, s);
-            wilson_launch_variant<R>(v, op, which, X, ldx, Y, ldy, k, U, s);
-            hipEventRecord(e1, s);
-            okv = hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t[r], e0, e1) == hipSuccess;
+        for (int r = 0; r < 5 && ok; ++r) {
+            ok = hipEventRecord(e0, s) == hipSuccess;
+            if (ok) wilson_launch_variant<R>(v, op, which, X, ldx, Y, ldy, k, U, s);
+            ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                 hipEventElapsedTime(&t[r], e0, e1) == hipSuccess;
         }
-        if (!okv) break;
+        if (!ok) break;
         std::sort(t, t + 5);
         rec.us[v] = t[2] * 1000.0f;
         if (rec.us[v] < best) {
@@ -839,9 +841,13 @@ static TuneRec tune_variants(const sc_op* op, int which, const R* X, int64_t ldx
             rec.best = v;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    return rec;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!ok) {
+        rec.best = dflt;
+        for (int v = 0; v < WV_COUNT; ++v) rec.us[v] = -1.0f;
+    }
+    return ok;
 }
 
 template <typename R>
@@ -855,11 +861,12 @@ static int choose_variant(const sc_op* op, int which, const R* X, int64_t ldx, R
         const char* e = getenv("SEEDCG_TUNE");
         g_tune_mode = (e && e[0] == '0') ? 0 : 1;
     }
+    // no timing while the stream is captured into a graph (or when that cannot be asked)
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    hipStreamIsCapturing(s, &cs);
-    if (g_tune_mode == 0 || cs != hipStreamCaptureStatusNone) return default_variant(sizeof(R) == 4, k);
-    TuneRec rec = tune_variants<R>(op, which, X, ldx, Y, ldy, k, U, s);
-    g_tune[key] = rec;
+    const bool capturing = hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+    if (g_tune_mode == 0 || capturing) return default_variant(sizeof(R) == 4, k);
+    TuneRec rec;
+    if (tune_variants<R>(op, which, X, ldx, Y, ldy, k, U, s, rec)) g_tune[key] = rec;
     return rec.best;
 }
 

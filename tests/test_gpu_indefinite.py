@@ -150,3 +150,24 @@ def test_indefinite_seeded_column_groups():
         assert abs(a - b) <= max(3, 0.05 * b), (out["iters"], ref["iters"])
     Xs = B / d[:, None]
     assert np.linalg.norm(out["X"].cpu().numpy().T - Xs) / np.linalg.norm(Xs) <= 2 * 334 * 1e-8  # cond = 1/0.003
+
+
+def test_minres_edge_cases():
+    # a zero column is solved by x = 0 in 0 iterations; maxit stops a column
+    # with its true residual reported; a converged start takes 0 iterations
+    _say("minres edge cases")
+    g = np.random.default_rng(9)
+    d = np.sort(np.concatenate([-g.uniform(0.2, 1.0, 100), g.uniform(0.2, 1.0, 100)]))
+    op = api.Op.diag(torch.from_numpy(d).to(DEV))
+    B = torch.zeros((2, d.size), dtype=torch.float64, device=DEV)
+    B[1] = torch.from_numpy(g.standard_normal(d.size)).to(DEV)
+    X, its, rel = api.solve_minres(op, B, 1e-10)
+    assert its[0] == 0 and float(X[0].abs().max()) == 0.0
+    assert rel[1] <= 1e-10
+    Xc, its, rel = api.solve_minres(op, B[1:], 1e-10, maxit=5)
+    assert its[0] == 5 and rel[0] > 1e-10
+    b = B[1].cpu().numpy()
+    assert abs(rel[0] - np.linalg.norm(b - d * Xc[0].cpu().numpy()) / np.linalg.norm(b)) <= 1e-12
+    X0 = torch.from_numpy(b / d).to(DEV)[None]
+    _, its, rel = api.solve_minres(op, B[1:], 1e-10, X0=X0)
+    assert its[0] == 0 and rel[0] <= 1e-10
