@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--indefinite", action="store_true",
                     help="time the indefinite variant (gamma_5 D, QR of T, MINRES; FP64) against the normal-equations "
                          "path on the workload instead of the benchmark (Sections 3 and 4)")
+    ap.add_argument("--batch", action="store_true",
+                    help="time the uneven batch (six independent Wilson lattices from 8^4 to 16^3x32, 4-24 RHS each, "
+                         "mixed precision) in one batched call against the same systems solved one after another")
     ap.add_argument("--compare-seeding", action="store_true",
                     help="A-applies, vector operations and time of no / multiple / single seeding on the workload "
                          "(Section 2, Table 2.1 analogue) instead of the benchmark")
@@ -201,6 +204,56 @@ def related_bench(args, w):
         assert max(out["relres"]) <= w.tol
         res[name] = {"ms": round(dt * 1e3, 2), "rhs_per_s": round(k / dt, 3), "iters": list(out["iters"])}
         log(f"[related] {name}: {dt * 1e3:.1f} ms, iters {list(out['iters'])}")
+    print(json.dumps(res), flush=True)
+
+
+def batch_bench(args):
+    """The uneven batch: one sc_batch_solve call (seed phases of all systems in
+    one HIP graph, then projection and CG of each system on its own stream)
+    against the same systems solved one after another by the one-call driver."""
+    import numpy as np
+    import torch
+
+    from paper_0810_0330_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    tol = 1e-8
+    systems = []
+    for sd in synth.uneven_batch():
+        op = api.Op.wilson(sd["dims"], torch.from_numpy(api.pack_links(sd["U"])).to(dev), sd["kappa"])
+        B = torch.from_numpy(api.pack_field(np.ascontiguousarray(sd["B"].T))).to(dev)
+        _, it, _ = api.solve_cg(op, B[:1], tol)
+        m = synth.seed_steps(it[0])
+        systems.append({"op": op, "B": B, "m": m, "freq": 100 if m >= 200 else 50, "tol": tol, "mixed": True,
+                        "dims": list(sd["dims"]), "kappa": round(sd["kappa"], 4)})
+    nrhs = sum(int(sd["B"].shape[0]) for sd in systems)
+    log(f"[batch] {len(systems)} systems, {nrhs} RHS: " +
+        ", ".join(f"{sd['dims']} k={sd['B'].shape[0]} m={sd['m']}" for sd in systems))
+
+    def batched():
+        return api.batch_solve(systems)
+
+    def one_at_a_time():
+        return [api.single_seed_solve(sd["op"], sd["B"], sd["m"], sd["freq"], tol, mixed=True) for sd in systems]
+
+    for fn in (batched, one_at_a_time):  # warm: tuning, graph capture, allocations
+        fn()
+    res = {"mode": "uneven_batch", "nrhs": nrhs, "tol": tol, "precision": "mixed", "steps": args.steps,
+           "systems": [{"dims": sd["dims"], "kappa": sd["kappa"], "nrhs": int(sd["B"].shape[0]), "m": sd["m"],
+                        "freq": sd["freq"]} for sd in systems]}
+    for name, fn in (("batched", batched), ("one_at_a_time", one_at_a_time)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            outs = fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        for o in outs:
+            assert o["status"] in (0, 2) and max(o["relres"]) <= tol
+        res[name] = {"ms": round(dt * 1e3, 2), "rhs_per_s": round(nrhs / dt, 2),
+                     "iters": [list(o["iters"]) for o in outs]}
+        log(f"[batch] {name}: {dt * 1e3:.1f} ms per batch, {nrhs / dt:.1f} RHS/s")
+    res["speedup"] = round(res["one_at_a_time"]["ms"] / res["batched"]["ms"], 3)
     print(json.dumps(res), flush=True)
 
 
@@ -424,6 +477,8 @@ def main():
         return sweep_freq(args, w)
     if args.indefinite:
         return indefinite_bench(args, w)
+    if args.batch:
+        return batch_bench(args)
     if args.related:
         return related_bench(args, w)
     if args.compare_seeding:
