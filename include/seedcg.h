@@ -240,7 +240,7 @@ sc_status sc_project(int64_t n, const void* V_dev, int64_t ldv, sc_dtype v_dtype
  * it is above tol.  One iteration = one A-apply.
  * mixed = 0: FP64 throughout.  mixed = 1: FP32 vectors and operator with FP64
  * reliable updates: x and the true residual b - A x are kept in FP64 and
- * recomputed whenever the FP32 residual has fallen by 100x since the last
+ * recomputed whenever the FP32 residual has fallen by 1e4x since the last
  * update, and at FP32 convergence; a column is converged only when its FP64
  * true residual is <= tol.  (Wilson needs U32_dev.)
  * iters (host, k ints), relres (host, k doubles: true relative residuals).

@@ -20,7 +20,7 @@
 // mixed = 1: the vectors and the operator run in FP32; x and the true
 // residual are FP64.  A reliable update (x64 += x32, r = b - A64 x64, r32 =
 // r, x32 = 0) is made for every column whose FP32 residual norm has fallen by
-// 100x since its last update, at the next host check (the column keeps
+// 1e4x since its last update, at the next host check (the column keeps
 // iterating meanwhile, so no column idles; p is kept and CG continues with
 // the true residual), and when the FP32 residual reaches tol (the column
 // stops; CG restarts from the true residual if it is still above tol).
@@ -32,8 +32,10 @@
 namespace sc {
 
 // Mixed precision: a column's reliable update is due once its FP32 residual
-// norm is 100x below the largest since its last update (squared: 1e-4).
-constexpr double kRelUpdate2 = 1e-4;
+// norm is 1e4 times below the largest since its last update (squared: 1e-8).
+// The FP32 recurrence then still sits about three orders of magnitude above
+// its rounding floor (single precision relative to that largest norm).
+constexpr double kRelUpdate2 = 1e-8;
 
 __global__ void k_cg_setup(CGCol* st, const double* rho, const double* bn, int k, double tol, int maxit, int first) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
