@@ -460,7 +460,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "bench.py measures one GPU only; the multi-GPU path is design-only "
-                                   "(lattice domain decomposition, see DESIGN.md)", "n_gpus": args.gpus}))
+                                   "(the lattice would be split across GPUs by domain decomposition; not built)",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np

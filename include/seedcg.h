@@ -68,7 +68,7 @@ typedef enum {
     SC_ERR_NOT_PD = -3,     /* a non-positive LU pivot of T: A is not positive definite */
     SC_ERR_NONFINITE = -4,  /* NaN or Inf met in a norm */
     SC_ERR_WORKSPACE = -5,  /* work buffer smaller than sc_workspace_size() */
-    SC_ERR_UNSUPPORTED = -6 /* valid request this build does not implement */
+    SC_ERR_UNSUPPORTED = -6 /* valid request the library does not implement */
 } sc_status;
 
 typedef struct sc_op sc_op;   /* opaque; immutable after creation */

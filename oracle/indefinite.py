@@ -6,7 +6,7 @@ for indefinite systems), and MINRES to finish each system.
 Test infrastructure only (see ``oracle/__init__.py``).
 
 The paper gives no algorithm for this variant beyond those two remarks.  The
-readings (listed in DESIGN.md) are:
+readings are:
   R21  Q = gamma_5 D, Hermitian and indefinite (gamma_5-hermiticity of D); it
        costs one product with D per iteration.  The system D x = b is Q x =
        gamma_5 b; the functions here solve Q x = b for the b they are given.

@@ -4,7 +4,7 @@ projection of the other right-hand sides over the stored Lanczos basis.
 
 Test infrastructure only (see ``oracle/__init__.py``).
 
-Readings of points the paper leaves open (each is listed in the design doc):
+Readings of points the paper leaves open:
   R1  v_2 is f / beta_1 after step 2; step 8 never runs at i = 1.
   R2  alpha_i = Re(v_i^H f): T is real symmetric tridiagonal for Hermitian A.
   R3  steps 5-7 use v_i as it was before step 8; step 8 then overwrites the
