@@ -82,18 +82,97 @@ __device__ __forceinline__ bool map_work(int ntiles, int ncg, int G, int per_xcd
     return true;
 }
 
+// Epilogues of the fused CG passes (the t-march and tiled forms; the partial
+// sums of a block are left per column in e.part, see the kernels):
+//   TM_NORM: out is written and the partials are of |out|^2 (for A = D^H D,
+//     <p, A p> = ||D p||^2, so CG needs no separate reduction over p and A p);
+//   TM_CG: out (= A p of a CG iteration) is not stored; for the columns active
+//     in e.st, r -= alpha out with alpha = rho / (sum of e.pq's partials), and
+//     the partials are of |r|^2.
+enum { TM_PLAIN = 0, TM_NORM = 1, TM_CG = 2 };
+
+struct TmEpi {
+    double* part;
+    const CGCol* st;
+    const double* pq;
+    void* r;
+    int64_t ldr;  // reals
+};
+
+
+// One output element of a tiled pass under epilogue EPI (see above): stored to
+// out, or (TM_CG) applied to r in place, with its |.|^2 added to nacc.
+template <typename R, int EPI>
+__device__ __forceinline__ void epi_store(R* dst, R* rv, size_t cb, unsigned us, cplx<R> r, R alpha, double& nacc) {
+    using V2 = typename vec2<R>::type;
+    if constexpr (EPI == TM_CG) {
+        V2 rr = reinterpret_cast<V2*>(rv + cb)[us];
+        rr.x = rr.x - alpha * r.re;
+        rr.y = rr.y - alpha * r.im;
+        reinterpret_cast<V2*>(rv + cb)[us] = rr;
+        nacc += (double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y;
+    } else {
+        reinterpret_cast<V2*>(dst + cb)[us] = V2{r.re, r.im};
+        if constexpr (EPI == TM_NORM) nacc += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
+    }
+}
+
+// alpha = rho / (sum of the TM_NORM partials) per column for TM_CG (block-uniform;
+// the same sum, in the same order, as the CG kernel that follows), and which
+// columns the pass updates
+template <typename R, int EPI, int NC>
+__device__ __forceinline__ void epi_setup(const TmEpi& e, const bool live[NC], int c0, int ntiles, double* sh,
+                                          R alpha[NC], bool upd[NC], double nacc[NC]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        nacc[c] = 0.0;
+        upd[c] = live[c];
+        alpha[c] = R(0);
+    }
+    if constexpr (EPI == TM_CG) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int col = live[c] ? c0 + c : c0;
+            const double pq = sum_partials(e.pq + (int64_t)col * ntiles, ntiles, sh);
+            upd[c] = live[c] && e.st[col].active;
+            alpha[c] = upd[c] ? (R)(e.st[col].rho / pq) : R(0);
+        }
+    }
+}
+
+// The block's partial of each live column at index column * ntiles + tile of e.part
+template <int EPI, int NC>
+__device__ __forceinline__ void epi_finish(const TmEpi& e, const bool live[NC], int c0, int ntiles, int tile,
+                                           double* sh, const double nacc[NC]) {
+    if constexpr (EPI != TM_PLAIN) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double tot = block_sum(nacc[c], sh);
+            if (threadIdx.x == 0 && live[c]) e.part[(int64_t)(c0 + c) * ntiles + tile] = tot;
+        }
+    }
+}
+
 // MODE 0: out = in - kappa * H in (D or D^H);  MODE 1: out = H in (or H^H in).
 // NC columns per thread: each link is loaded once and applied to NC spinors.
-template <typename R, bool DAG, int MODE, int NC, int MINW, bool BAR = false>
+// With an epilogue (EPI != TM_PLAIN) every lane of a block stays for the block
+// sums: a lane past the last site works on the last site and stores nothing.
+template <typename R, bool DAG, int MODE, int NC, int MINW, bool BAR = false, int EPI = TM_PLAIN>
 __global__ __launch_bounds__(kBlock, MINW) void k_wilson(R* __restrict__ out, int64_t ldo, const R* __restrict__ in,
                                                    int64_t ldi, const R* __restrict__ U, Geom g, R kappa, R tsign,
-                                                   int k, int ncg, int ntiles, int per_xcd, int G, int zb) {
+                                                   int k, int ncg, int ntiles, int per_xcd, int G, int zb, TmEpi e) {
     int tile, cgi;
     if (!map_work(ntiles, ncg, G, per_xcd, zb, g.T, tile, cgi)) return;
     const int c0 = cgi * NC;
-    const int s = tile * kBlock + threadIdx.x;
+    int s = tile * kBlock + threadIdx.x;
     const int V = (int)g.V;
-    if (s >= V) return;
+    bool ok = true;
+    if constexpr (EPI == TM_PLAIN) {
+        if (s >= V) return;
+    } else {
+        ok = s < V;
+        if (!ok) s = V - 1;
+    }
     const int XY = g.X * g.Y, XYZ = XY * g.Z;
     const int x = s % g.X;
     const int y = (s / g.X) % g.Y;
@@ -119,6 +198,15 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson(R* __restrict__ out, in
     for (int c = 0; c < NC; ++c) {
         live[c] = c0 + c < k;
         src[c] = in + (int64_t)(live[c] ? c0 + c : c0) * ldi;
+    }
+    [[maybe_unused]] double* esh = nullptr;
+    R alpha[NC];
+    bool upd[NC];
+    double nacc[NC];
+    if constexpr (EPI != TM_PLAIN) {
+        __shared__ double esh_[kWaves];
+        esh = esh_;
+        epi_setup<R, EPI, NC>(e, live, c0, ntiles, esh, alpha, upd, nacc);
     }
 
     cplx<R> acc[NC][4][3];
@@ -155,7 +243,11 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson(R* __restrict__ out, in
 
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        if (!live[c]) continue;
+        if constexpr (EPI == TM_PLAIN) {
+            if (!live[c]) continue;
+        } else {
+            if (!ok || !upd[c]) continue;
+        }
         R* dst = out + (int64_t)(c0 + c) * ldo;
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -167,25 +259,35 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson(R* __restrict__ out, in
                     const cplx<R> p = ldc(src[c] + cb, us);
                     r = {p.re - kappa * r.re, p.im - kappa * r.im};
                 }
-                reinterpret_cast<typename vec2<R>::type*>(dst + cb)[us] = typename vec2<R>::type{r.re, r.im};
+                if constexpr (EPI == TM_PLAIN)
+                    reinterpret_cast<typename vec2<R>::type*>(dst + cb)[us] = typename vec2<R>::type{r.re, r.im};
+                else
+                    epi_store<R, EPI>(dst, (R*)e.r + (int64_t)(c0 + c) * e.ldr, cb, us, r, alpha[c], nacc[c]);
             }
     }
+    if constexpr (EPI != TM_PLAIN) epi_finish<EPI, NC>(e, live, c0, ntiles, tile, esh, nacc);
 }
 
 // Rolled variant: a runtime loop over the 8 hops with a wave-uniform switch.
 // Only one hop's operands are live at a time (low register use, high
 // occupancy); the latency of a hop's loads is hidden by the other waves.
-template <typename R, bool DAG, int MODE, int NC, int MINW>
+template <typename R, bool DAG, int MODE, int NC, int MINW, int EPI = TM_PLAIN>
 __global__ __launch_bounds__(kBlock, MINW) void k_wilson_r(R* __restrict__ out, int64_t ldo, const R* __restrict__ in,
                                                          int64_t ldi, const R* __restrict__ U, Geom g, R kappa,
                                                          R tsign, int k, int ncg, int ntiles, int per_xcd, int G,
-                                                         int zb) {
+                                                         int zb, TmEpi e) {
     int tile, cgi;
     if (!map_work(ntiles, ncg, G, per_xcd, zb, g.T, tile, cgi)) return;
     const int c0 = cgi * NC;
-    const int s = tile * kBlock + threadIdx.x;
+    int s = tile * kBlock + threadIdx.x;
     const int V = (int)g.V;
-    if (s >= V) return;
+    bool ok = true;  // as in k_wilson
+    if constexpr (EPI == TM_PLAIN) {
+        if (s >= V) return;
+    } else {
+        ok = s < V;
+        if (!ok) s = V - 1;
+    }
     const int XY = g.X * g.Y, XYZ = XY * g.Z;
     const int x = s % g.X;
     const int y = (s / g.X) % g.Y;
@@ -201,6 +303,15 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson_r(R* __restrict__ out, 
     for (int c = 0; c < NC; ++c) {
         live[c] = c0 + c < k;
         src[c] = in + (int64_t)(live[c] ? c0 + c : c0) * ldi;
+    }
+    [[maybe_unused]] double* esh = nullptr;
+    R alpha[NC];
+    bool upd[NC];
+    double nacc[NC];
+    if constexpr (EPI != TM_PLAIN) {
+        __shared__ double esh_[kWaves];
+        esh = esh_;
+        epi_setup<R, EPI, NC>(e, live, c0, ntiles, esh, alpha, upd, nacc);
     }
     cplx<R> acc[NC][4][3];
 #pragma unroll
@@ -245,7 +356,11 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson_r(R* __restrict__ out, 
 
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        if (!live[c]) continue;
+        if constexpr (EPI == TM_PLAIN) {
+            if (!live[c]) continue;
+        } else {
+            if (!ok || !upd[c]) continue;
+        }
         R* dst = out + (int64_t)(c0 + c) * ldo;
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -257,9 +372,13 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson_r(R* __restrict__ out, 
                     const cplx<R> p = ldc(src[c] + cb, us);
                     r = {p.re - kappa * r.re, p.im - kappa * r.im};
                 }
-                reinterpret_cast<typename vec2<R>::type*>(dst + cb)[us] = typename vec2<R>::type{r.re, r.im};
+                if constexpr (EPI == TM_PLAIN)
+                    reinterpret_cast<typename vec2<R>::type*>(dst + cb)[us] = typename vec2<R>::type{r.re, r.im};
+                else
+                    epi_store<R, EPI>(dst, (R*)e.r + (int64_t)(c0 + c) * e.ldr, cb, us, r, alpha[c], nacc[c]);
             }
     }
+    if constexpr (EPI != TM_PLAIN) epi_finish<EPI, NC>(e, live, c0, ntiles, tile, esh, nacc);
 }
 
 // t-march form, for lattices whose xy-plane is one 256-site tile.  A block
@@ -280,21 +399,8 @@ __global__ __launch_bounds__(kBlock, MINW) void k_wilson_r(R* __restrict__ out, 
 // (CGMINOR = true: all column groups of a plane share its links through one
 // L2).
 //
-// Epilogues (EPI), with the block's partial sums left per column at index
-// column * (Z * nseg) + (segment * Z + z) of e.part:
-//   TM_NORM: out is written and the partials are of |out|^2 (for A = D^H D,
-//     <p, A p> = ||D p||^2, so CG needs no separate reduction over p and A p);
-//   TM_CG: out (= A p of a CG iteration) is not stored; for the columns active
-//     in e.st, r -= alpha out with alpha = rho / (sum of e.pq's partials), and
-//     the partials are of |r|^2.
-enum { TM_PLAIN = 0, TM_NORM = 1, TM_CG = 2 };
-struct TmEpi {
-    double* part;
-    const CGCol* st;
-    const double* pq;
-    void* r;
-    int64_t ldr;  // reals
-};
+// Epilogues (EPI, above), with the block's partial sums left per column at
+// index column * (Z * nseg) + (segment * Z + z) of e.part.
 
 // Sum over the 256 threads of plane zz of a block of NZ planes (the tree of
 // block_sum, so the value is that of a one-plane block), and the index-order
@@ -718,12 +824,12 @@ static void wilson_launch_v(const sc_op* op, int which, const R* X, int64_t ldx,
     const R ts = op->antiperiodic ? R(-1) : R(1);
     // ld arguments are in reals (2 per complex element)
 #define SC_WL(DAG, MODE)                                                                                       \
-    if (ROLLED)                                                                                                \
+    if constexpr (ROLLED)                                                                                      \
         SC_TLAUNCH((k_wilson_r<R, DAG, MODE, NC, 1>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,         \
-                           2 * ldx, U, g, kap, ts, k, ncg, ntiles, per_xcd, G, zb);                            \
+                           2 * ldx, U, g, kap, ts, k, ncg, ntiles, per_xcd, G, zb, TmEpi{});                   \
     else                                                                                                       \
         SC_TLAUNCH((k_wilson<R, DAG, MODE, NC, 1, false>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,    \
-                           2 * ldx, U, g, kap, ts, k, ncg, ntiles, per_xcd, G, zb);
+                           2 * ldx, U, g, kap, ts, k, ncg, ntiles, per_xcd, G, zb, TmEpi{});
     switch (which) {
         case 0: SC_WL(false, 0) break;
         case 1: SC_WL(true, 0) break;
@@ -731,6 +837,48 @@ static void wilson_launch_v(const sc_op* op, int which, const R* X, int64_t ldx,
         default: SC_WL(true, 1) break;
     }
 #undef SC_WL
+}
+
+// The fused CG passes on a tiled shape: epi TM_NORM is the D pass (partials of
+// |D p|^2), TM_CG the D^H pass (r -= alpha A p); partials per column and tile.
+template <typename R, int NC, bool ROLLED>
+static void wilson_launch_v_epi(const sc_op* op, int epi, const R* X, int64_t ldx, R* Y, int64_t ldy, int k,
+                                const R* U, int chunk, int order, const TmEpi& e, hipStream_t s) {
+    Geom g{op->dims[0], op->dims[1], op->dims[2], op->dims[3], op->vol};
+    const int ntiles = (int)((g.V + kBlock - 1) / kBlock);
+    const int ncg = (k + NC - 1) / NC;
+    const int G = chunk_groups(chunk, ncg);
+    const int zb = (order == 1 && zblock_ok(op)) ? kZBlock : 1;
+    const int per_xcd = (ntiles * ncg + kXcd - 1) / kXcd;
+    dim3 grid((unsigned)(per_xcd * kXcd));
+    const R kap = (R)op->kappa;
+    const R ts = op->antiperiodic ? R(-1) : R(1);
+#define SC_WLE(DAG, EPI_)                                                                                      \
+    if constexpr (ROLLED)                                                                                      \
+        SC_TLAUNCH((k_wilson_r<R, DAG, 0, NC, 1, EPI_>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X, 2 * ldx, U, \
+                   g, kap, ts, k, ncg, ntiles, per_xcd, G, zb, e);                                             \
+    else                                                                                                       \
+        SC_TLAUNCH((k_wilson<R, DAG, 0, NC, 1, false, EPI_>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X,        \
+                   2 * ldx, U, g, kap, ts, k, ncg, ntiles, per_xcd, G, zb, e);
+    if (epi == TM_NORM) {
+        SC_WLE(false, TM_NORM)
+    } else {
+        SC_WLE(true, TM_CG)
+    }
+#undef SC_WLE
+}
+
+template <typename R>
+static void wilson_launch_variant_epi(int v, const sc_op* op, int epi, const R* X, int64_t ldx, R* Y, int64_t ldy,
+                                      int k, const R* U, const TmEpi& e, hipStream_t s) {
+    constexpr int N4 = sizeof(R) == 4 ? 4 : 2;
+    const int chunk = v % kChunks, order = v / (WS_COUNT * kChunks);
+    switch ((v / kChunks) % WS_COUNT) {
+        case WS_UNROLLED_1: wilson_launch_v_epi<R, 1, false>(op, epi, X, ldx, Y, ldy, k, U, chunk, order, e, s); break;
+        case WS_ROLLED_1: wilson_launch_v_epi<R, 1, true>(op, epi, X, ldx, Y, ldy, k, U, chunk, order, e, s); break;
+        case WS_ROLLED_2: wilson_launch_v_epi<R, 2, true>(op, epi, X, ldx, Y, ldy, k, U, chunk, order, e, s); break;
+        default: wilson_launch_v_epi<R, N4, true>(op, epi, X, ldx, Y, ldy, k, U, chunk, order, e, s); break;
+    }
 }
 
 static int default_variant(bool single, int k) {
@@ -944,12 +1092,20 @@ static sc_status wilson_cg_fused_t(const sc_op* op, const R* p, R* tmp, int k, c
                                    double* part_pq, R* r, int64_t ldr, double* part_rr, int max_parts, int* G,
                                    hipStream_t s) {
     *G = 0;
-    if (!tmarch_ok(op)) return SC_OK;
+    // the t-march shapes (partials per plane and segment) and the tiled ones
+    // (partials per 256-site tile); the direction-split shape has no epilogues
     const int v = choose_variant<R>(op, 0, p, op->n, tmp, op->n, k, U, s);
-    if (!is_tmarch(v)) return SC_OK;
-    const TmShape t = tm_shape(v, sizeof(R) == 4, op->dims[2]);
-    const int tlen = std::max(1, std::min(t.tlen, op->dims[3]));
-    const int parts = op->dims[2] * ((op->dims[3] + tlen - 1) / tlen);
+    const bool tm = is_tmarch(v) && tmarch_ok(op);
+    if (!tm && (v == WV_DIR || is_tmarch(v))) return SC_OK;
+    TmShape t{};
+    int parts;
+    if (tm) {
+        t = tm_shape(v, sizeof(R) == 4, op->dims[2]);
+        const int tlen = std::max(1, std::min(t.tlen, op->dims[3]));
+        parts = op->dims[2] * ((op->dims[3] + tlen - 1) / tlen);
+    } else {
+        parts = (int)((op->vol + kBlock - 1) / kBlock);
+    }
     if (parts > max_parts) return SC_OK;
     const double bytes = (48.0 * k + 72.0) * sizeof(R) * (double)op->vol;
     const int cls = sizeof(R) == 4 ? (k == 1 ? TC_WILSON_F32 : TC_WILSON_F32_K) : (k == 1 ? TC_WILSON_F64 : TC_WILSON_F64_K);
@@ -957,7 +1113,10 @@ static sc_status wilson_cg_fused_t(const sc_op* op, const R* p, R* tmp, int k, c
         TimerScope ts_(cls, s, bytes, 1368.0 * k * (double)op->vol);
         TmEpi e{};
         e.part = part_pq;
-        tm_launch<R>(op, 0, p, op->n, tmp, op->n, k, U, t, TM_NORM, e, s);
+        if (tm)
+            tm_launch<R>(op, 0, p, op->n, tmp, op->n, k, U, t, TM_NORM, e, s);
+        else
+            wilson_launch_variant_epi<R>(v, op, TM_NORM, p, op->n, tmp, op->n, k, U, e, s);
         SC_LAUNCH_CHECK();
     }
     {
@@ -969,7 +1128,10 @@ static sc_status wilson_cg_fused_t(const sc_op* op, const R* p, R* tmp, int k, c
         e.pq = part_pq;
         e.r = r;
         e.ldr = 2 * ldr;
-        tm_launch<R>(op, 1, tmp, op->n, tmp, op->n, k, U, t, TM_CG, e, s);
+        if (tm)
+            tm_launch<R>(op, 1, tmp, op->n, tmp, op->n, k, U, t, TM_CG, e, s);
+        else
+            wilson_launch_variant_epi<R>(v, op, TM_CG, tmp, op->n, tmp, op->n, k, U, e, s);
         SC_LAUNCH_CHECK();
     }
     *G = parts;

@@ -460,6 +460,42 @@ def test_not_pd_and_nonfinite():
     assert e.value.status == -4
 
 
+@pytest.mark.parametrize("dims", [(4, 4, 4, 6), (8, 8, 16, 4)])
+def test_fused_cg_every_tiled_shape(dims):
+    # on lattices whose xy-plane is not one 256-site tile, CG fuses <p, Ap>
+    # into the D pass and r -= alpha Ap into the D^H pass of the tiled shape
+    # the tuner picked; each tiled shape (ids 0..31) pinned in turn, FP64 and
+    # mixed, against the oracle's CG and against the unfused path (the
+    # direction-split shape, 44, has no epilogue).  4^3 x 6 has a ragged last
+    # tile; 8 x 8 x 16 x 4 holds 4 tiles per time slice (the z-blocked order).
+    _say("fused CG on tiled shapes", dims)
+    U, op = _wilson(dims, cfg=12)
+    k = 5  # partial column groups for 2 and 4 columns per thread
+    B = np.concatenate([synth.point_sources(dims, synth.ALL_SPIN_COLOUR[:3]),
+                        synth.z4_noise(op.n, 2, synth.rng(12, 3))], axis=1)
+    oop = ops.WilsonNormalOp(U, 0.12)
+    tol = 1e-10
+    ref = [cg(oop, B[:, j], tol=tol)[1] for j in range(k)]
+    for single in (False, True):
+        base = None
+        for v in list(range(32)) + [44]:
+            op.tune_set(k, v, single=single)
+            X, its, rel = api.solve_cg(op, _to_lib(B), tol, mixed=single)
+            assert max(rel) <= tol, (single, v, rel)
+            Xn = _to_nat(X)
+            for j in (0, k - 1):
+                r = B[:, j] - oop(Xn[:, j])
+                assert np.linalg.norm(r) / np.linalg.norm(B[:, j]) <= 1.5 * tol, (single, v, j)
+            for a, b in zip(its, ref):
+                assert abs(a - b) <= (4 if single else 2), (single, v, its, ref)
+            if v == 0:
+                base = its
+            elif not single:
+                for a, b in zip(its, base):
+                    assert abs(a - b) <= 1, (v, its, base)
+        op.tune_set(k, -1, single=single)
+
+
 def test_cg_edge_cases():
     _say("cg edge cases")
     op = api.Op.laplace2d(16, 16)
