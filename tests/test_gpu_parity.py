@@ -496,6 +496,23 @@ def test_fused_cg_every_tiled_shape(dims):
         op.tune_set(k, -1, single=single)
 
 
+def test_tuner_record():
+    # after tuning, each candidate's time is -1 (not applicable, not run) or
+    # positive, and the chosen shape is the fastest of those timed; the
+    # t-march shapes do not apply to a lattice whose xy-plane is not 256 sites
+    _say("tuner record")
+    U, op = _wilson((4, 4, 4, 6), cfg=13)
+    X = _to_lib(synth.complex_gaussian(op.n, 3, synth.rng(13, 1))).to(torch.complex64)
+    op.tune_set(3, -1, single=True)
+    op.dslash(X, 0, single=True)
+    v, us = op.tune_info(3, single=True)
+    us = np.array(us)
+    assert 0 <= v < api.WILSON_VARIANTS
+    assert np.all((us == -1.0) | (us > 0.0))
+    assert us[v] == us[us > 0.0].min()
+    assert np.all(us[32:44] == -1.0) and np.all(us[45:] == -1.0)
+
+
 def test_cg_edge_cases():
     _say("cg edge cases")
     op = api.Op.laplace2d(16, 16)
