@@ -513,6 +513,58 @@ def test_tuner_record():
     assert np.all(us[32:44] == -1.0) and np.all(us[45:] == -1.0)
 
 
+@pytest.mark.parametrize("m", [1, 2])
+def test_shortest_seeds(m):
+    # one and two Lanczos steps (T is 1x1 or 2x2, a reorthogonalization at
+    # every step from i = 2): the seeded guesses and the CG counts of both
+    # paths against the oracle, on the real Laplacian and on Wilson 4^4 (FP64
+    # and mixed)
+    _say("shortest seeds, m =", m)
+    cases = []
+    B = synth.make_inputs(synth.laplace_32x32())["B"][:, :3]
+    cases.append((api.Op.laplace2d(32, 32), ops.Laplace2DOp(32, 32), B, torch.from_numpy(B.T.copy()).to(DEV), 1e-10,
+                  lambda X: X.cpu().numpy().T))
+    U, op = _wilson((4, 4, 4, 4), cfg=14)
+    Bw = np.concatenate([synth.point_sources((4, 4, 4, 4), synth.ALL_SPIN_COLOUR[:2]),
+                         synth.z4_noise(op.n, 1, synth.rng(14, 2))], axis=1)
+    cases.append((op, ops.WilsonNormalOp(U, 0.12), Bw, _to_lib(Bw), 1e-10, _to_nat))
+    for gop, oop, Bn, Bt, tol, nat in cases:
+        ref = o_seeded_solve(oop, Bn, m, 1, tol)
+        for mixed in ((False, True) if gop is op else (False,)):
+            three = api.seeded_solve(gop, Bt, m, 1, tol, mixed=mixed)
+            one = api.single_seed_solve(gop, Bt, m, 1, tol, mixed=mixed)
+            assert one["m_done"] == three["basis"].m_done == m
+            if not mixed:
+                assert _rel(nat(three["X_seeded"]), ref["X_seeded"]) < 1e-10
+            for out in (three, one):
+                assert max(out["relres"]) <= tol
+                for a, b in zip(out["iters"], ref["iters"]):
+                    assert abs(a - b) <= (4 if mixed else 2), (m, mixed, out["iters"], ref["iters"])
+
+
+def test_seeded_solve_periodic_time():
+    # periodic (not antiperiodic) time boundary through the whole method, on a
+    # t-march lattice (xy-plane of 256 sites) and on a tiled one, FP64 and mixed
+    for dims in [(16, 16, 2, 4), (4, 4, 4, 8)]:
+        _say("seeded solve, periodic t", dims)
+        U = synth.su3_links(dims, synth.rng(15, 0))
+        op = api.Op.wilson(dims, torch.from_numpy(api.pack_links(U)).to(DEV), 0.12, False)
+        oop = ops.WilsonNormalOp(U, 0.12, antiperiodic=False)
+        B = np.concatenate([synth.point_sources(dims, synth.ALL_SPIN_COLOUR[:2]),
+                            synth.z4_noise(oop.n, 2, synth.rng(15, 2))], axis=1)
+        m, tol = 30, 1e-10
+        ref = o_seeded_solve(oop, B, m, 1, tol)
+        for mixed in (False, True):
+            out = api.single_seed_solve(op, _to_lib(B), m, 1, tol, mixed=mixed)
+            assert out["m_done"] == m and max(out["relres"]) <= tol
+            for a, b in zip(out["iters"], ref["iters"]):
+                assert abs(a - b) <= (4 if mixed else 2), (dims, mixed, out["iters"], ref["iters"])
+            X = _to_nat(out["X"])
+            for j in range(B.shape[1]):
+                r = B[:, j] - oop(X[:, j])
+                assert np.linalg.norm(r) / np.linalg.norm(B[:, j]) <= 1.5 * tol, (dims, mixed, j)
+
+
 def test_cg_edge_cases():
     _say("cg edge cases")
     op = api.Op.laplace2d(16, 16)
