@@ -87,3 +87,38 @@ def test_batch_uneven_six_lattices_mixed():
             x = _nat(X[j:j + 1])[:, 0]
             rr = np.linalg.norm(sd["B"][:, j] - oop(x)) / np.linalg.norm(sd["B"][:, j])
             assert rr <= 1.5 * tol, (sd["dims"], j, rr)
+
+
+def test_batch_mixed_operator_kinds():
+    # one batch of different operator kinds and outcomes: the real 32x32
+    # Laplacian, a diagonal whose seed breaks down (b on 150 of 600
+    # eigenvectors), and Wilson 4^4 in mixed precision; statuses, basis sizes
+    # and counts against the same systems solved alone by the one-call driver
+    print("batch of mixed operator kinds", flush=True)
+    g = np.random.default_rng(16)
+    Bl = synth.make_inputs(synth.laplace_32x32())["B"][:, :3]
+    d = np.linspace(1.0, 3.0, 600)
+    Bd = np.zeros((600, 2))
+    Bd[:150, :] = g.standard_normal((150, 2))
+    dims = (4, 4, 4, 4)
+    U = synth.su3_links(dims, synth.rng(16, 0))
+    opw = api.Op.wilson(dims, torch.from_numpy(api.pack_links(U)).to(DEV), 0.12)
+    Bw = synth.point_sources(dims, synth.ALL_SPIN_COLOUR[:3])
+    systems = [
+        {"op": api.Op.laplace2d(32, 32), "B": torch.from_numpy(Bl.T.copy()).to(DEV), "m": 100, "freq": 1,
+         "tol": 1e-10},
+        {"op": api.Op.diag(torch.from_numpy(d).to(DEV)), "B": torch.from_numpy(Bd.T.copy()).to(DEV), "m": 200,
+         "freq": 1, "tol": 1e-10},
+        {"op": opw, "B": _lib(Bw), "m": 60, "freq": 10, "tol": 1e-9, "mixed": True},
+    ]
+    res = api.batch_solve(systems)
+    assert res[0]["status"] == 0 and res[2]["status"] == 0
+    assert res[1]["status"] == 2 and res[1]["m_done"] <= 150
+    for sd, r in zip(systems, res):
+        assert max(r["relres"]) <= sd["tol"]
+        alone = api.single_seed_solve(sd["op"], sd["B"], sd["m"], sd["freq"], sd["tol"], mixed=sd.get("mixed", False))
+        assert alone["m_done"] == r["m_done"] and alone["status"] == r["status"]
+        for a, b in zip(r["iters"], alone["iters"]):
+            assert abs(a - b) <= 2, (r["iters"], alone["iters"])
+    Xd = res[1]["X"].cpu().numpy().T
+    assert np.linalg.norm(Xd - Bd / d[:, None]) / np.linalg.norm(Bd / d[:, None]) <= 3 * 1e-10  # cond = 3
