@@ -5,7 +5,9 @@ dL/dkappa within 1e-8 relative (FP64 solves to 1e-12); on the 12^4 lattice
 (12 point sources, kappa = 0.12), the central difference in kappa with
 h = 1e-6 (FP64 solves to 1e-13, so the difference carries ~1e-13/1e-6 noise)
 within 1e-5 relative, and the central difference along random directions of
-b, which has no truncation error because L is linear in b, within 1e-8.
+b, which has no truncation error because L is linear in b, within 1e-8.  In
+mixed precision (FP32 solves with FP64 reliable updates, tol 1e-10) on 4^4,
+against the oracle gradient within 1e-7 (cond(A) tol bounds the solution errors).
 """
 import numpy as np
 import pytest
@@ -48,6 +50,28 @@ def test_grad_matches_oracle_4x4():
     gB = _nat(Bl.grad)
     assert np.abs(gB - Lamo).max() <= 1e-8 * np.abs(Lamo).max()
     assert abs(kap.grad.item() - gko) <= 1e-8 * abs(gko)
+
+
+def test_grad_mixed_precision_4x4():
+    # FP32 solves with FP64 reliable updates in the forward and the adjoint:
+    # the FP64 true residuals at tol = 1e-10 bound the errors of X and of the
+    # adjoint solutions by cond(A) tol (about 5e-9 here), hence 1e-7 on the gradients
+    print("grad mixed precision 4^4", flush=True)
+    dims = (4, 4, 4, 4)
+    U = synth.su3_links(dims, synth.rng(32, 0))
+    B = synth.point_sources(dims, synth.ALL_SPIN_COLOUR[:3])
+    Eta = synth.complex_gaussian(B.shape[0], 3, synth.rng(32, 2))
+    Lo, Xo, Lamo, gko = ograd.grads(U, 0.12, B, Eta, dense=True)
+    Ul = torch.from_numpy(api.pack_links(U)).to(DEV)
+    Bl = _lib(B).requires_grad_(True)
+    kap = torch.tensor(0.12, dtype=torch.float64, device=DEV, requires_grad=True)
+    X = seeded_solve(Bl, kap, Ul, dims, 60, 10, 1e-10, mixed=True)
+    L = _loss(X, _lib(Eta))
+    L.backward()
+    assert abs(L.item() - Lo) <= 1e-7 * abs(Lo)
+    gB = _nat(Bl.grad)
+    assert np.abs(gB - Lamo).max() <= 1e-7 * np.abs(Lamo).max()
+    assert abs(kap.grad.item() - gko) <= 1e-7 * abs(gko)
 
 
 @pytest.fixture(scope="module")
