@@ -25,8 +25,9 @@ seed       -- the Lanczos version of single seed CG with periodic
 seeded     -- the whole single-seed driver (seed, project, CG), the related
               right-hand-side variant of Section 2.3, and the multiple-seeding
               comparator of Section 2.1.
-mixed      -- a float32 emulation of CG with FP64 reliable updates (used to
-              state expected mixed-precision behaviour; parity unpinned).
+mixed      -- the mixed-precision path emulated in NumPy: CG with float32 /
+              complex64 vectors and operator and FP64 reliable updates, and
+              the seed phase with a single-precision basis and FP64 scalars.
 grad       -- gradients of L = sum_j Re<eta_j, x_j> with respect to b and kappa.
 indefinite -- the indefinite variant: gamma_5 D, the Lanczos seed without LU,
               minimum-residual guesses through the (m+1) x m tridiagonal matrix,

@@ -31,6 +31,10 @@ Conventions (shared with the library as a data format, not as code):
 Smaller operators: the unscaled 2D five-point Laplacian with zero Dirichlet
 boundary, and a diagonal matrix (the paper's Examples 1-5 use a diagonal A).
 
+Every operator also has a single-precision apply (``single()``: the same
+formulas evaluated in float32 / complex64 arithmetic), which the emulation of
+the mixed-precision solver in ``mixed.py`` uses.
+
 Parity pins (tests/test_oracle_operators.py): a dense matrix built entry by
 entry with pure-Python loops on tiny lattices; the closed-form free-field
 spectrum (plane waves); gamma_5-hermiticity D^H = gamma_5 D gamma_5; gauge
@@ -67,13 +71,13 @@ I4 = np.eye(4, dtype=np.complex128)
 # ----------------------------------------------------------------------------
 # 2D Laplacian (unscaled, zero Dirichlet halo)
 # ----------------------------------------------------------------------------
-def laplace2d_apply(x, nx, ny):
+def laplace2d_apply(x, nx, ny, dtype=np.float64):
     """y = 4 x - (north + south + east + west) on an nx-by-ny grid, zeros outside.
 
     ``x`` is a vector of length nx*ny (index i + nx*j, i fastest) or a matrix
-    whose columns are such vectors.
+    whose columns are such vectors.  Arithmetic in ``dtype``.
     """
-    x = np.asarray(x, dtype=np.float64)
+    x = np.asarray(x, dtype=dtype)
     cols = x.reshape(ny, nx, -1)
     y = 4.0 * cols
     y[1:, :, :] -= cols[:-1, :, :]
@@ -149,13 +153,17 @@ def _spin(p, chi):
     return np.matmul(p, chi)
 
 
-def wilson_hop(psi, U, antiperiodic=True, dagger=False):
-    """Hopping term H psi (or H^H psi when ``dagger``) on fields of shape (T,Z,Y,X,4,3)."""
-    psi = np.asarray(psi, dtype=np.complex128)
+def wilson_hop(psi, U, antiperiodic=True, dagger=False, dtype=np.complex128):
+    """Hopping term H psi (or H^H psi when ``dagger``) on fields of shape (T,Z,Y,X,4,3).
+
+    Arithmetic in ``dtype`` (complex128, or complex64 for the single-precision apply).
+    """
+    psi = np.asarray(psi, dtype=dtype)
+    U = np.asarray(U, dtype=dtype)
     out = np.zeros_like(psi)
     for mu in range(4):
-        pm = I4 - GAMMA[mu]
-        pp = I4 + GAMMA[mu]
+        pm = (I4 - GAMMA[mu]).astype(dtype)
+        pp = (I4 + GAMMA[mu]).astype(dtype)
         p_fwd, p_bwd = (pp, pm) if dagger else (pm, pp)
         fwd = _colour(U[mu], _shift_fwd(psi, mu, antiperiodic))
         u_back = np.roll(U[mu], 1, axis=_site_axis(mu))  # U_mu(x - mu)
@@ -164,19 +172,25 @@ def wilson_hop(psi, U, antiperiodic=True, dagger=False):
     return out
 
 
-def wilson_D(psi, U, kappa, antiperiodic=True):
+def _real_of(dtype):
+    return np.float32 if np.dtype(dtype) == np.complex64 else np.float64
+
+
+def wilson_D(psi, U, kappa, antiperiodic=True, dtype=np.complex128):
     """D psi = psi - kappa H psi."""
-    return np.asarray(psi, dtype=np.complex128) - kappa * wilson_hop(psi, U, antiperiodic)
+    k = _real_of(dtype)(kappa)
+    return np.asarray(psi, dtype=dtype) - k * wilson_hop(psi, U, antiperiodic, dtype=dtype)
 
 
-def wilson_Ddag(psi, U, kappa, antiperiodic=True):
+def wilson_Ddag(psi, U, kappa, antiperiodic=True, dtype=np.complex128):
     """D^H psi = psi - kappa H^H psi."""
-    return np.asarray(psi, dtype=np.complex128) - kappa * wilson_hop(psi, U, antiperiodic, dagger=True)
+    k = _real_of(dtype)(kappa)
+    return np.asarray(psi, dtype=dtype) - k * wilson_hop(psi, U, antiperiodic, dagger=True, dtype=dtype)
 
 
-def wilson_normal(psi, U, kappa, antiperiodic=True):
+def wilson_normal(psi, U, kappa, antiperiodic=True, dtype=np.complex128):
     """A psi = D^H D psi (two D-applies, Section 4)."""
-    return wilson_Ddag(wilson_D(psi, U, kappa, antiperiodic), U, kappa, antiperiodic)
+    return wilson_Ddag(wilson_D(psi, U, kappa, antiperiodic, dtype), U, kappa, antiperiodic, dtype)
 
 
 class WilsonNormalOp:
@@ -211,6 +225,18 @@ class WilsonNormalOp:
     def Hdag(self, v):
         return wilson_hop(self._field(v), self.U, self.antiperiodic, dagger=True).reshape(-1)
 
+    def single(self):
+        """A = D^H D applied in complex64 arithmetic (links rounded to complex64)."""
+        U32 = self.U.astype(np.complex64)
+
+        def apply(v):
+            v = np.asarray(v)
+            if v.ndim == 2:
+                return np.stack([apply(v[:, j]) for j in range(v.shape[1])], axis=1)
+            f = v.astype(np.complex64).reshape(self.dims + (4, 3))
+            return wilson_normal(f, U32, self.kappa, self.antiperiodic, np.complex64).reshape(-1)
+        return apply
+
 
 class Laplace2DOp:
     def __init__(self, nx, ny):
@@ -221,6 +247,10 @@ class Laplace2DOp:
     def __call__(self, v):
         return laplace2d_apply(v, self.nx, self.ny)
 
+    def single(self):
+        """The same stencil in float32 arithmetic."""
+        return lambda v: laplace2d_apply(v, self.nx, self.ny, dtype=np.float32)
+
 
 class DiagOp:
     def __init__(self, d):
@@ -230,6 +260,11 @@ class DiagOp:
 
     def __call__(self, v):
         return diag_apply(v, self.d)
+
+    def single(self):
+        """diag(d) in float32 arithmetic (d rounded to float32)."""
+        d32 = self.d.astype(np.float32)
+        return lambda v: diag_apply(np.asarray(v, dtype=np.float32), d32)
 
 
 class DenseOp:

@@ -100,6 +100,16 @@ def diag_example(n, gen):
     return np.sort(gen.uniform(0.0, 1.0, n))
 
 
+def related_rhs(u):
+    """Related right-hand sides from the columns u^1, u^2, ... (Example 3's recipe):
+    b^1 = u^1, b^j = b^{j-1} + 0.2^{j-1} u^j."""
+    B = np.zeros_like(u)
+    B[:, 0] = u[:, 0]
+    for j in range(1, u.shape[1]):
+        B[:, j] = B[:, j - 1] + 0.2 ** j * u[:, j]
+    return B
+
+
 # ----------------------------------------------------------------------------
 # workload presets
 # ----------------------------------------------------------------------------

@@ -1,0 +1,165 @@
+"""Pins of the mixed-precision oracle (oracle/mixed.py) against things other than itself.
+
+  * FP64 arrays, updates off: it is the FP64 oracle CG (cg.cg) iterate by
+    iterate, on the 32 x 32 Laplacian and the paper's Example 1 matrix.
+  * FP64 arrays, updates on: a reliable update that keeps the direction is an
+    exact identity, so the iterates equal plain CG's to rounding and the count
+    is the same within one.  A planted mistake in the update rule (restarting
+    the direction p at each update) breaks this, which the test shows on a
+    copy of the recursion with that mistake.
+  * Single precision: after every update the stored true residual equals b - A x
+    recomputed here with the FP64 operator, and the recursion had dropped by at
+    least 1e4 (norm) since the previous update; the final true residual is at
+    tol on Example 1 and on Wilson 4^4; on Wilson the count is within a few of
+    FP64 CG's, on Example 1 (isolated small eigenvalues) it is longer, as
+    finite-precision CG is.
+  * The seed phase with FP64 arrays reproduces the FP64 oracle seed; with a
+    single-precision basis, the basis just after a reorthogonalization event is
+    orthonormal to single precision (about 1e-6 in Frobenius norm) and the
+    three-term Lanczos relation holds to single precision.
+"""
+import numpy as np
+import pytest
+
+from oracle import mixed
+from oracle import operators as ops
+from oracle.cg import cg
+from oracle.seed import seed_lanczos, tridiag_dense
+from paper_0810_0330_amd import synth
+
+
+def _lap():
+    op = ops.Laplace2DOp(32, 32)
+    b = synth.real_gaussian(1024, 1, synth.rng(80, 1))[:, 0]
+    return op, b
+
+
+def _ex1():
+    d = synth.diag_example(5000, synth.rng(81, 0))
+    op = ops.DiagOp(d)
+    b = synth.real_gaussian(5000, 1, synth.rng(81, 1))[:, 0]
+    return op, b
+
+
+def _wilson4():
+    dims = (4, 4, 4, 4)
+    U = synth.su3_links(dims, synth.rng(82, 0))
+    op = ops.WilsonNormalOp(U, 0.12)
+    b = synth.z4_noise(op.n, 1, synth.rng(82, 1))[:, 0]
+    return op, b
+
+
+@pytest.mark.parametrize("case", [_lap, _ex1])
+def test_fp64_without_updates_is_plain_cg(case):
+    op, b = case()
+    h_ref, h = [], []
+    x_ref, it_ref, rel_ref = cg(op, b, tol=1e-10, history=h_ref)
+    x, it, rel = mixed.cg_mixed(op, op, b, tol=1e-10, lo=np.float64, updates=False, history=h)
+    assert it == it_ref
+    for a, c in zip(h, h_ref):
+        assert np.array_equal(a, c)
+    assert np.array_equal(x, x_ref) and rel == rel_ref
+
+
+@pytest.mark.parametrize("case", [_lap, _ex1])
+def test_fp64_updates_are_an_identity(case):
+    op, b = case()
+    h_ref, h, ev = [], [], []
+    _, it_ref, _ = cg(op, b, tol=1e-12, history=h_ref)
+    x, it, rel = mixed.cg_mixed(op, op, b, tol=1e-12, lo=np.float64, updates=True, history=h, events=ev)
+    assert len(ev) >= 2                       # at least two updates happened
+    assert abs(it - it_ref) <= 1 and rel <= 1e-12
+    xs = np.linalg.norm(h_ref[-1])
+    for k in range(min(len(h), len(h_ref)) - 5):
+        assert np.linalg.norm(h[k] - h_ref[k]) <= 1e-9 * xs, k
+
+
+def test_planted_update_mistake_is_caught():
+    # restarting the direction at an update (instead of keeping p) loses
+    # conjugacy: the iterates leave plain CG's by far more than rounding, so the
+    # identity test above would catch it
+    op, b = _lap()
+    h_ref, h = [], []
+    cg(op, b, tol=1e-12, history=h_ref)
+
+    def restarting(apply64, apply_lo, b, tol, maxit, history):
+        # the FP64 recursion with updates, and p = r after every update (the mistake)
+        x = np.zeros_like(b)
+        r = b - apply64(x)
+        rho = r @ r
+        p = r.copy()
+        rmax = rho
+        for _ in range(maxit):
+            q = apply_lo(p)
+            a = rho / (p @ q)
+            x = x + a * p
+            r = r - a * q
+            rn = r @ r
+            history.append(x.copy())
+            if rn <= tol * tol * (b @ b):
+                break
+            p = r + (rn / rho) * p
+            rho = rn
+            rmax = max(rmax, rho)
+            if rho < mixed.UPDATE_DROP2 * rmax:
+                r = b - apply64(x)
+                rho = r @ r
+                rmax = rho
+                p = r.copy()          # the mistake
+        return x
+    restarting(op, op, b, 1e-12, 100000, h)
+    xs = np.linalg.norm(h_ref[-1])
+    worst = max(np.linalg.norm(h[k] - h_ref[k]) for k in range(min(len(h), len(h_ref)) - 5))
+    assert worst > 1e-6 * xs
+
+
+@pytest.mark.parametrize("case", [_ex1, _wilson4])
+def test_single_precision_updates_and_final_residual(case):
+    op, b = case()
+    tol = 1e-8
+    ev = []
+    x, it, rel = mixed.cg_mixed(op, op.single(), b, tol=tol, events=ev)
+    _, it64, _ = cg(op, b, tol=tol)
+    assert rel <= tol
+    # A well-conditioned operator (Wilson at kappa 0.12) needs the FP64 count
+    # within a few; on Example 1 (small isolated eigenvalues) the single-precision
+    # recursion loses orthogonality sooner and takes longer (measured 653 vs 528),
+    # as finite-precision CG does
+    slack = 6 if isinstance(op, ops.WilsonNormalOp) else it64 // 2
+    assert it64 - 2 <= it <= it64 + slack, (it, it64)
+    assert len(ev) >= 1
+    for e in ev:
+        r = b - op(e["x"])
+        assert np.array_equal(r, e["r_true"])
+        assert e["rho_rec"] < mixed.UPDATE_DROP2 * e["rmax"]
+    # the error against the FP64 solution is at the level the residual fixes
+    xr = np.linalg.solve(np.diag(op.d), b) if isinstance(op, ops.DiagOp) else cg(op, b, tol=1e-13)[0]
+    assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-5
+
+
+def test_seed_fp64_arrays_reproduce_oracle_seed():
+    op, b = _lap()
+    ref = seed_lanczos(op, b[:, None], m=60, freq=10)
+    res = mixed.seed_lanczos_mixed(op, b, 60, 10, lo=np.float64)
+    assert res.m_done == ref.m_done == 60
+    np.testing.assert_allclose(res.alpha, ref.alpha, rtol=1e-12)
+    np.testing.assert_allclose(res.beta, ref.beta, rtol=1e-12)
+    assert np.abs(res.V - ref.V).max() <= 1e-10
+
+
+def test_seed_single_basis_orthogonality_and_relation():
+    op, b = _wilson4()
+    m, freq = 60, 20
+    res = mixed.seed_lanczos_mixed(op.single(), b, m, freq)
+    assert res.m_done == m and res.V.dtype == np.complex64
+    V = res.V.astype(np.complex128)
+    # just after the event at step 40 (column i-1 = 39 renormalised, v_41 formed from f)
+    Vk = V[:, :41]
+    err = np.linalg.norm(Vk.conj().T @ Vk - np.eye(41))
+    assert 1e-9 < err < 1e-5, err    # the single-precision floor: far above an FP64 basis's 1e-14
+    Vm = V[:, :m]
+    AV = np.stack([op(Vm[:, j]) for j in range(m)], axis=1)
+    T = tridiag_dense(res.alpha, res.beta, m)
+    R = AV - Vm @ T
+    R[:, m - 1] -= res.beta[m] * V[:, m]
+    assert np.abs(R).max() <= 1e-5 * 4.0
