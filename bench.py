@@ -183,11 +183,7 @@ def related_bench(args, w):
     inp = synth.make_inputs(w)
     op = api.Op.wilson(w.dims, torch.from_numpy(api.pack_links(inp["U"])).to(dev), w.kappa)
     k = args.related
-    u = synth.z4_noise(op.n, k, synth.rng(w.config_id, 6))
-    Bn = np.zeros_like(u)
-    Bn[:, 0] = u[:, 0]
-    for j in range(1, k):
-        Bn[:, j] = Bn[:, j - 1] + 0.2 ** j * u[:, j]
+    Bn = synth.related_rhs(synth.z4_noise(op.n, k, synth.rng(w.config_id, 6)))
     B = torch.from_numpy(api.pack_field(np.ascontiguousarray(Bn.T))).to(dev)
     mixed = w.precision == "mixed"
     api.related_rhs_solve(op, B[:2], 50, 10, w.tol, mixed=mixed)  # warm: tuning, allocations

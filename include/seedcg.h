@@ -157,10 +157,16 @@ sc_status sc_wilson_dslash(const sc_op* op, sc_dtype dtype, int which, const voi
  * blocks of 2 and 4 consecutive z-planes, whose z neighbours inside the
  * block are staged in LDS too; where the planes do not fit LDS (4 planes of
  * 2 columns, FP64 beyond 2 planes) or do not divide Z, the launch uses the
- * next smaller plane count.
+ * next smaller plane count.  69..80: FP32 D and D^H passes on lattices with
+ * X = Y = 16 (and |kappa| >= 1e-6), for k > 1: one block per xy-plane and
+ * column group marching t, x neighbours exchanged between lanes (DPP), y
+ * neighbours through LDS as half spinors already multiplied by the source
+ * site's link; 69 + 6 * (c - 1) + 3 * o + {0, 1, 2} for c = 1, 2 columns
+ * per thread, segments of {4, 8, 16} slices, o = 0: the planes of a segment
+ * are consecutive work items, 1: the column groups of a plane are.
  * us (host, SC_WILSON_VARIANTS floats): measured microseconds per pass of each
  * candidate (-1 if not run). */
-#define SC_WILSON_VARIANTS 69
+#define SC_WILSON_VARIANTS 81
 sc_status sc_wilson_tune_info(const sc_op* op, sc_dtype dtype, int k, int* variant, float* us);
 
 /* Pin the stencil launch shape for (this op's lattice, dtype, k) instead of
@@ -184,7 +190,8 @@ typedef enum {
     SC_CALL_INDEFINITE = 9
 } sc_call;
 
-/* Bytes of `work` needed by a call.  k: right-hand sides per call; m: basis
+/* Bytes of `work` needed by a call.  k: right-hand sides per call (a call
+ * with more columns than the k it was sized for needs a new query); m: basis
  * size (seed, project); dtype: vector dtype of the call (for SC_CALL_CG pass
  * the op dtype and set k; the mixed-precision solver needs the same query with
  * the single-precision dtype).  For SC_CALL_PROJECT op may be NULL when n is

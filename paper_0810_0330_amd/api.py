@@ -143,7 +143,7 @@ def release_workspace():
 
 
 # ----------------------------------------------------------------------------- timing
-WILSON_VARIANTS = 69  # SC_WILSON_VARIANTS: tiled, t-march (1, 2, 4 planes per block), direction-split
+WILSON_VARIANTS = 81  # SC_WILSON_VARIANTS: tiled, t-march (1, 2, 4 planes per block), direction-split, DPP
 
 TIMER_CLASSES = {0: "wilson_f32_k1", 1: "wilson_f64_k1", 2: "gemm_cn", 3: "gemm_nn", 4: "wilson_f32_kn",
                  5: "wilson_f64_kn"}
@@ -371,8 +371,9 @@ def project(basis, R0, X0=None, m=None):
     return X
 
 
-def solve_cg(op, B, tol, X0=None, mixed=False, maxit=100000):
-    """CG on the rows of B from X0; returns (X, iters list, true relative residuals list)."""
+def solve_cg(op, B, tol, X0=None, mixed=False, maxit=100000, with_status=False):
+    """CG on the rows of B from X0; returns (X, iters list, true relative residuals list)
+    (and the status code, SC_OK or SC_NOT_CONVERGED, when with_status)."""
     B = op._vec(B, op.dtype)
     X = torch.zeros_like(B) if X0 is None else op._vec(X0, op.dtype).clone()
     k = B.shape[0]
@@ -382,9 +383,9 @@ def solve_cg(op, B, tol, X0=None, mixed=False, maxit=100000):
     w = _work(nb.value, op.device)
     iters = (ctypes.c_int * k)()
     rel = (ctypes.c_double * k)()
-    _check(lib().sc_solve_cg(op.handle, 1 if mixed else 0, _ptr(B), op.n, _ptr(X), op.n, k, float(tol), int(maxit),
-                             iters, rel, _ptr(w), w.numel(), _stream()), ok=(0, 1))
-    return X, list(iters), list(rel)
+    st = _check(lib().sc_solve_cg(op.handle, 1 if mixed else 0, _ptr(B), op.n, _ptr(X), op.n, k, float(tol),
+                                  int(maxit), iters, rel, _ptr(w), w.numel(), _stream()), ok=(0, 1))
+    return (X, list(iters), list(rel), st) if with_status else (X, list(iters), list(rel))
 
 
 def seeded_solve(op, B, m, freq, tol, mixed=False, maxit=100000):
@@ -443,8 +444,9 @@ def single_seed_solve(op, B, m, freq, tol, mixed=False, maxit=100000):
     return {"X": X, "iters": list(iters), "relres": list(rel), "m_done": md.value, "status": st}
 
 
-def solve_minres(op, B, tol, X0=None, maxit=100000):
-    """MINRES (FP64) on the rows of B from X0 (Hermitian op, e.g. Op.wilson_g5); returns (X, iters, relres)."""
+def solve_minres(op, B, tol, X0=None, maxit=100000, with_status=False):
+    """MINRES (FP64) on the rows of B from X0 (Hermitian op, e.g. Op.wilson_g5); returns (X, iters, relres)
+    (and the status code when with_status)."""
     B = op._vec(B, op.dtype)
     X = torch.zeros_like(B) if X0 is None else op._vec(X0, op.dtype).clone()
     k = B.shape[0]
@@ -456,7 +458,7 @@ def solve_minres(op, B, tol, X0=None, maxit=100000):
     st = lib().sc_solve_minres(op.handle, _ptr(B), op.n, _ptr(X), op.n, k, float(tol), int(maxit), iters, rel,
                                _ptr(w), w.numel(), _stream())
     _check(st, ok=(0, 1))
-    return X, list(iters), list(rel)
+    return (X, list(iters), list(rel), st) if with_status else (X, list(iters), list(rel))
 
 
 def indefinite_solve(op, B, m, freq, tol, maxit=100000):

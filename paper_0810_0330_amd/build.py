@@ -1,34 +1,59 @@
 """Build the HIP library libseedcg.so in-tree for gfx950 with hipcc.
 
+Each source is compiled to an object of its own (in parallel), then the
+objects are linked into one shared library.
+
 Usage: python -m paper_0810_0330_amd.build  (or call build()).
 """
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libseedcg.so")
-SOURCES = ["abi.hip", "k_stencil.hip", "k_blas.hip", "k_tsgemm.hip", "seed.hip", "cg.hip", "timer.hip", "grad.hip", "batch.hip", "related.hip", "multiseed.hip", "seeded.hip", "minres.hip", "indefinite.hip"]
+# every translation unit of the library (the largest first, so the parallel build ends sooner)
+SOURCES = sorted((f for f in os.listdir(CSRC) if f.endswith(".hip")),
+                 key=lambda f: -os.path.getsize(os.path.join(CSRC, f)))
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep packed FP32 instructions out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
 
 
-def build(verbose=False):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+def _compile(src):
+    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC] + FLAGS + ["-c", "-o", obj, os.path.join(CSRC, src)]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    return src, obj, cmd, res
+
+
+def build(verbose=False, jobs=None):
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), max(1, min(16, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(_compile, SOURCES))
+    objs = []
+    for src, obj, cmd, res in results:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError(f"hipcc failed on {src}")
+        objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + srcs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libseedcg.so")
+        raise RuntimeError("hipcc failed linking libseedcg.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,6 +1,7 @@
 // C ABI entry points (declared in include/seedcg.h): argument validation,
 // workspace queries and dispatch to the drivers.  Nothing throws across the
 // boundary; every failure is a status code plus a message in sc_last_error().
+#include <atomic>
 #include <cmath>
 #include <new>
 
@@ -24,6 +25,13 @@ sc_status batch_solve(int nsys, sc_batch_system* sys, void* work, size_t work_by
 
 static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+static std::atomic<uint64_t> g_op_gen{0};
+static sc_op* new_op() {
+    sc_op* op = new sc_op();
+    op->gen = ++g_op_gen;
+    return op;
+}
+
 // the op's precision or its single counterpart
 static bool dtype_ok_for(const sc_op* op, sc_dtype d) { return d == op->dtype || d == single_of(op->dtype); }
 
@@ -31,10 +39,14 @@ static size_t apply_workspace(const sc_op* op, int k, sc_dtype d) {
     return (size_t)std::max<int64_t>(op_apply_tmp_elems(op), 0) * dtype_bytes(d) * (size_t)std::max(k, 1) + 256;
 }
 
-size_t project_workspace(int64_t n, int m, bool cpl) {
+// columns of one pass of the projection (k right-hand sides go in groups of at most kMaxCols)
+static int project_group(int k) { return std::max(1, std::min(k, kMaxCols)); }
+
+size_t project_workspace(int64_t n, int m, int k, bool cpl) {
+    const int N = project_group(k);
     Carver c(nullptr, 0);
-    c.take<double>((size_t)m * kMaxCols * 2);
-    c.take<double>(gemm_cn_part_doubles(n, m, kMaxCols, cpl));
+    c.take<double>((size_t)m * N * 2);
+    c.take<double>(gemm_cn_part_doubles(n, m, N, cpl));
     c.take<double>((size_t)m * 2);
     return c.off + 256;
 }
@@ -44,17 +56,18 @@ sc_status project_impl(int64_t n, const void* V, int64_t ldv, sc_dtype vdt, int 
                               int64_t ldx, void* work, size_t work_bytes, hipStream_t s) {
     const bool cpl = is_complex(vdt);
     const bool vs = is_single(vdt);
+    const int N = project_group(k);
     Carver c(work, work_bytes);
-    double* G = c.take<double>((size_t)m * kMaxCols * 2);
-    double* part = c.take<double>(gemm_cn_part_doubles(n, m, kMaxCols, cpl));
+    double* G = c.take<double>((size_t)m * N * 2);
+    double* part = c.take<double>(gemm_cn_part_doubles(n, m, N, cpl));
     double* trid = c.take<double>((size_t)m * 2);
     if (!c.ok()) {
         set_error("project: work buffer too small");
         return SC_ERR_WORKSPACE;
     }
     const size_t eb = dtype_bytes(xdt);
-    for (int j0 = 0; j0 < k; j0 += kMaxCols) {
-        const int nb = std::min(kMaxCols, k - j0);
+    for (int j0 = 0; j0 < k; j0 += N) {
+        const int nb = std::min(N, k - j0);
         ColPtrs<const void> rc{};
         ColPtrs<void> xc{};
         for (int j = 0; j < nb; ++j) {
@@ -94,7 +107,7 @@ sc_status sc_op_laplace2d(int nx, int ny, sc_op** out) {
     SC_GUARD_BEGIN
     SC_ARG(out, "out is NULL");
     SC_ARG(nx >= 1 && ny >= 1, "nx and ny must be >= 1");
-    sc_op* op = new sc_op();
+    sc_op* op = new_op();
     op->kind = SC_OPK_LAPLACE2D;
     op->nx = nx;
     op->ny = ny;
@@ -110,7 +123,7 @@ sc_status sc_op_diag(const double* d_dev, int64_t n, sc_op** out) {
     SC_ARG(out, "out is NULL");
     SC_ARG(d_dev && aligned(d_dev, 8), "d_dev is NULL or misaligned");
     SC_ARG(n >= 1, "n must be >= 1");
-    sc_op* op = new sc_op();
+    sc_op* op = new_op();
     op->kind = SC_OPK_DIAG;
     op->d = d_dev;
     op->n = n;
@@ -131,7 +144,7 @@ sc_status sc_op_wilson_normal(const int dims[4], const void* U64_dev, const void
     SC_ARG(std::isfinite(kappa), "kappa must be finite");
     const int64_t vol = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
     SC_ARG(vol * 36 < (int64_t(1) << 31), "lattice too large: 32-bit site indexing needs 36 * volume < 2^31");
-    sc_op* op = new sc_op();
+    sc_op* op = new_op();
     op->kind = SC_OPK_WILSON;
     for (int i = 0; i < 4; ++i) op->dims[i] = dims[i];
     op->vol = vol;
@@ -157,6 +170,7 @@ sc_status sc_op_wilson_g5(const int dims[4], const void* U64_dev, const void* U3
 
 sc_status sc_op_destroy(sc_op* op) {
     SC_GUARD_BEGIN
+    if (op) batch_forget_op(op);
     delete op;
     return SC_OK;
     SC_GUARD_END
@@ -187,7 +201,7 @@ sc_status sc_workspace_size(const sc_op* op, int call, int k, int m, sc_dtype dt
         case SC_CALL_PROJECT: {
             int64_t n = op ? op->n : (int64_t)*bytes;
             SC_ARG(n >= 1, "project size query needs an op or n in *bytes");
-            *bytes = project_workspace(n, std::max(m, 1), is_complex(dtype));
+            *bytes = project_workspace(n, std::max(m, 1), k, is_complex(dtype));
             return SC_OK;
         }
         case SC_CALL_CG:
@@ -299,7 +313,7 @@ sc_status sc_project(int64_t n, const void* V_dev, int64_t ldv, sc_dtype v_dtype
                aligned(X_dev, dtype_bytes(vec_dtype)),
            "misaligned device pointer");
     SC_ARG(ldv >= n && ldr >= n && ldx >= n, "leading dimension smaller than n");
-    if (work_bytes < project_workspace(n, m, is_complex(vec_dtype)) - 256) {
+    if (work_bytes < project_workspace(n, m, k, is_complex(vec_dtype)) - 256) {
         set_error("project: work buffer too small");
         return SC_ERR_WORKSPACE;
     }

@@ -7,11 +7,15 @@
 // join back.  One graph launch then advances every lattice concurrently: the
 // small lattices, which cannot fill the GPU alone, overlap with the large
 // ones.  The instantiated graph is cached and replayed when the same argument
-// set is solved again (a graph bakes in its pointers and sizes).
+// set is solved again: a graph bakes in its pointers, sizes, operator
+// parameters (kappa, links, lattice) and stencil launch shapes, so the cache
+// key holds all of them and each op's generation number, and destroying an
+// op drops the graphs recorded for it.
 //
 // The rest is data dependent: each system's final seed state is read, x^1
 // formed, the other right-hand sides projected, and every column finished
 // with CG, one host thread and one stream per system.
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <thread>
@@ -49,7 +53,7 @@ std::vector<SysPlan> plan_batch(int nsys, const sc_batch_system* sys, size_t* to
         q.seed_bytes = seed_workspace(op, sys[i].m, single);
         off = align256(off + q.seed_bytes);
         q.proj_off = off;
-        q.proj_bytes = project_workspace(op->n, sys[i].m, cpl);
+        q.proj_bytes = project_workspace(op->n, sys[i].m, sys[i].k - 1, cpl);
         off = align256(off + q.proj_bytes);
         q.cg_off = off;
         q.cg_bytes = cg_workspace(op, sys[i].k, single);
@@ -67,6 +71,7 @@ struct GraphKey {
 struct GraphEntry {
     GraphKey key;
     hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> gens;  // generations of the ops the graph was recorded for
 };
 std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;  // most recent last
@@ -82,7 +87,27 @@ GraphKey make_key(int nsys, const sc_batch_system* sys, const void* work, hipStr
     put(&work, sizeof work);
     put(&s, sizeof s);
     for (int i = 0; i < nsys; ++i) {
-        put(&sys[i].op, sizeof sys[i].op);
+        const sc_op* op = sys[i].op;
+        put(&op, sizeof op);
+        put(&op->gen, sizeof op->gen);
+        put(&op->kind, sizeof op->kind);
+        put(&op->n, sizeof op->n);
+        put(&op->dtype, sizeof op->dtype);
+        put(&op->nx, sizeof op->nx);
+        put(&op->ny, sizeof op->ny);
+        put(&op->d, sizeof op->d);
+        put(op->dims, sizeof op->dims);
+        put(&op->U64, sizeof op->U64);
+        put(&op->U32, sizeof op->U32);
+        put(&op->kappa, sizeof op->kappa);
+        put(&op->antiperiodic, sizeof op->antiperiodic);
+        // the stencil shape the seed phase's one-column passes were tuned to
+        int variant = -1;
+        if (has_links(op)) {
+            float us[SC_WILSON_VARIANTS];
+            (void)wilson_tune_query(op, sys[i].mixed != 0, 1, &variant, us);
+        }
+        put(&variant, sizeof variant);
         put(&sys[i].B_dev, sizeof sys[i].B_dev);
         put(&sys[i].ldb, sizeof sys[i].ldb);
         put(&sys[i].X_dev, sizeof sys[i].X_dev);
@@ -96,6 +121,19 @@ GraphKey make_key(int nsys, const sc_batch_system* sys, const void* work, hipStr
 }
 
 }  // namespace
+
+void batch_forget_op(const sc_op* op) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (size_t j = 0; j < g_graphs.size();) {
+        const auto& g = g_graphs[j].gens;
+        if (std::find(g.begin(), g.end(), op->gen) != g.end()) {
+            (void)hipGraphExecDestroy(g_graphs[j].exec);
+            g_graphs.erase(g_graphs.begin() + j);
+        } else {
+            ++j;
+        }
+    }
+}
 
 size_t batch_workspace(int nsys, const sc_batch_system* sys) {
     size_t total = 0;
@@ -217,7 +255,9 @@ sc_status batch_solve(int nsys, sc_batch_system* sys, void* work, size_t work_by
             (void)hipGraphExecDestroy(g_graphs.front().exec);
             g_graphs.erase(g_graphs.begin());
         }
-        g_graphs.push_back({key, exec});
+        std::vector<uint64_t> gens;
+        for (int i = 0; i < nsys; ++i) gens.push_back(sys[i].op->gen);
+        g_graphs.push_back({key, exec, gens});
     }
     if (hipGraphLaunch(exec, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
         cleanup();

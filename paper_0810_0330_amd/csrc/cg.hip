@@ -24,9 +24,22 @@
 // iterating meanwhile, so no column idles; p is kept and CG continues with
 // the true residual), and when the FP32 residual reaches tol (the column
 // stops; CG restarts from the true residual if it is still above tol).
+//
+// A column whose residual has stalled stops early and is reported as not
+// converged: its recursive residual norm has not fallen 1% below its smallest
+// value within kStallWindow iterations (a breakdown of the recurrence, an
+// operator that is not HPD, an inconsistent system), or,
+// in mixed precision, a FP64 true residual that has not halved over
+// kStallUpdates successive reliable updates (tol below what the FP64 residual
+// can reach).  Its iteration limit is lowered to the count reached, so no
+// restart takes it up again.  A reliable update whose true residual has not
+// halved also restarts the direction (p = r): the kept p belongs to a
+// recursion that has left the true residual behind, and continuing with it
+// can diverge.
 #include "sc_internal.h"
 
 #include <cmath>
+#include <limits>
 #include <vector>
 
 namespace sc {
@@ -36,6 +49,8 @@ namespace sc {
 // The FP32 recurrence then still sits about three orders of magnitude above
 // its rounding floor (single precision relative to that largest norm).
 constexpr double kRelUpdate2 = 1e-8;
+constexpr int kStallWindow = 1000;
+constexpr int kStallUpdates = 3;
 
 __global__ void k_cg_setup(CGCol* st, const double* rho, const double* bn, int k, double tol, int maxit, int first) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -371,6 +386,15 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
     std::vector<double> chk_rho(k, 0.0);
     std::vector<int> chk_it(k, -1);
     int cur = 0;  // index of the state copy the next iteration reads
+    // stall detection (see the file header)
+    constexpr double kInf = std::numeric_limits<double>::infinity();
+    std::vector<double> min_rho(k, kInf), best_true(k, kInf);
+    std::vector<int> it_min(k, 0), nstall(k, 0);
+    auto stop_stalled = [&](int j) {
+        hst[j].active = 0;
+        hst[j].flag = 0;
+        hst[j].maxit = hst[j].iters;
+    };
 
     SC_TRY(dot(0, B, ldb2, 0, B, ldb2, N2, k, w.bn, w.part, nullptr, s));
     // r = b - A x; rho = ||r||^2
@@ -437,7 +461,17 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
             any = false;
             std::vector<int> upd;
             int need = 0;  // iterations the slowest active column still needs, as estimated
+            bool dirty = false;  // host-side state changes to copy back
             for (int j = 0; j < k; ++j) {
+                if (hst[j].active) {
+                    if (hst[j].rho < 0.98 * min_rho[j]) {
+                        min_rho[j] = hst[j].rho;
+                        it_min[j] = hst[j].iters;
+                    } else if (hst[j].iters - it_min[j] >= kStallWindow) {
+                        stop_stalled(j);
+                        dirty = true;
+                    }
+                }
                 any |= hst[j].active != 0;
                 if (mixed && hst[j].flag != 0 && hst[j].iters < hst[j].maxit) upd.push_back(j);
                 if (hst[j].active) {
@@ -453,6 +487,10 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
                 chk_it[j] = hst[j].iters;
             }
             chunk = need > 0 ? need : kChunk;
+            if (dirty && upd.empty()) {
+                SC_HIP(hipMemcpyAsync(w.st[cur], hst.data(), sizeof(CGCol) * k, hipMemcpyHostToDevice, s));
+                SC_HIP(hipStreamSynchronize(s));
+            }
             if (!upd.empty()) {
                 // reliable update of the flagged columns (batched over the list):
                 // x64 += xs; xs = 0; r64 = b - A64 x64; r = r64; then the direction
@@ -476,22 +514,37 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
                 std::vector<int> dl;
                 std::vector<double> db;
                 for (int c = 0; c < nu; ++c) {
-                    CGCol& cc = hst[upd[c]];
+                    const int j = upd[c];
+                    CGCol& cc = hst[j];
                     const double rr = hrr[c];
                     const bool done = !(rr > cc.tol2);
-                    if (!done && cc.flag == 1) {
-                        // the FP32 recurrence reached tol but the true residual did not:
-                        // restart the direction from the true residual
-                        dl.push_back(upd[c]);
+                    // the true residual should have fallen with the recursive one; if
+                    // it has not halved since the best one seen, the FP64 residual is
+                    // at its rounding floor and the kept direction no longer matches it
+                    const bool improved = rr < 0.5 * best_true[j];
+                    if (improved) {
+                        best_true[j] = rr;
+                        nstall[j] = 0;
+                    } else if (!done) {
+                        ++nstall[j];
+                    }
+                    if (!done && (cc.flag == 1 || !improved)) {
+                        // the FP32 recurrence reached tol but the true residual did not,
+                        // or the true residual stopped falling: restart the direction
+                        // from the true residual
+                        dl.push_back(j);
                         db.push_back(0.0);
                     }
-                    // flag 2: p was formed from the recursive residual and is kept;
-                    // CG continues from the true residual (rho = ||r_true||^2)
+                    // otherwise (flag 2) p was formed from the recursive residual and is
+                    // kept; CG continues from the true residual (rho = ||r_true||^2)
                     cc.rho = rr;
                     cc.rho_prev = rr;
                     cc.rmax2 = rr;
                     cc.active = done ? 0 : 1;
                     cc.flag = 0;
+                    min_rho[j] = rr;
+                    it_min[j] = cc.iters;
+                    if (!done && nstall[j] >= kStallUpdates) stop_stalled(j);
                     any |= cc.active != 0;
                 }
                 if (!dl.empty()) {
@@ -524,7 +577,7 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
             const double bn = hst[j].bnorm2;
             relres[j] = bn > 0.0 ? std::sqrt(hrr[j] / bn) : 0.0;
             iters[j] = hst[j].iters;
-            if (bn > 0.0 && !(relres[j] <= tol) && hst[j].iters < maxit) again = true;
+            if (bn > 0.0 && !(relres[j] <= tol) && hst[j].iters < hst[j].maxit) again = true;
         }
         if (!again || restarts >= 5) break;
         ++restarts;
@@ -564,7 +617,8 @@ sc_status solve_cg(const sc_op* op, int mixed, const void* B, int64_t ldb, void*
         if (vec) SC_TRY((cg_run<double, true>(op, false, (const double*)B, ldb, (double*)X, ldx, k, tol, maxit, iters, relres, w, s, &result)));
         else SC_TRY((cg_run<double, false>(op, false, (const double*)B, ldb, (double*)X, ldx, k, tol, maxit, iters, relres, w, s, &result)));
     }
-    if (result == SC_NOT_CONVERGED) set_error("solve_cg: some right-hand side is above tol at maxit");
+    if (result == SC_NOT_CONVERGED)
+        set_error("solve_cg: some right-hand side is above tol (iteration limit reached or residual stalled)");
     return result;
 }
 

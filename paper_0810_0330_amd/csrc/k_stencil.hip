@@ -2,6 +2,7 @@
 // stencil D = 1 - kappa H, its adjoint, and the hopping term alone, in several
 // launch shapes chosen by an autotuner.  The hop arithmetic is in wilson_dev.h.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -98,6 +99,12 @@ struct TmEpi {
     void* r;
     int64_t ldr;  // reals
 };
+
+}  // namespace sc
+
+#include "wilson_tx.h"
+
+namespace sc {
 
 
 // One output element of a tiled pass under epilogue EPI (see above): stored to
@@ -699,8 +706,55 @@ constexpr int WV_TILED = kOrders * WS_COUNT * kChunks;
 constexpr int WV_TMARCH = 12;
 constexpr int WV_DIR = WV_TILED + WV_TMARCH;  // the direction-split form
 constexpr int WV_TM2 = WV_DIR + 1;            // t-march, 2 and 4 planes per block
-constexpr int WV_COUNT = WV_TM2 + 2 * WV_TMARCH;
+constexpr int WV_TX = WV_TM2 + 2 * WV_TMARCH;  // one column per thread, x hops by DPP (FP32, X = Y = 16)
+constexpr int WV_NTX = 12;
+constexpr int WV_COUNT = WV_TX + WV_NTX;
 static_assert(WV_COUNT == SC_WILSON_VARIANTS, "variant count must match the header");
+
+// The DPP form (wilson_tx.h): ids WV_TX + 6 * (nc - 1) + 3 * order + {0, 1, 2}
+// for nc = 1, 2 columns per thread and segments of {4, 8, 16} time slices,
+// order 0: the planes of a segment are consecutive work items, 1: the column
+// groups of a plane are.  FP32 D and D^H passes only, on
+// lattices with X = Y = 16 (an x-row is a 16-lane DPP row, four y-rows a
+// wave); its accumulator starts at -psi / kappa, so kappa must not be tiny.
+static bool is_tx(int v) { return v >= WV_TX && v < WV_TX + WV_NTX; }
+static bool tx_ok(const sc_op* op) {
+    return op->dims[0] == 16 && op->dims[1] == 16 && std::fabs(op->kappa) >= 1e-6 &&
+           288 * op->vol < (int64_t(1) << 31);  // FP32 links below 2^31 bytes (32-bit buffer offsets)
+}
+static int tx_tlen(const sc_op* op, int v) {
+    const int i = (v - WV_TX) % 3;
+    return std::max(1, std::min(i == 0 ? 4 : (i == 1 ? 8 : 16), op->dims[3]));
+}
+static int tx_nc(int v) { return (v - WV_TX) >= 6 ? 2 : 1; }
+static int tx_parts(const sc_op* op, int v) { return op->dims[2] * ((op->dims[3] + tx_tlen(op, v) - 1) / tx_tlen(op, v)); }
+
+static void tx_launch(const sc_op* op, int v, bool dag, int epi, const float* X, int64_t ldx, float* Y, int64_t ldy,
+                      int k, const float* U, const TmEpi& e, hipStream_t s) {
+    Geom g{op->dims[0], op->dims[1], op->dims[2], op->dims[3], op->vol};
+    const int tlen = tx_tlen(op, v);
+    const int nseg = (g.T + tlen - 1) / tlen;
+    const int ncg = (k + tx_nc(v) - 1) / tx_nc(v);
+    const int per_xcd = (ncg * g.Z * nseg + kXcd - 1) / kXcd;
+    const dim3 grid((unsigned)(per_xcd * kXcd)), blk(kBlock);
+    const float kap = (float)op->kappa, ts = op->antiperiodic ? -1.0f : 1.0f;
+    const int cgm = ((v - WV_TX) % 6) >= 3 ? 1 : 0;
+#define SC_TX(DAG, EPI_, NC_)                                                                                   \
+    SC_TLAUNCH((k_wilson_tx<DAG, EPI_, NC_>), grid, blk, 0, s, Y, 2 * ldy, X, 2 * ldx, U, g, kap, ts, k, nseg, \
+               tlen, per_xcd, cgm, e)
+#define SC_TXE(NC_)                                 \
+    if (epi == TM_NORM) SC_TX(false, TM_NORM, NC_); \
+    else if (epi == TM_CG) SC_TX(true, TM_CG, NC_); \
+    else if (dag) SC_TX(true, TM_PLAIN, NC_);       \
+    else SC_TX(false, TM_PLAIN, NC_);
+    if (tx_nc(v) == 1) {
+        SC_TXE(1)
+    } else {
+        SC_TXE(2)
+    }
+#undef SC_TXE
+#undef SC_TX
+}
 
 static int chunk_groups(int chunk, int ncg) {
     const int g = chunk == 0 ? ncg : (chunk == 1 ? 1 : (chunk == 2 ? 2 : 4));
@@ -758,7 +812,7 @@ struct TmShape {
     int tlen, nc, nz;
     bool cgminor;
 };
-static bool is_tmarch(int v) { return (v >= WV_TILED && v < WV_DIR) || (v >= WV_TM2 && v < WV_COUNT); }
+static bool is_tmarch(int v) { return (v >= WV_TILED && v < WV_DIR) || (v >= WV_TM2 && v < WV_TX); }
 static TmShape tm_shape(int v, bool single, int Z) {
     const int i = v < WV_DIR ? v - WV_TILED : (v - WV_TM2) % WV_TMARCH;
     TmShape t;
@@ -889,6 +943,15 @@ static int default_variant(bool single, int k) {
 template <typename R>
 static void wilson_launch_variant(int v, const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k,
                                   const R* U, hipStream_t s) {
+    if (is_tx(v)) {
+        if constexpr (sizeof(R) == 4) {
+            if (tx_ok(op) && which < 2) {
+                tx_launch(op, v, which == 1, TM_PLAIN, X, ldx, Y, ldy, k, U, TmEpi{}, s);
+                return;
+            }
+        }
+        v = default_variant(sizeof(R) == 4, k);  // H passes, FP64 or another lattice
+    }
     if (v == WV_DIR) {
         wilson_launch_dir<R>(op, which, X, ldx, Y, ldy, k, U, s);
         return;
@@ -911,6 +974,7 @@ static void wilson_launch_variant(int v, const sc_op* op, int which, const R* X,
 
 // variants worth timing for this lattice, precision and column count
 static bool variant_applies(const sc_op* op, int v, bool single, int k) {
+    if (is_tx(v)) return single && tx_ok(op) && k > 1 && !(tx_nc(v) == 2 && k == 2 && ((v - WV_TX) % 6) >= 3);
     if (v == WV_DIR) return k <= 4;
     if (is_tmarch(v)) {
         const int i = v < WV_DIR ? v - WV_TILED : (v - WV_TM2) % WV_TMARCH;
@@ -1023,6 +1087,10 @@ sc_status wilson_tune_pin(const sc_op* op, bool single, int k, int variant) {
         set_error("wilson_tune_set: the t-march shapes need an xy-plane of exactly 256 sites");
         return SC_ERR_ARG;
     }
+    if (is_tx(variant) && !(single && tx_ok(op))) {
+        set_error("wilson_tune_set: the DPP shapes need FP32, X = Y = 16 and |kappa| >= 1e-6");
+        return SC_ERR_ARG;
+    }
     TuneKey key{{op->dims[0], op->dims[1], op->dims[2], op->dims[3]}, single ? 1 : 0, k};
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (variant < 0) {
@@ -1071,6 +1139,18 @@ static sc_status wilson_d_norm(const sc_op* op, const R* X, int64_t ldx, R* Y, i
                                double* part, int max_parts, int* G, hipStream_t s) {
     *G = 0;
     const int v = choose_variant<R>(op, 0, X, ldx, Y, ldy, k, U, s);
+    if constexpr (sizeof(R) == 4) {
+        if (is_tx(v) && tx_ok(op) && tx_parts(op, v) <= max_parts) {
+            const double bytes = (48.0 * k + 72.0) * 4.0 * (double)op->vol;
+            TimerScope ts_(k == 1 ? TC_WILSON_F32 : TC_WILSON_F32_K, s, bytes, 1368.0 * k * (double)op->vol);
+            TmEpi e{};
+            e.part = part;
+            tx_launch(op, v, false, TM_NORM, X, ldx, Y, ldy, k, U, e, s);
+            SC_LAUNCH_CHECK();
+            *G = tx_parts(op, v);
+            return SC_OK;
+        }
+    }
     if (!is_tmarch(v) || !tmarch_ok(op)) return wilson_launch<R>(op, 0, X, ldx, Y, ldy, k, U, s);
     const TmShape t = tm_shape(v, sizeof(R) == 4, op->dims[2]);
     const int tlen = std::max(1, std::min(t.tlen, op->dims[3]));
@@ -1095,6 +1175,34 @@ static sc_status wilson_cg_fused_t(const sc_op* op, const R* p, R* tmp, int k, c
     // the t-march shapes (partials per plane and segment) and the tiled ones
     // (partials per 256-site tile); the direction-split shape has no epilogues
     const int v = choose_variant<R>(op, 0, p, op->n, tmp, op->n, k, U, s);
+    if constexpr (sizeof(R) == 4) {
+        if (is_tx(v) && tx_ok(op)) {
+            const int parts = tx_parts(op, v);
+            if (parts > max_parts) return SC_OK;
+            const int cls = k == 1 ? TC_WILSON_F32 : TC_WILSON_F32_K;
+            {
+                TimerScope ts_(cls, s, (48.0 * k + 72.0) * 4.0 * (double)op->vol, 1368.0 * k * (double)op->vol);
+                TmEpi e{};
+                e.part = part_pq;
+                e.st = st;  // columns no longer active are skipped
+                tx_launch(op, v, false, TM_NORM, p, op->n, tmp, op->n, k, U, e, s);
+                SC_LAUNCH_CHECK();
+            }
+            {
+                TimerScope ts_(cls, s, (72.0 * k + 72.0) * 4.0 * (double)op->vol, 1368.0 * k * (double)op->vol);
+                TmEpi e{};
+                e.part = part_rr;
+                e.st = st;
+                e.pq = part_pq;
+                e.r = r;
+                e.ldr = 2 * ldr;
+                tx_launch(op, v, true, TM_CG, tmp, op->n, tmp, op->n, k, U, e, s);
+                SC_LAUNCH_CHECK();
+            }
+            *G = parts;
+            return SC_OK;
+        }
+    }
     const bool tm = is_tmarch(v) && tmarch_ok(op);
     if (!tm && (v == WV_DIR || is_tmarch(v))) return SC_OK;
     TmShape t{};

@@ -16,12 +16,20 @@
 // It stops when |phibar| <= tol ||b||; the start (r = b - A x, beta_1 = ||r||)
 // is also the true-residual check, so a finished batch is started again and
 // the columns whose true residual is at tol stay inactive (at most 5 restarts,
-// as the CG does).
+// as the CG does).  A column whose rotated residual norm has not fallen by 1%
+// within kStallWindow iterations (tol below the attainable residual) stops
+// and is reported as not converged; its iteration limit is lowered to the
+// count reached, so no restart takes it up again.
 #include "sc_internal.h"
+
+#include <cmath>
+#include <vector>
 
 namespace sc {
 
 namespace {
+
+constexpr int kStallWindow = 1000;
 
 struct MRCol {
     double beta;    // beta_k (the norm that scales v_k)
@@ -239,6 +247,8 @@ sc_status minres_solve(const sc_op* op, const void* B, int64_t ldb, void* X, int
     int vi = 1;    // w.v[vi] is v_k, w.v[1 - vi] is v_{k-1}
     int wi = 1;    // w.w[wi] is w_{k-1}, w.w[1 - wi] is w_{k-2}
     std::vector<MRCol> hst(k);
+    std::vector<double> mark(k, 0.0);  // rotated residual at the last 1% decrease
+    std::vector<int> it_mark(k, 0);
 
     hipLaunchKernelGGL(k_mr_norm, grid, blk, 0, s, (const double*)B, ldb2, N2, w.part_a);
     SC_LAUNCH_CHECK();
@@ -258,6 +268,11 @@ sc_status minres_solve(const sc_op* op, const void* B, int64_t ldb, void* X, int
         bool any = false;
         for (int j = 0; j < k; ++j) any |= hst[j].active != 0;
         if (!any || restart > 5) break;
+        // stall detection from this start on
+        for (int j = 0; j < k; ++j) {
+            mark[j] = std::fabs(hst[j].phibar);
+            it_mark[j] = hst[j].iters;
+        }
         while (any) {
             for (int it = 0; it < 8; ++it) {
                 SC_TRY(op_apply(op, false, w.v[vi], op->n, w.p, op->n, k, w.tmp, s));
@@ -276,7 +291,25 @@ sc_status minres_solve(const sc_op* op, const void* B, int64_t ldb, void* X, int
             SC_HIP(hipMemcpyAsync(hst.data(), w.st[cur], sizeof(MRCol) * k, hipMemcpyDeviceToHost, s));
             SC_HIP(hipStreamSynchronize(s));
             any = false;
-            for (int j = 0; j < k; ++j) any |= hst[j].active != 0;
+            bool dirty = false;
+            for (int j = 0; j < k; ++j) {
+                if (hst[j].active) {
+                    const double ph = std::fabs(hst[j].phibar);
+                    if (ph <= 0.99 * mark[j]) {
+                        mark[j] = ph;
+                        it_mark[j] = hst[j].iters;
+                    } else if (hst[j].iters - it_mark[j] >= kStallWindow) {
+                        hst[j].active = 0;
+                        hst[j].maxit = hst[j].iters;
+                        dirty = true;
+                    }
+                }
+                any |= hst[j].active != 0;
+            }
+            if (dirty) {
+                SC_HIP(hipMemcpyAsync(w.st[cur], hst.data(), sizeof(MRCol) * k, hipMemcpyHostToDevice, s));
+                SC_HIP(hipStreamSynchronize(s));
+            }
         }
     }
     bool conv = true;

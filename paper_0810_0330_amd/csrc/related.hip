@@ -40,7 +40,7 @@ RelPlan plan(const sc_op* op, int k, int m, bool mixed) {
     p.seed_bytes = seed_workspace(op, m, mixed);
     off = al256(off + p.seed_bytes);
     p.proj_off = off;
-    p.proj_bytes = project_workspace(op->n, m, cpl);
+    p.proj_bytes = project_workspace(op->n, m, k - 1, cpl);
     off = al256(off + p.proj_bytes);
     p.cg_off = off;
     p.cg_bytes = cg_workspace(op, k, mixed);

@@ -21,6 +21,9 @@ struct sc_op {
     const void* U32 = nullptr;
     double kappa = 0.0;
     int antiperiodic = 1;
+    // distinct for every op the process creates (an op allocated at a freed
+    // op's address is still a different op to the caches keyed on it)
+    uint64_t gen = 0;
 };
 
 // operators built on the Wilson links (D^H D, and gamma_5 D, which is Hermitian indefinite)
@@ -148,13 +151,18 @@ sc_status seed_finalize_any(const sc_op* op, void* x1, void* V, int64_t ldv, sc_
                             bool form_x1 = true);
 
 // ---------------------------------------------------------------- projection and CG
-size_t project_workspace(int64_t n, int m, bool cpl);
+// bytes of work of project_impl for k right-hand sides (any k up to kMaxCols needs the same)
+size_t project_workspace(int64_t n, int m, int k, bool cpl);
 sc_status project_impl(int64_t n, const void* V, int64_t ldv, sc_dtype vdt, int m, const double* alpha,
                        const double* beta, sc_dtype xdt, const void* R0, int64_t ldr, int k, void* X, int64_t ldx,
                        void* work, size_t work_bytes, hipStream_t s);
 size_t cg_workspace(const sc_op* op, int k, bool mixed);
 sc_status solve_cg(const sc_op* op, int mixed, const void* B, int64_t ldb, void* X, int64_t ldx, int k, double tol,
                    int maxit, int* iters, double* relres, void* work, size_t work_bytes, hipStream_t s);
+
+// ---------------------------------------------------------------- batches (batch.hip)
+// drop every cached batch graph that was recorded for this op (called when the op is destroyed)
+void batch_forget_op(const sc_op* op);
 
 // ---------------------------------------------------------------- multiple seeding (multiseed.hip)
 size_t multiseed_workspace(const sc_op* op, int k);

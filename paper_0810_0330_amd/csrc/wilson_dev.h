@@ -69,14 +69,9 @@ __device__ __forceinline__ void su3_mul(const cplx<R> u[3][3], const cplx<R> h[3
     }
 }
 
-// One hop, acc += (1 + SIG gamma_MU) (U or U^H) psi (times bf for the time
-// direction), in two halves: hop_half projects psi to the two colour vectors
-// of the half spinor and multiplies them by the link; hop_acc rebuilds the
-// four spin components from them and adds them to acc.
-template <int MU, int SIG, bool DAGU, typename R>
-__device__ __forceinline__ void hop_half(const cplx<R> psi[4][3], const cplx<R> u[3][3], R bf, cplx<R> c0[3],
-                                         cplx<R> c1[3]) {
-    cplx<R> h0[3], h1[3];
+// The two colour vectors of the half spinor h = psi_up + SIG A_mu psi_down.
+template <int MU, int SIG, typename R>
+__device__ __forceinline__ void project(const cplx<R> psi[4][3], cplx<R> h0[3], cplx<R> h1[3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         if constexpr (MU == 0) {         // A = -i sigma_x: A psi_dn = (-i psi3, -i psi2)
@@ -93,6 +88,17 @@ __device__ __forceinline__ void hop_half(const cplx<R> psi[4][3], const cplx<R> 
             h1[c] = adds<SIG>(psi[1][c], psi[3][c]);
         }
     }
+}
+
+// One hop, acc += (1 + SIG gamma_MU) (U or U^H) psi (times bf for the time
+// direction), in two halves: hop_half projects psi to the two colour vectors
+// of the half spinor and multiplies them by the link; hop_acc rebuilds the
+// four spin components from them and adds them to acc.
+template <int MU, int SIG, bool DAGU, typename R>
+__device__ __forceinline__ void hop_half(const cplx<R> psi[4][3], const cplx<R> u[3][3], R bf, cplx<R> c0[3],
+                                         cplx<R> c1[3]) {
+    cplx<R> h0[3], h1[3];
+    project<MU, SIG>(psi, h0, h1);
     if constexpr (MU == 3) {  // (anti)periodic boundary factor of the time hops
 #pragma unroll
         for (int c = 0; c < 3; ++c) {

@@ -122,3 +122,37 @@ def test_batch_mixed_operator_kinds():
             assert abs(a - b) <= 2, (r["iters"], alone["iters"])
     Xd = res[1]["X"].cpu().numpy().T
     assert np.linalg.norm(Xd - Bd / d[:, None]) / np.linalg.norm(Bd / d[:, None]) <= 3 * 1e-10  # cond = 3
+
+
+def test_batch_graph_cache_follows_the_operator():
+    # two calls with identical shapes, buffers and stream but different
+    # operators (kappa and links; the first op destroyed before the second is
+    # made, so it may reuse the address): each must equal the single-system
+    # solve of its own operator, not a replay of the other's seed graph
+    print("batch graph cache keyed on the operator", flush=True)
+    import gc
+    dims = (4, 4, 4, 4)
+    B = np.concatenate([synth.point_sources(dims, synth.ALL_SPIN_COLOUR[:2]),
+                        synth.z4_noise(dims[0] ** 4 * 12, 1, synth.rng(42, 2))], axis=1)
+    Bl = _lib(B)
+    m, freq, tol = 30, 1, 1e-10
+    outs = []
+    for cfg, kappa in ((42, 0.12), (43, 0.11)):
+        U = synth.su3_links(dims, synth.rng(cfg, 0))
+        Ut = torch.from_numpy(api.pack_links(U)).to(DEV)
+        op = api.Op.wilson(dims, Ut, kappa)
+        r = api.batch_solve([{"op": op, "B": Bl, "m": m, "freq": freq, "tol": tol}])[0]
+        alone = api.seeded_solve(op, Bl, m, freq, tol)
+        assert r["status"] in (0, 2) and max(r["relres"]) <= tol
+        assert r["m_done"] == alone["basis"].m_done
+        for a, b in zip(r["iters"], alone["iters"]):
+            assert abs(a - b) <= 1, (kappa, r["iters"], alone["iters"])
+        Xr, Xa = _nat(r["X"]), _nat(alone["X"])
+        assert np.abs(Xr - Xa).max() <= 1e-9 * np.abs(Xa).max()
+        oop = ops.WilsonNormalOp(U, kappa)
+        for j in range(B.shape[1]):
+            assert np.linalg.norm(B[:, j] - oop(Xr[:, j])) <= 2 * tol * np.linalg.norm(B[:, j])
+        outs.append(Xr)
+        del op, r, alone
+        gc.collect()
+    assert np.abs(outs[0] - outs[1]).max() > 1e-3 * np.abs(outs[0]).max()

@@ -2,13 +2,19 @@
 
 Bars: against the oracle gradient (dense solves) on a 4^4 lattice, dL/db and
 dL/dkappa within 1e-8 relative (FP64 solves to 1e-12); on the 12^4 lattice
-(12 point sources, kappa = 0.12), the central difference in kappa with
+(point sources, kappa = 0.12), against the oracle gradient of two right-hand
+sides (tight oracle CG solves, stored in tests/golden/oracle_grad12.json by
+tests/golden/make_oracle_golden.py): L, dL/dkappa and dL/db at 256 sampled
+entries within 1e-8 relative; with all 12, the central difference in kappa with
 h = 1e-6 (FP64 solves to 1e-13, so the difference carries ~1e-13/1e-6 noise)
 within 1e-5 relative, and the central difference along random directions of
 b, which has no truncation error because L is linear in b, within 1e-8.  In
 mixed precision (FP32 solves with FP64 reliable updates, tol 1e-10) on 4^4,
 against the oracle gradient within 1e-7 (cond(A) tol bounds the solution errors).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -19,6 +25,8 @@ from paper_0810_0330_amd.autograd import seeded_solve
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
+GOLDEN_GRAD12 = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                            "oracle_grad12.json")))
 
 
 def _lib(Bnat):
@@ -80,6 +88,33 @@ def c4():
     inp = synth.make_inputs(w)
     Eta = synth.complex_gaussian(w.n, w.nrhs, synth.rng(w.config_id, 2))
     return w, inp, Eta
+
+
+def test_grad_12x4_against_oracle(c4):
+    # the C4 lattice itself: two right-hand sides through the autograd path
+    # (forward seeded solve, adjoint solves seeded from the forward basis)
+    # against the oracle's gradient with tight CG solves
+    w, inp, Eta = c4
+    g = GOLDEN_GRAD12
+    assert g["workload"] == w.name
+    cols = g["cols"]
+    print("grad vs oracle 12^4, columns", cols, flush=True)
+    Ul = torch.from_numpy(api.pack_links(inp["U"])).to(DEV)
+    Bl = _lib(inp["B"][:, cols]).requires_grad_(True)
+    kap = torch.tensor(w.kappa, dtype=torch.float64, device=DEV, requires_grad=True)
+    X = seeded_solve(Bl, kap, Ul, w.dims, w.m, w.freq, 1e-12)
+    L = _loss(X, _lib(Eta[:, cols]))
+    L.backward()
+    gB = _nat(Bl.grad)
+    idx = np.array(g["sample_index"])
+    lam = np.stack([np.array([complex(a, b) for a, b in col]) for col in g["lambda_sample"]], axis=1)
+    print(f"L {L.item():.15e} oracle {g['L']:.15e}; dL/dkappa {kap.grad.item():.15e} oracle {g['dL_dkappa']:.15e}",
+          flush=True)
+    assert abs(L.item() - g["L"]) <= 1e-8 * abs(g["L"])
+    assert abs(kap.grad.item() - g["dL_dkappa"]) <= 1e-8 * abs(g["dL_dkappa"])
+    assert np.abs(gB[idx] - lam).max() <= 1e-8 * np.abs(lam).max()
+    for j in range(len(cols)):
+        assert abs(np.linalg.norm(gB[:, j]) - g["lambda_norm"][j]) <= 1e-8 * g["lambda_norm"][j]
 
 
 def test_grad_fd_12x4(c4):

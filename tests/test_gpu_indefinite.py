@@ -113,6 +113,23 @@ def test_indefinite_seeded_wilson_4x4():
         assert np.linalg.norm(X[:, j] - ref["X"][:, j]) / np.linalg.norm(ref["X"][:, j]) <= 2 * 50 * tol
 
 
+def _oracle_range(apply_a, B, m, freq, tol, ref_iters, nens=8):
+    """Per-RHS (lo, hi) of the oracle's counts over 1e-15 relative changes of b^1.
+
+    Run past convergence, the Lanczos recurrence amplifies rounding, so the
+    counts the data fix are a range; the GPU is held to +-2 of it, as the FP64
+    seed tests are."""
+    lo, hi = list(ref_iters), list(ref_iters)
+    for e in range(nens):
+        gen = np.random.default_rng(500 + e)
+        B2 = B.copy()
+        B2[:, 0] = B2[:, 0] + gen.standard_normal(B.shape[0]) * (1e-15 * np.linalg.norm(B[:, 0]) / np.sqrt(B.shape[0]))
+        its = ind.seeded_solve(apply_a, B2, m, freq, tol)["iters"]
+        lo = [min(a, b) for a, b in zip(lo, its)]
+        hi = [max(a, b) for a, b in zip(hi, its)]
+    return lo, hi
+
+
 def test_indefinite_seeded_diagonal_breakdown_and_outliers():
     # the oracle's character example: small eigenvalues of both signs; the
     # seed run past convergence halves the others' MINRES counts
@@ -126,9 +143,11 @@ def test_indefinite_seeded_diagonal_breakdown_and_outliers():
     out = api.indefinite_solve(op, torch.from_numpy(B.T.copy()).to(DEV), 400, 10, 1e-8)
     assert max(out["relres"]) <= 1e-8
     plain = api.solve_minres(op, torch.from_numpy(B[:, 1:].T.copy()).to(DEV), 1e-8)[1]
-    for a, b, p in zip(out["iters"][1:], ref["iters"][1:], plain):
+    lo, hi = _oracle_range(ops.DiagOp(d), B, 400, 10, 1e-8, ref["iters"])
+    _say("gpu", out["iters"], "oracle range", lo, hi)
+    for a, l, h, p in zip(out["iters"][1:], lo[1:], hi[1:], plain):
         assert a < 0.6 * p, (out["iters"], plain)
-        assert abs(a - b) <= max(3, 0.05 * b), (out["iters"], ref["iters"])
+        assert l - 2 <= a <= h + 2, (out["iters"], lo, hi)
     Xs = B / d[:, None]
     assert np.linalg.norm(out["X"].cpu().numpy().T - Xs) / np.linalg.norm(Xs) <= 2 * 500 * 1e-8  # cond = 500
 
@@ -146,8 +165,9 @@ def test_indefinite_seeded_column_groups():
     out = api.indefinite_solve(op, torch.from_numpy(B.T.copy()).to(DEV), 300, 10, 1e-8)
     assert out["m_done"] == ref["m_done"] == 300
     assert max(out["relres"]) <= 1e-8
-    for a, b in zip(out["iters"], ref["iters"]):
-        assert abs(a - b) <= max(3, 0.05 * b), (out["iters"], ref["iters"])
+    lo, hi = _oracle_range(ops.DiagOp(d), B, 300, 10, 1e-8, ref["iters"])
+    for a, l, h in zip(out["iters"], lo, hi):
+        assert l - 2 <= a <= h + 2, (out["iters"], lo, hi)
     Xs = B / d[:, None]
     assert np.linalg.norm(out["X"].cpu().numpy().T - Xs) / np.linalg.norm(Xs) <= 2 * 334 * 1e-8  # cond = 1/0.003
 
