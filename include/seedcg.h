@@ -239,6 +239,25 @@ sc_status sc_project(int64_t n, const void* V_dev, int64_t ldv, sc_dtype v_dtype
                      const void* R0_dev, int64_t ldr, int k, void* X_dev, int64_t ldx,
                      void* work_dev, size_t work_bytes, void* stream);
 
+/* ------------------------------------------------------------------ projection, no allocation
+ * sc_project without a work buffer, for callers that cannot allocate device
+ * memory: code under HIP stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, layouts, result and errors as
+ * sc_project, minus work_dev/work_bytes.  The scratch space (the m x k
+ * coefficient block, the contraction's partial sums, the tridiagonal solve's
+ * work) lives in an array of SC_NOALLOC_SCRATCH_BYTES bytes of device memory
+ * that the library holds on every GPU it runs on until the process ends; the
+ * call itself allocates nothing.  Sizes whose scratch
+ * (sc_workspace_size(NULL, SC_CALL_PROJECT, k, m, ...) with n passed in) would
+ * exceed it are rejected with SC_ERR_WORKSPACE before anything is launched.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * device (two streams, two threads) race.  The optional benchmark timer never
+ * times this call. */
+#define SC_NOALLOC_SCRATCH_BYTES (64u << 20)
+sc_status sc_project_noalloc(int64_t n, const void* V_dev, int64_t ldv, sc_dtype v_dtype, int m,
+                             const double* alpha_dev, const double* beta_dev, sc_dtype vec_dtype,
+                             const void* R0_dev, int64_t ldr, int k, void* X_dev, int64_t ldx, void* stream);
+
 /* ------------------------------------------------------------------ CG
  * Plain CG (Hestenes-Stiefel) on each of k columns, batched: B_dev and X_dev
  * (in: guesses, out: solutions) are n x k in the op dtype.  Stops each column

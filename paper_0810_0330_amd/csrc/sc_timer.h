@@ -57,6 +57,14 @@ class TimerScope {
         }                                                                                                    \
     } while (0)
 
+// While a TimerMute is alive on a thread, no TimerScope of that thread times
+// anything (no events are created or recorded).
+class TimerMute {
+   public:
+    TimerMute();
+    ~TimerMute();
+};
+
 sc_status timer_enable(int on);
 sc_status timer_read(int cls, double* ms, int64_t* launches, double* bytes, double* flops);
 

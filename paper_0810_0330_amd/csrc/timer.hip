@@ -52,7 +52,11 @@ bool timer_on() { return g_on; }
 
 namespace {
 thread_local TimerScope* t_current = nullptr;
+thread_local int t_mute = 0;
 }
+
+TimerMute::TimerMute() { ++t_mute; }
+TimerMute::~TimerMute() { --t_mute; }
 
 TimerScope* TimerScope::current() { return t_current; }
 
@@ -63,7 +67,7 @@ void TimerScope::launched() {
 
 TimerScope::TimerScope(int cls, hipStream_t s, double bytes, double flops)
     : cls_(cls), s_(s), bytes_(bytes), flops_(flops), a_(nullptr), b_(nullptr), used_(false), prev_(t_current) {
-    if (!g_on) return;
+    if (!g_on || t_mute > 0) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;  // not in graphs
     std::lock_guard<std::mutex> lk(g_mu);
