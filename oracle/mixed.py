@@ -25,9 +25,13 @@ Reliable updates (CG):
     the norm);
   * the update: x += x_s; x_s = 0; r_true = b - A x in FP64; r = r_true
     rounded to single; rho = ||r_true||^2, which also becomes the new largest
-    value; the direction p is kept, unless ||r_true||^2 has not halved since
-    the smallest value seen at an update (the FP64 residual is at its rounding
-    floor): then p = r;
+    value; the direction p is kept, unless the true residual no longer follows
+    the recursion: ||r_true||^2 has not halved since the smallest value seen
+    at an update, or it is more than 4 times the recursive ||r||^2 just before
+    the update (||r_true|| more than twice ||r||).  Either means that the FP64
+    residual is at its rounding floor while the recursion kept falling; the
+    kept p belongs to that recursion, and CG continued with it and with the
+    true residual's rho diverges.  Then p = r;
   * when ||r|| <= tol ||b|| the single-precision recursion stops, x_s is folded
     into x and the true residual decides: at tol, the column is done; above it,
     CG restarts from r_true with p = r (at most 5 restarts, as ``cg.cg``).
@@ -131,12 +135,14 @@ def cg_mixed(apply64, apply_lo, b, x0=None, tol=1e-8, maxit=100000, lo=None, upd
                 if events is not None:
                     events.append({"iter": it, "x": x.copy(), "r_true": r_true.copy(), "rho_rec": rho,
                                    "rmax": rmax})
+                consistent = rho_true <= 4.0 * rho
                 rho = rho_true
                 rmax = rho
                 r = r_true.astype(lo)
-                if rho_true < 0.5 * best_true:
+                improved = rho_true < 0.5 * best_true
+                if improved:
                     best_true = rho_true
-                else:
+                if not (improved and consistent):
                     p = r.copy()
         x = x + xs.astype(hi)
         r_true = b - apply64(x)

@@ -32,10 +32,12 @@
 // in mixed precision, a FP64 true residual that has not halved over
 // kStallUpdates successive reliable updates (tol below what the FP64 residual
 // can reach).  Its iteration limit is lowered to the count reached, so no
-// restart takes it up again.  A reliable update whose true residual has not
-// halved also restarts the direction (p = r): the kept p belongs to a
-// recursion that has left the true residual behind, and continuing with it
-// can diverge.
+// restart takes it up again; in mixed precision it keeps x as of its last
+// reliable update (the FP32 increment since then is dropped).  A reliable
+// update whose true residual has not halved, or is more than twice the
+// recursive residual norm, also restarts the direction (p = r): the kept p
+// belongs to a recursion that has left the true residual behind, and
+// continuing with it diverges.
 #include "sc_internal.h"
 
 #include <cmath>
@@ -470,6 +472,9 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
                     } else if (hst[j].iters - it_min[j] >= kStallWindow) {
                         stop_stalled(j);
                         dirty = true;
+                        // a recursion that stopped falling may have left the solution
+                        // behind: the column keeps x as of its last reliable update
+                        if (mixed) SC_TRY(fill<float>((float*)w.xs + (int64_t)j * N2, N2, 0.0f, s));
                     }
                 }
                 any |= hst[j].active != 0;
@@ -519,19 +524,22 @@ static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ld
                     const double rr = hrr[c];
                     const bool done = !(rr > cc.tol2);
                     // the true residual should have fallen with the recursive one; if
-                    // it has not halved since the best one seen, the FP64 residual is
-                    // at its rounding floor and the kept direction no longer matches it
+                    // it has not halved since the best one seen, or it is more than
+                    // twice the recursive residual norm (cc.rho is the recursion's
+                    // ||r||^2 at this check), the FP64 residual is at its rounding
+                    // floor and the kept direction no longer matches it
                     const bool improved = rr < 0.5 * best_true[j];
+                    const bool consistent = rr <= 4.0 * cc.rho;
                     if (improved) {
                         best_true[j] = rr;
                         nstall[j] = 0;
                     } else if (!done) {
                         ++nstall[j];
                     }
-                    if (!done && (cc.flag == 1 || !improved)) {
+                    if (!done && (cc.flag == 1 || !improved || !consistent)) {
                         // the FP32 recurrence reached tol but the true residual did not,
-                        // or the true residual stopped falling: restart the direction
-                        // from the true residual
+                        // or the true residual stopped following it: restart the
+                        // direction from the true residual
                         dl.push_back(j);
                         db.push_back(0.0);
                     }

@@ -16,10 +16,15 @@
 // It stops when |phibar| <= tol ||b||; the start (r = b - A x, beta_1 = ||r||)
 // is also the true-residual check, so a finished batch is started again and
 // the columns whose true residual is at tol stay inactive (at most 5 restarts,
-// as the CG does).  A column whose rotated residual norm has not fallen by 1%
-// within kStallWindow iterations (tol below the attainable residual) stops
-// and is reported as not converged; its iteration limit is lowered to the
-// count reached, so no restart takes it up again.
+// as the CG does).  A column stops early and is reported as not converged
+// when its residual cannot reach tol: the rotated residual norm has not
+// fallen by 1% within kStallWindow iterations (tol below the attainable
+// residual), or ||A r_k|| has fallen to max(tol, sqrt(eps)) ||A|| ||r_k|| (the estimate of
+// ||A|| being the Frobenius norm of the tridiagonal matrix so far), the
+// least-squares stop of Paige and Saunders: r_k is then a null vector of A to
+// that accuracy (an inconsistent system), and in finite precision the rotated
+// residual keeps drifting down below the true one.  Its iteration limit is
+// lowered to the count reached, so no restart takes it up again.
 #include "sc_internal.h"
 
 #include <cmath>
@@ -30,6 +35,7 @@ namespace sc {
 namespace {
 
 constexpr int kStallWindow = 1000;
+constexpr double kLsqFloor = 1.4901161193847656e-8;  // sqrt(DBL_EPSILON): least-squares stop (see k_mr_update)
 
 struct MRCol {
     double beta;    // beta_k (the norm that scales v_k)
@@ -41,6 +47,7 @@ struct MRCol {
     double bnorm;   // ||b||
     double tol;
     double relres;  // true relative residual at the last start
+    double tnorm2;  // squared Frobenius norm of the tridiagonal matrix so far (estimate of ||A||^2)
     int active, iters, maxit, pad;
 };
 
@@ -116,6 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_mr_start(MRCol* st, double* __restri
         c.s = 0.0;
         c.delta1 = 0.0;
         c.eps = 0.0;
+        c.tnorm2 = 0.0;
         st[j] = c;
     }
     if (!run) return;
@@ -203,8 +211,19 @@ __global__ __launch_bounds__(kBlock) void k_mr_update(const MRCol* st, MRCol* st
         o.eps = en;
         o.phibar = ss * c.phibar;
         o.iters = c.iters + 1;
+        o.tnorm2 = c.tnorm2 + a * a + c.beta * c.beta + bn * bn;
         if (!(fabs(o.phibar) > c.tol * c.bnorm) || !(bn > 0.0) || !isfinite(o.phibar) || o.iters >= c.maxit)
             o.active = 0;
+        // least-squares stop: ||A r|| / ||r|| = sqrt(g1^2 + d1n^2) has fallen to
+        // max(tol, sqrt(eps)) times the estimate of ||A||, so r is a null vector of
+        // A to that accuracy and no later iteration can reduce it.  In FP64 the
+        // ratio bottoms out not far below sqrt(eps) = 1.5e-8 (about 1e-10 on an
+        // inconsistent diagonal system), and the iterations after that point
+        // let x grow without bound, so a smaller tol must not postpone the stop.
+        if (o.active && !(sqrt(g1 * g1 + d1n * d1n) > fmax(c.tol, kLsqFloor) * sqrt(o.tnorm2))) {
+            o.active = 0;
+            o.maxit = o.iters;
+        }
         st_next[j] = o;
     }
     const double* vc = v + j * N;

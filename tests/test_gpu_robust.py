@@ -7,8 +7,11 @@ iteration limit (100000):
     can reach: mixed-precision CG stops when reliable updates stop reducing the
     true residual, FP64 CG after its bounded restarts;
   * an inconsistent system (a well-conditioned diagonal with one zero entry,
-    b nonzero there) leaves MINRES's residual at a plateau (the least-squares
-    residual): it stops by the window rule.
+    b nonzero there): MINRES's residual reaches the least-squares residual
+    |b_0| within a few dozen iterations and cannot fall further; it stops by
+    the least-squares test (||A r|| tiny against ||A|| ||r||) there, before
+    the later iterations let x grow without bound (they would push the true
+    residual above the plateau while the rotated one drifts below it).
 Each case also checks that the answer returned is still the best the solver
 reached (true residual at the rounding floor, or at the plateau).
 """
@@ -58,7 +61,7 @@ def test_stall_on_inconsistent_system():
     _say("minres on a singular diagonal")
     X, its, rel, st = api.solve_minres(op, Bt, 1e-10, with_status=True)
     _say("  iters", its, "relres", rel, "status", st)
-    assert st == 1 and max(its) < 1500
+    assert st == 1 and max(its) < 200
     for j in range(2):
         assert rel[j] < 1.0001 * floor[j]
 

@@ -13,6 +13,10 @@
     tol on Example 1 and on Wilson 4^4; on Wilson the count is within a few of
     FP64 CG's, on Example 1 (isolated small eigenvalues) it is longer, as
     finite-precision CG is.
+  * With tol below what an FP64 x can reach (1e-17 on the Laplacian) the
+    result stays at the FP64 rounding floor, checked with a dense matrix built
+    from the 5-point definition (the update that finds the floor restarts the
+    direction instead of diverging).
   * The seed phase with FP64 arrays reproduces the FP64 oracle seed; with a
     single-precision basis, the basis just after a reorthogonalization event is
     orthonormal to single precision (about 1e-6 in Frobenius norm) and the
@@ -135,6 +139,33 @@ def test_single_precision_updates_and_final_residual(case):
     # the error against the FP64 solution is at the level the residual fixes
     xr = np.linalg.solve(np.diag(op.d), b) if isinstance(op, ops.DiagOp) else cg(op, b, tol=1e-13)[0]
     assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-5
+
+
+def test_tol_below_the_fp64_floor_stays_at_the_floor():
+    # tol 1e-17 cannot be reached: the true residual of an FP64 x bottoms out
+    # near 1e-16.  At the update that finds it there the recursion has fallen
+    # further, so the kept direction no longer matches the true residual, and
+    # continuing CG with it diverges (the recursion's rho and the true one
+    # differ by orders of magnitude).  The rule restarts p = r instead, and the
+    # result stays at the floor: checked with the dense 5-point matrix built
+    # here from its definition (4 on the diagonal, -1 to each grid neighbour,
+    # Dirichlet boundary).
+    nx = 32
+    t = 2.0 * np.eye(nx) - np.eye(nx, k=1) - np.eye(nx, k=-1)
+    a = np.kron(np.eye(nx), t) + np.kron(t, np.eye(nx))
+    op = ops.Laplace2DOp(nx, nx)
+    B = synth.real_gaussian(nx * nx, 3, synth.rng(60, 1))
+    for j in range(3):
+        ev = []
+        x, it, rel = mixed.cg_mixed(op, op.single(), B[:, j], tol=1e-17, maxit=600, max_restarts=0, events=ev)
+        true = np.linalg.norm(B[:, j] - a @ x) / np.linalg.norm(B[:, j])
+        assert np.isfinite(true) and true < 1e-14, (j, true)
+        # the updates before the floor kept the direction: there the true
+        # residual followed the recursion (rho within 1%, far from the factor 4)
+        for e in ev:
+            rt = float(e["r_true"] @ e["r_true"])
+            if rt > 1e-24 * float(B[:, j] @ B[:, j]):
+                assert abs(rt / e["rho_rec"] - 1.0) < 1e-2
 
 
 def test_seed_fp64_arrays_reproduce_oracle_seed():
