@@ -176,6 +176,19 @@ sc_status sc_wilson_tune_info(const sc_op* op, sc_dtype dtype, int k, int* varia
  * 45..68) on a lattice with X Y != 256. */
 sc_status sc_wilson_tune_set(const sc_op* op, sc_dtype dtype, int k, int variant);
 
+/* Host-only check of the addressing of the DPP-form stencil shapes (69..80),
+ * whose loads and stores go through buffer descriptors: an access outside
+ * its descriptor's record would read zero or be dropped instead of faulting.
+ * Walks, on the CPU and with the kernel's own index functions, every access
+ * that one pass over a lattice of dims[4] = {X, Y, Z, T} with k columns of
+ * leading dimensions ldx (source) and ldy (destination; complex elements)
+ * would make, and counts those outside their record (*outside) among all
+ * checked (*accesses); a correct shape gives *outside = 0.  Touches no GPU.
+ * Errors: SC_ERR_ARG for a variant that is not a DPP-form shape, or a
+ * lattice it does not run on (X = Y = 16, 288 V < 2^31 bytes). */
+sc_status sc_wilson_range_check(const int* dims, int variant, int k, int64_t ldx, int64_t ldy, int64_t* accesses,
+                                int64_t* outside);
+
 /* ------------------------------------------------------------------ workspace */
 typedef enum {
     SC_CALL_APPLY = 0,

@@ -57,6 +57,7 @@ _PROTOS = {
     "sc_workspace_size": [_P, _INT, _INT, _INT, _INT, ctypes.POINTER(_SZ)],
     "sc_seed_lanczos": [_P, _P, _P, _INT, _INT, _P, _I64, _INT, _P, _P, ctypes.POINTER(_INT), _P, _SZ, _P],
     "sc_project": [_I64, _P, _I64, _INT, _INT, _P, _P, _INT, _P, _I64, _INT, _P, _I64, _P, _SZ, _P],
+    "sc_wilson_range_check": [_P, _INT, _INT, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64)],
     "sc_project_noalloc": [_I64, _P, _I64, _INT, _INT, _P, _P, _INT, _P, _I64, _INT, _P, _I64, _P],
     "sc_solve_cg": [_P, _INT, _P, _I64, _P, _I64, _INT, _DBL, _INT, ctypes.POINTER(_INT), ctypes.POINTER(_DBL),
                     _P, _SZ, _P],

@@ -412,8 +412,17 @@ sc_status sc_wilson_tune_set(const sc_op* op, sc_dtype dtype, int k, int variant
     SC_GUARD_BEGIN
     SC_ARG(op && has_links(op), "not a Wilson op");
     SC_ARG(dtype == SC_C128 || dtype == SC_C64, "dtype must be SC_C128 or SC_C64");
-    SC_ARG(k >= 1 && variant >= -1 && variant < SC_WILSON_VARIANTS, "k must be >= 1 and variant in -1..68");
+    SC_ARG(k >= 1 && variant >= -1 && variant < SC_WILSON_VARIANTS,
+           "k must be >= 1 and variant in -1..SC_WILSON_VARIANTS-1");
     return wilson_tune_pin(op, dtype == SC_C64, k, variant);
+    SC_GUARD_END
+}
+
+sc_status sc_wilson_range_check(const int* dims, int variant, int k, int64_t ldx, int64_t ldy, int64_t* accesses,
+                                int64_t* outside) {
+    SC_GUARD_BEGIN
+    SC_ARG(dims && accesses && outside, "NULL argument");
+    return wilson_tx_check(dims, variant, k, ldx, ldy, accesses, outside);
     SC_GUARD_END
 }
 

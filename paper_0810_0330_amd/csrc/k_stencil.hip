@@ -729,19 +729,31 @@ static int tx_tlen(const sc_op* op, int v) {
 static int tx_nc(int v) { return (v - WV_TX) >= 6 ? 2 : 1; }
 static int tx_parts(const sc_op* op, int v) { return op->dims[2] * ((op->dims[3] + tx_tlen(op, v) - 1) / tx_tlen(op, v)); }
 
+// launch geometry of a DPP-form pass (used by the launch and by its range check)
+struct TxGeom {
+    int nc, tlen, nseg, ncg, per_xcd, blocks, cgm;
+};
+static TxGeom tx_geom(const sc_op* op, int v, int k) {
+    TxGeom q;
+    q.nc = tx_nc(v);
+    q.tlen = tx_tlen(op, v);
+    q.nseg = (op->dims[3] + q.tlen - 1) / q.tlen;
+    q.ncg = (k + q.nc - 1) / q.nc;
+    q.per_xcd = (q.ncg * op->dims[2] * q.nseg + kXcd - 1) / kXcd;
+    q.blocks = q.per_xcd * kXcd;
+    q.cgm = ((v - WV_TX) % 6) >= 3 ? 1 : 0;
+    return q;
+}
+
 static void tx_launch(const sc_op* op, int v, bool dag, int epi, const float* X, int64_t ldx, float* Y, int64_t ldy,
                       int k, const float* U, const TmEpi& e, hipStream_t s) {
     Geom g{op->dims[0], op->dims[1], op->dims[2], op->dims[3], op->vol};
-    const int tlen = tx_tlen(op, v);
-    const int nseg = (g.T + tlen - 1) / tlen;
-    const int ncg = (k + tx_nc(v) - 1) / tx_nc(v);
-    const int per_xcd = (ncg * g.Z * nseg + kXcd - 1) / kXcd;
-    const dim3 grid((unsigned)(per_xcd * kXcd)), blk(kBlock);
+    const TxGeom q = tx_geom(op, v, k);
+    const dim3 grid((unsigned)q.blocks), blk(kBlock);
     const float kap = (float)op->kappa, ts = op->antiperiodic ? -1.0f : 1.0f;
-    const int cgm = ((v - WV_TX) % 6) >= 3 ? 1 : 0;
-#define SC_TX(DAG, EPI_, NC_)                                                                                   \
-    SC_TLAUNCH((k_wilson_tx<DAG, EPI_, NC_>), grid, blk, 0, s, Y, 2 * ldy, X, 2 * ldx, U, g, kap, ts, k, nseg, \
-               tlen, per_xcd, cgm, e)
+#define SC_TX(DAG, EPI_, NC_)                                                                                     \
+    SC_TLAUNCH((k_wilson_tx<DAG, EPI_, NC_>), grid, blk, 0, s, Y, 2 * ldy, X, 2 * ldx, U, g, kap, ts, k, q.nseg, \
+               q.tlen, q.per_xcd, q.cgm, e)
 #define SC_TXE(NC_)                                 \
     if (epi == TM_NORM) SC_TX(false, TM_NORM, NC_); \
     else if (epi == TM_CG) SC_TX(true, TM_CG, NC_); \
@@ -754,6 +766,85 @@ static void tx_launch(const sc_op* op, int v, bool dag, int epi, const float* X,
     }
 #undef SC_TXE
 #undef SC_TX
+}
+
+// Every buffer access of one DPP-form launch (any epilogue) on a lattice
+// with these dims, k columns of leading dimensions ldx (source) and ldy
+// (destination) in complex elements, walked on the host with the kernel's own
+// index functions (wilson_tx.h): each load and store's byte offset against
+// its descriptor's record (links 288 V bytes; a column 96 V bytes from the
+// column's start, which must itself lie within the caller's k columns), and
+// each partial-sum index against the k * parts of the caller's buffer.
+// *accesses counts the checks, *outside the failures.
+sc_status wilson_tx_check(const int dims[4], int v, int k, int64_t ldx, int64_t ldy, int64_t* accesses,
+                          int64_t* outside) {
+    sc_op op{};
+    for (int i = 0; i < 4; ++i) op.dims[i] = dims[i];
+    op.vol = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
+    op.n = 12 * op.vol;
+    op.kappa = 0.12;
+    if (!is_tx(v) || !tx_ok(&op) || k < 1 || dims[2] < 1 || dims[3] < 1) {
+        set_error("wilson_tx_check: not a DPP-form shape for this lattice");
+        return SC_ERR_ARG;
+    }
+    const TxGeom q = tx_geom(&op, v, k);
+    const int Z = dims[2], T = dims[3];
+    const int64_t V = op.vol;
+    const unsigned uV = (unsigned)V;
+    const int parts = Z * q.nseg;
+    int64_t n = 0, bad = 0;
+    // a load or store of site `site` with components up to `cmax` through a
+    // descriptor of `rec` bytes: 32-bit offsets that the hardware adds, in range
+    auto chk = [&](int64_t site, int cmax, int64_t rec) {
+        ++n;
+        const int64_t boff = (int64_t)tx_boff((unsigned)site), soff = (int64_t)tx_soff(cmax, uV);
+        if (site < 0 || site >= V || boff + soff + 8 > rec || boff + soff + 8 > (int64_t(1) << 31)) ++bad;
+    };
+    // a column's descriptor: it starts col * ld complex elements in and spans 96 V
+    // bytes, within the caller's k columns of ld elements (ld >= n)
+    auto chk_col = [&](int col, int64_t ld) {
+        ++n;
+        const int64_t start = (int64_t)col * ld * 8, end = ((int64_t)(k - 1) * ld + op.n) * 8;
+        if (col < 0 || col >= k || ld < op.n || start + (int64_t)kTxSpinorBytes * V > end) ++bad;
+    };
+    const int64_t lrec = (int64_t)kTxLinkBytes * V, srec = (int64_t)kTxSpinorBytes * V;
+    for (int b = 0; b < q.blocks; ++b) {
+        const int L = (b % kXcd) * q.per_xcd + b / kXcd;
+        if (L >= q.ncg * Z * q.nseg) continue;  // the kernel returns
+        const TxItem wi = tx_item(L, q.ncg, Z, q.nseg, q.cgm);
+        const int t0 = wi.seg * q.tlen, t1 = std::min(T, t0 + q.tlen);
+        ++n;
+        if (wi.cg < 0 || wi.cg >= q.ncg || wi.z < 0 || wi.z >= Z || wi.seg < 0 || wi.seg >= q.nseg || t0 >= T) ++bad;
+        for (int c = 0; c < q.nc; ++c) {
+            const int col = tx_col(wi.cg, c, q.nc, k);
+            chk_col(col, ldx);
+            if (wi.cg * q.nc + c < k) {  // a column that stores (others get a zero-size record)
+                chk_col(col, ldy);
+                ++n;
+                const int64_t pi = (int64_t)col * parts + (int64_t)wi.seg * Z + wi.z;
+                if (pi < 0 || pi >= (int64_t)k * parts) ++bad;
+            }
+        }
+        const int zp = tx_zstep(wi.z, Z, 1), zm = tx_zstep(wi.z, Z, -1);
+        for (int p = 0; p < kTxPlane; ++p) {
+            const int sm = tx_site(p, wi.z, tx_tprev(t0, T), Z);
+            chk(sm, 3 * 9 + 8, lrec);  // U_t of the carried -t hop
+            chk(sm, 11, srec);         // its spinor
+            chk(tx_site(p, wi.z, t0, Z), 11, srec);
+            for (int t = t0; t < t1; ++t) {
+                const int s = tx_site(p, wi.z, t, Z);
+                for (int mu = 0; mu < 4; ++mu) chk(s, mu * 9 + 8, lrec);
+                chk(s + zm, 2 * 9 + 8, lrec);
+                chk(s + zp, 11, srec);
+                chk(s + zm, 11, srec);
+                chk(tx_tnext_site(s, t, T, Z), 11, srec);
+                chk(s, 11, srec);  // the store (and the TM_CG load of r)
+            }
+        }
+    }
+    *accesses = n;
+    *outside = bad;
+    return SC_OK;
 }
 
 static int chunk_groups(int chunk, int ncg) {

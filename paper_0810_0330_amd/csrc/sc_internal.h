@@ -85,6 +85,9 @@ sc_status wilson_pass(const sc_op* op, bool single, int which, const void* X, in
 sc_status wilson_tune_query(const sc_op* op, bool single, int k, int* variant, float* us);
 // pin a variant for (lattice, precision, k); variant < 0 forgets the choice
 sc_status wilson_tune_pin(const sc_op* op, bool single, int k, int variant);
+// host-side walk of every buffer access of a DPP-form stencil launch (no GPU)
+sc_status wilson_tx_check(const int dims[4], int v, int k, int64_t ldx, int64_t ldy, int64_t* accesses,
+                          int64_t* outside);
 
 // ---------------------------------------------------------------- streaming kernels (k_blas.hip)
 // All act on "real views": a complex column of n elements is 2n reals.

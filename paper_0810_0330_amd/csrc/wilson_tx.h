@@ -55,6 +55,51 @@ __device__ __forceinline__ float dpp_from_xm(float v) {
 
 #define SC_TX_FENCE() asm volatile("" ::: "memory")
 
+// ---- the kernel's index arithmetic, shared with the host-side range check
+// (tx_check_ranges in k_stencil.hip walks every access of a launch with these
+// functions and compares it with its descriptor's record size)
+constexpr int kTxPlane = 256;             // sites of an xy-plane (X = Y = 16)
+constexpr unsigned kTxSpinorBytes = 96u;  // per site of a spinor column: 12 complex64
+constexpr unsigned kTxLinkBytes = 288u;   // per site of the links: 4 x 9 complex64
+
+// work item L -> (column group, z-plane, t-segment)
+struct TxItem {
+    int cg, z, seg;
+};
+__host__ __device__ inline TxItem tx_item(int L, int ncg, int Z, int nseg, int cgminor) {
+    TxItem w;
+    if (cgminor) {
+        w.cg = L % ncg;
+        const int r = L / ncg;
+        w.z = r % Z;
+        w.seg = r / Z;
+    } else {
+        w.z = L % Z;
+        const int r = L / Z;
+        w.seg = r % nseg;
+        w.cg = r / nseg;
+    }
+    return w;
+}
+// column c of group cg: a column past k (a partial last group) repeats the last one
+__host__ __device__ inline int tx_col(int cg, int c, int nc, int k) {
+    const int j = cg * nc + c;
+    return j < k ? j : k - 1;
+}
+__host__ __device__ inline int tx_site(int p, int z, int t, int Z) { return p + kTxPlane * (z + Z * t); }
+// offset from a site of plane z to the same (x, y, t) on plane z + 1 (dir > 0) or z - 1, periodic
+__host__ __device__ inline int tx_zstep(int z, int Z, int dir) {
+    if (dir > 0) return z == Z - 1 ? -(Z - 1) * kTxPlane : kTxPlane;
+    return z == 0 ? (Z - 1) * kTxPlane : -kTxPlane;
+}
+__host__ __device__ inline int tx_tprev(int t, int T) { return t == 0 ? T - 1 : t - 1; }
+// the site one slice up from site s of slice t, periodic
+__host__ __device__ inline int tx_tnext_site(int s, int t, int T, int Z) {
+    return t == T - 1 ? s - (T - 1) * kTxPlane * Z : s + kTxPlane * Z;
+}
+__host__ __device__ inline unsigned tx_boff(unsigned site) { return site * 8u; }               // per-lane part
+__host__ __device__ inline unsigned tx_soff(int comp, unsigned V) { return (unsigned)comp * V * 8u; }  // wave-uniform
+
 // Memory access through buffer resources: one descriptor per array (a
 // spinor column, the links, the output column), the component's byte offset
 // (comp * V * 8, wave-uniform) in a scalar register and the site's byte
@@ -80,11 +125,11 @@ __device__ __forceinline__ void tx_st(const TxBuf& b, unsigned boff, unsigned so
                                           b.r, (int)boff, (int)soff, 0);
 }
 __device__ __forceinline__ void tx_spinor(const TxBuf& f, unsigned V, unsigned site, cplx<float> psi[4][3]) {
-    const unsigned boff = site * 8u;
+    const unsigned boff = tx_boff(site);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) psi[s][c] = tx_ld(f, boff, (unsigned)(s * 3 + c) * V * 8u);
+        for (int c = 0; c < 3; ++c) psi[s][c] = tx_ld(f, boff, tx_soff(s * 3 + c, V));
 }
 // A value the optimizer cannot see through: a link loaded a second time with
 // it is a second load, not the first load's registers kept live across the
@@ -94,11 +139,11 @@ __device__ __forceinline__ unsigned tx_opaque(unsigned x) {
     return x;
 }
 __device__ __forceinline__ void tx_link(const TxBuf& U, unsigned V, int mu, unsigned site, cplx<float> u[3][3]) {
-    const unsigned boff = site * 8u;
+    const unsigned boff = tx_boff(site);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) u[a][b] = tx_ld(U, boff, (unsigned)((mu * 3 + a) * 3 + b) * V * 8u);
+        for (int b = 0; b < 3; ++b) u[a][b] = tx_ld(U, boff, tx_soff((mu * 3 + a) * 3 + b, V));
 }
 
 template <bool DAG, int EPI, int NC>
@@ -115,18 +160,8 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
     const int L = (b % kXcd) * per_xcd + b / kXcd;
     const int ncg = (k + NC - 1) / NC;  // column groups
     if (L >= ncg * g.Z * nseg) return;  // uniform over the block
-    int cg, z, seg;
-    if (cgminor) {
-        cg = L % ncg;
-        const int r = L / ncg;
-        z = r % g.Z;
-        seg = r / g.Z;
-    } else {
-        z = L % g.Z;
-        const int r = L / g.Z;
-        seg = r % nseg;
-        cg = r / nseg;
-    }
+    const TxItem wi = tx_item(L, ncg, g.Z, nseg, cgminor);
+    const int cg = wi.cg, z = wi.z, seg = wi.seg;
     // the group's columns; a column past k (a partial last group) repeats the
     // last one and stores nothing, as does a column not active in e.st
     int col[NC];
@@ -134,9 +169,8 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
     bool any = false;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const int j = cg * NC + c;
-        col[c] = j < k ? j : k - 1;
-        upd[c] = j < k && (!e.st || e.st[col[c]].active);
+        col[c] = tx_col(cg, c, NC, k);
+        upd[c] = cg * NC + c < k && (!e.st || e.st[col[c]].active);
         any |= upd[c];
     }
     if (!any) return;  // uniform over the block
@@ -146,12 +180,12 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
     const int t1 = min(g.T, t0 + tlen);
     const int p = threadIdx.x;
     const int pyp = (p + 16) & (kBlock - 1), pym = (p - 16) & (kBlock - 1);
-    const int XY = kBlock, XYZ = XY * g.Z;
+    static_assert(kBlock == kTxPlane, "a block is one xy-plane");
     const unsigned uV = (unsigned)g.V;
-    const int zoff_p = z == g.Z - 1 ? -(g.Z - 1) * XY : XY;
-    const int zoff_m = z == 0 ? (g.Z - 1) * XY : -XY;
-    const unsigned colbytes = 96u * uV;  // 12 complex components of V sites
-    const TxBuf Ub = tx_buf(U, 288u * uV);
+    const int zoff_p = tx_zstep(z, g.Z, 1);
+    const int zoff_m = tx_zstep(z, g.Z, -1);
+    const unsigned colbytes = kTxSpinorBytes * uV;
+    const TxBuf Ub = tx_buf(U, kTxLinkBytes * uV);
     TxBuf src[NC], dst[NC];
     float alpha[NC];
 #pragma unroll
@@ -180,8 +214,8 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
     // the -t hop into slice t0, from slice t0 - 1
     C cr0[NC][3], cr1[NC][3];
     {
-        const int tm = t0 == 0 ? g.T - 1 : t0 - 1;
-        const unsigned sm = (unsigned)(p + XY * z + XYZ * tm);
+        const int tm = tx_tprev(t0, g.T);
+        const unsigned sm = (unsigned)tx_site(p, z, tm, g.Z);
         const float bf = t0 == 0 ? tsign : 1.0f;
         C u[3][3];
         tx_link(Ub, uV, 3, sm, u);
@@ -201,11 +235,11 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
     }
     C cur[NC][4][3];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) tx_spinor(src[c], uV, (unsigned)(p + XY * z + XYZ * t0), cur[c]);
+    for (int c = 0; c < NC; ++c) tx_spinor(src[c], uV, (unsigned)tx_site(p, z, t0, g.Z), cur[c]);
 
 #pragma unroll 1
     for (int t = t0; t < t1; ++t) {
-        const unsigned s = (unsigned)(p + XY * z + XYZ * t);
+        const unsigned s = (unsigned)tx_site(p, z, t, g.Z);
         C acc[NC][4][3];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -329,7 +363,7 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
         SC_TX_FENCE();
         // +t with the next slice, which becomes current
         const bool tlast = t == g.T - 1;
-        const unsigned sn = (unsigned)(tlast ? (int)s - (g.T - 1) * XYZ : (int)s + XYZ);
+        const unsigned sn = (unsigned)tx_tnext_site((int)s, t, g.T, g.Z);
         // the boundary sign as a multiply, not a branch: a branch here splits
         // the slice into basic blocks and the allocation across them spills
         const float bf = tlast ? tsign : 1.0f;
@@ -361,12 +395,12 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc) {
                     C r = {-kappa * acc[c][a][cc].re, -kappa * acc[c][a][cc].im};
-                    const unsigned soff = (unsigned)(a * 3 + cc) * uV * 8u;
+                    const unsigned soff = tx_soff(a * 3 + cc, uV);
                     if constexpr (EPI == TM_CG) {
-                        const C q = tx_ld(dst[c], s * 8u, soff);
+                        const C q = tx_ld(dst[c], tx_boff(s), soff);
                         r = {q.re - alpha[c] * r.re, q.im - alpha[c] * r.im};
                     }
-                    tx_st(dst[c], s * 8u, soff, r);
+                    tx_st(dst[c], tx_boff(s), soff, r);
                     sq = __builtin_fmaf(r.re, r.re, sq);
                     sq = __builtin_fmaf(r.im, r.im, sq);
                 }
