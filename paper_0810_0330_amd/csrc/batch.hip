@@ -13,12 +13,18 @@
 // op drops the graphs recorded for it.
 //
 // The rest is data dependent: each system's final seed state is read, x^1
-// formed, the other right-hand sides projected, and every column finished
-// with CG, one host thread and one stream per system.
+// formed and the other right-hand sides projected on the system's stream.
+// Every column is then finished with CG, all systems from one host thread:
+// each system's fixed chunk of CG iterations (per-column masks on the device)
+// is captured once into a graph (cached like the seed graph) and replayed on
+// the system's stream, and between replays the host checks every system
+// (stall rules, reliable updates, the final true-residual check).  Before any
+// of this, every lattice's stencil shapes (one column for the seed, k columns
+// for CG) are tuned one system at a time, so no shape is timed while other
+// systems share the chip.
 #include <algorithm>
 #include <cstring>
 #include <mutex>
-#include <thread>
 #include <vector>
 
 #include "sc_internal.h"
@@ -75,7 +81,7 @@ struct GraphEntry {
 };
 std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;  // most recent last
-constexpr size_t kGraphCache = 4;
+constexpr size_t kGraphCache = 32;  // seed graphs and per-system CG chunk graphs
 
 GraphKey make_key(int nsys, const sc_batch_system* sys, const void* work, hipStream_t s) {
     GraphKey k;
@@ -118,6 +124,98 @@ GraphKey make_key(int nsys, const sc_batch_system* sys, const void* work, hipStr
         put(&sys[i].mixed, sizeof sys[i].mixed);
     }
     return k;
+}
+
+// The graph of one system's CG chunk: its kGraphChunk iterations captured
+// on the system's stream.  The key holds everything the captured launches
+// bake in (operator, buffers, workspace, the tuned shape of the k-column
+// passes, the state copy the chunk starts from); an even chunk returns the
+// CG object to the same state copy, so the graph replays as captured.
+constexpr int kGraphChunk = 8;
+static_assert(kGraphChunk % 2 == 0, "a chunk must return to its starting state copy");
+
+GraphKey make_cg_key(const sc_batch_system& b, const void* cg_work, int cur) {
+    GraphKey k;
+    auto put = [&](const void* p, size_t n) {
+        const char* c = (const char*)p;
+        k.bytes.insert(k.bytes.end(), c, c + n);
+    };
+    const char tag = 'C';
+    put(&tag, 1);
+    const sc_op* op = b.op;
+    put(&op, sizeof op);
+    put(&op->gen, sizeof op->gen);
+    put(&op->kind, sizeof op->kind);
+    put(&op->n, sizeof op->n);
+    put(&op->dtype, sizeof op->dtype);
+    put(&op->nx, sizeof op->nx);
+    put(&op->ny, sizeof op->ny);
+    put(&op->d, sizeof op->d);
+    put(op->dims, sizeof op->dims);
+    put(&op->U64, sizeof op->U64);
+    put(&op->U32, sizeof op->U32);
+    put(&op->kappa, sizeof op->kappa);
+    put(&op->antiperiodic, sizeof op->antiperiodic);
+    int variant = -1;
+    if (has_links(op)) {
+        float us[SC_WILSON_VARIANTS];
+        (void)wilson_tune_query(op, b.mixed != 0, b.k, &variant, us);
+    }
+    put(&variant, sizeof variant);
+    put(&b.B_dev, sizeof b.B_dev);
+    put(&b.ldb, sizeof b.ldb);
+    put(&b.X_dev, sizeof b.X_dev);
+    put(&b.ldx, sizeof b.ldx);
+    put(&b.k, sizeof b.k);
+    put(&b.mixed, sizeof b.mixed);
+    put(&cg_work, sizeof cg_work);
+    put(&cur, sizeof cur);
+    return k;
+}
+
+// Finds or records the chunk graph of one system (*exec stays null, and the
+// chunk runs eagerly, if the stream cannot be captured)
+sc_status chunk_graph(const sc_batch_system& b, const void* cg_work, CGRun& cg, hipGraphExec_t* exec) {
+    *exec = nullptr;
+    GraphKey key = make_cg_key(b, cg_work, cg.state_index());
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (size_t j = 0; j < g_graphs.size(); ++j)
+            if (g_graphs[j].key == key) {
+                *exec = g_graphs[j].exec;
+                GraphEntry e = g_graphs[j];
+                g_graphs.erase(g_graphs.begin() + j);
+                g_graphs.push_back(e);
+                return SC_OK;
+            }
+    }
+    hipStream_t s = cg.stream();
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return SC_OK;
+    const int before = cg.state_index();
+    const sc_status st = cg.iterate(kGraphChunk);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(s, &graph);
+    if (st != SC_OK || ce != hipSuccess || cg.state_index() != before) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (st != SC_OK) return st;
+        set_error(std::string("batch_solve: chunk capture failed: ") + hipGetErrorString(ce));
+        return SC_ERR_HIP;
+    }
+    hipGraphExec_t e = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&e, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+        set_error(std::string("batch_solve: chunk graph instantiation failed: ") + hipGetErrorString(ie));
+        return SC_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    if (g_graphs.size() >= kGraphCache) {
+        (void)hipGraphExecDestroy(g_graphs.front().exec);
+        g_graphs.erase(g_graphs.begin());
+    }
+    g_graphs.push_back({key, e, {b.op->gen}});
+    *exec = e;
+    return SC_OK;
 }
 
 }  // namespace
@@ -182,8 +280,15 @@ sc_status batch_solve(int nsys, sc_batch_system* sys, void* work, size_t work_by
         }
 
     sc_status st = SC_OK;
-    // tune each lattice's seed-phase stencil shape before any capture
-    for (int i = 0; i < nsys && st == SC_OK; ++i) st = seed_pretune(sys[i].op, sys[i].mixed != 0, sw[i], s);
+    // tune each lattice's stencil shapes before any capture and before the
+    // systems run concurrently (a shape timed while other systems' kernels
+    // share the chip would be chosen on contended timings): the seed phase's
+    // one-column passes and the CG passes over the system's k columns
+    for (int i = 0; i < nsys && st == SC_OK; ++i) {
+        st = seed_pretune(sys[i].op, sys[i].mixed != 0, sw[i], s);
+        if (st == SC_OK && sys[i].k > 1)
+            st = cg_pretune(sys[i].op, sys[i].mixed, sys[i].k, base + plan[i].cg_off, plan[i].cg_bytes, s);
+    }
     if (st != SC_OK) {
         cleanup();
         return st;
@@ -265,34 +370,89 @@ sc_status batch_solve(int nsys, sc_batch_system* sys, void* work, size_t work_by
         return SC_ERR_HIP;
     }
 
-    // ---- per system: x^1, projection, CG (one thread and one stream each)
-    std::vector<sc_status> res(nsys, SC_OK);
+    // ---- per system: x^1 and the projection, enqueued on the system's stream
+    std::vector<sc_status> res(nsys, SC_OK), seed_st(nsys, SC_OK);
     std::vector<std::string> err(nsys);
-    auto finish = [&](int i) {
+    auto fail = [&](int i, sc_status r) {
+        res[i] = r;
+        if (r < 0) err[i] = sc_last_error();
+    };
+    for (int i = 0; i < nsys; ++i) {
         sc_batch_system& b = sys[i];
         const SysPlan& q = plan[i];
-        hipStream_t st_i = ss[i];
-        sc_status seed_status = SC_OK;
         sc_status r = seed_finalize_any(b.op, b.X_dev, base + q.v_off, b.op->n, q.vdt, (double*)(base + q.a_off),
-                                        (double*)(base + q.b_off), &b.m_done, sw[i], st_i, &seed_status);
-        if (r == SC_OK && (seed_status == SC_ERR_NOT_PD || seed_status == SC_ERR_NONFINITE)) r = seed_status;
+                                        (double*)(base + q.b_off), &b.m_done, sw[i], ss[i], &seed_st[i]);
+        if (r == SC_OK && (seed_st[i] == SC_ERR_NOT_PD || seed_st[i] == SC_ERR_NONFINITE)) r = seed_st[i];
         const size_t eb = dtype_bytes(b.op->dtype);
         if (r == SC_OK && b.k > 1 && b.m_done >= 1)
             r = project_impl(b.op->n, base + q.v_off, b.op->n, q.vdt, b.m_done, (double*)(base + q.a_off),
                              (double*)(base + q.b_off), b.op->dtype, (const char*)b.B_dev + b.ldb * eb, b.ldb, b.k - 1,
-                             (char*)b.X_dev + b.ldx * eb, b.ldx, base + q.proj_off, q.proj_bytes, st_i);
-        if (r == SC_OK)
-            r = solve_cg(b.op, b.mixed, b.B_dev, b.ldb, b.X_dev, b.ldx, b.k, b.tol, b.maxit, b.iters, b.relres,
-                         base + q.cg_off, q.cg_bytes, st_i);
-        if (r == SC_OK && seed_status == SC_BREAKDOWN) r = SC_BREAKDOWN;
-        b.status = r;
-        res[i] = r;
-        if (r < 0) err[i] = sc_last_error();
-    };
-    std::vector<std::thread> th;
-    for (int i = 1; i < nsys; ++i) th.emplace_back(finish, i);
-    finish(0);
-    for (auto& t : th) t.join();
+                             (char*)b.X_dev + b.ldx * eb, b.ldx, base + q.proj_off, q.proj_bytes, ss[i]);
+        fail(i, r);
+    }
+
+    // ---- CG of every system, advanced together from one host thread: each
+    // system's fixed chunk of kGraphChunk iterations (column masks on the
+    // device) is captured once into a graph, cached like the seed graph, and
+    // replayed on the system's stream; the host then checks every system
+    // (stall rules, reliable updates) and replays again
+    std::vector<std::unique_ptr<CGRun>> cg(nsys);
+    std::vector<hipGraphExec_t> chunk(nsys, nullptr);
+    std::vector<bool> done(nsys, true);
+    for (int i = 0; i < nsys; ++i) {
+        if (res[i] != SC_OK) continue;
+        sc_batch_system& b = sys[i];
+        sc_status r = SC_OK;
+        cg[i] = cg_make(b.op, b.mixed, b.B_dev, b.ldb, b.X_dev, b.ldx, b.k, b.tol, b.maxit, base + plan[i].cg_off,
+                        plan[i].cg_bytes, ss[i], &r);
+        if (cg[i]) r = cg[i]->start();
+        if (r == SC_OK) r = chunk_graph(sys[i], base + plan[i].cg_off, *cg[i], &chunk[i]);
+        if (r != SC_OK) {
+            fail(i, r);
+            cg[i].reset();
+            continue;
+        }
+        done[i] = false;
+    }
+    for (;;) {
+        bool left = false;
+        for (int i = 0; i < nsys; ++i)
+            if (!done[i] && cg[i]->any_active()) {
+                const sc_status r = chunk[i] ? (hipGraphLaunch(chunk[i], ss[i]) == hipSuccess ? SC_OK : SC_ERR_HIP)
+                                             : cg[i]->iterate(kGraphChunk);
+                if (r != SC_OK) {
+                    if (r == SC_ERR_HIP) set_error("batch_solve: chunk graph launch failed");
+                    fail(i, r);
+                    done[i] = true;
+                }
+            }
+        for (int i = 0; i < nsys; ++i) {
+            if (done[i]) continue;
+            sc_status r = SC_OK;
+            if (cg[i]->any_active()) {
+                bool any = false;
+                r = cg[i]->check(&any);
+            } else {
+                bool again = false;
+                r = cg[i]->verify(&again);
+                if (r == SC_OK && !again) {
+                    sc_batch_system& b = sys[i];
+                    cg[i]->results(b.iters, b.relres, &r);
+                    if (r == SC_OK && seed_st[i] == SC_BREAKDOWN) r = SC_BREAKDOWN;
+                    done[i] = true;
+                }
+            }
+            if (r < 0) {
+                fail(i, r);
+                done[i] = true;
+            } else if (done[i]) {
+                res[i] = r;
+            }
+            left |= !done[i];
+        }
+        if (!left) break;
+    }
+    for (int i = 0; i < nsys; ++i) sys[i].status = res[i];
     // join: the caller's stream waits for every system's stream
     bool joined = true;
     for (int i = 0; i < nsys; ++i)

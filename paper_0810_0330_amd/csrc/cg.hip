@@ -42,6 +42,7 @@
 
 #include <cmath>
 #include <limits>
+#include <memory>
 #include <vector>
 
 namespace sc {
@@ -351,6 +352,22 @@ size_t cg_workspace(const sc_op* op, int k, bool mixed) {
     return c.off + 256;
 }
 
+sc_status cg_pretune(const sc_op* op, int mixed, int k, void* work, size_t work_bytes, hipStream_t s) {
+    Carver c(work, work_bytes);
+    CGWork w = carve_cg(c, op, k, mixed != 0);
+    if (!c.ok()) {
+        set_error("cg_pretune: work buffer too small");
+        return SC_ERR_WORKSPACE;
+    }
+    // q = A p on k columns of the workspace: the first pass of (lattice,
+    // precision, k) runs the stencil autotuner, which the CG passes reuse
+    const bool cpl = is_complex(op->dtype);
+    const int64_t N2 = op->n * (cpl ? 2 : 1);
+    if (mixed) SC_TRY(fill<float>((float*)w.p, N2 * k, 0.0f, s));
+    else SC_TRY(fill<double>((double*)w.p, N2 * k, 0.0, s));
+    return op_apply(op, mixed != 0, w.p, op->n, w.q, op->n, k, w.tmp, s);
+}
+
 // r64 = b - A x (FP64) for k columns, rr[j] = ||r64_j||^2
 static sc_status true_residual(const sc_op* op, const double* B, int64_t ldb2, const double* X, int64_t ldx2, int k,
                                const CGWork& w, double* r64, int64_t ldr2, double* rr, hipStream_t s) {
@@ -363,268 +380,360 @@ static sc_status true_residual(const sc_op* op, const double* B, int64_t ldb2, c
     return SC_OK;
 }
 
+// The batched CG of k columns as a steppable object: start() forms the
+// residuals and column states (one host synchronisation); iterate(n) enqueues
+// n iterations and nothing else (no host interaction, so a fixed n can be
+// captured into a graph); check() reads the column states after iterations,
+// applies the stall rules and makes the due reliable updates; verify() runs
+// when no column is active: it checks every column's true residual and
+// restarts the ones still above tol.  solve_cg drives it with host checks
+// every chunk() iterations; the batch driver replays captured chunks of
+// kGraphChunk iterations for many systems at once.
 template <typename R, bool VEC>
-static sc_status cg_run(const sc_op* op, bool mixed, const double* B, int64_t ldb, double* X, int64_t ldx, int k,
-                        double tol, int maxit, int* iters, double* relres, const CGWork& w, hipStream_t s,
-                        sc_status* result) {
-    const bool cpl = is_complex(op->dtype);
-    const int64_t N2 = op->n * (cpl ? 2 : 1);
-    const int64_t mul = cpl ? 2 : 1;
-    const int64_t ldb2 = ldb * mul, ldx2 = ldx * mul;
-    const int vt = mixed ? 1 : 0;
-    R* r = (R*)w.r;
-    R* p = (R*)w.p;
-    R* q = (R*)w.q;
-    const dim3 blk(kBlock);
-    const int g = red_grid(N2);
-    const dim3 grid(g, k);
-    std::vector<CGCol> hst(k);
-    std::vector<double> hrr(k);
+class CGRunT final : public CGRun {
+   public:
+    CGRunT(const sc_op* op, bool mixed, const double* B, int64_t ldb, double* X, int64_t ldx, int k, double tol,
+           int maxit, const CGWork& w, hipStream_t s)
+        : op_(op), mixed_(mixed), B_(B), X_(X), k_(k), tol_(tol), maxit_(maxit), w_(w), s_(s) {
+        const bool cpl = is_complex(op->dtype);
+        N2_ = op->n * (cpl ? 2 : 1);
+        const int64_t mul = cpl ? 2 : 1;
+        ldb2_ = ldb * mul;
+        ldx2_ = ldx * mul;
+        ldx_ = ldx;
+        g_ = red_grid(N2_);
+        hst_.resize(k);
+        hrr_.resize(k);
+        chk_rho_.assign(k, 0.0);
+        chk_it_.assign(k, -1);
+        min_rho_.assign(k, kInf);
+        best_true_.assign(k, kInf);
+        it_min_.assign(k, 0);
+        nstall_.assign(k, 0);
+        relres_.assign(k, 0.0);
+    }
+
+    sc_status start() override {
+        const int vt = mixed_ ? 1 : 0;
+        R* r = (R*)w_.r;
+        R* p = (R*)w_.p;
+        hipStream_t s = s_;
+        SC_TRY(dot(0, B_, ldb2_, 0, B_, ldb2_, N2_, k_, w_.bn, w_.part, nullptr, s));
+        // r = b - A x; rho = ||r||^2
+        double* r64 = mixed_ ? w_.r64 : (double*)r;
+        SC_TRY(true_residual(op_, B_, ldb2_, X_, ldx2_, k_, w_, r64, N2_, w_.rho, s));
+        if (mixed_) {
+            SC_TRY(lincomb(1, r, N2_, 0, r64, N2_, 0, nullptr, 0, N2_, k_, 1.0, 0.0, s));
+            SC_TRY(fill<float>((float*)w_.xs, N2_ * k_, 0.0f, s));
+        }
+        SC_TRY(lincomb(vt, p, N2_, vt, r, N2_, 0, nullptr, 0, N2_, k_, 1.0, 0.0, s));
+        hipLaunchKernelGGL(k_cg_setup, dim3((k_ + 63) / 64), dim3(64), 0, s, w_.st[cur_], w_.rho, w_.bn, k_, tol_,
+                           maxit_, 1);
+        SC_LAUNCH_CHECK();
+        // columns with b = 0 are solved by x = 0
+        SC_HIP(hipMemcpyAsync(hst_.data(), w_.st[cur_], sizeof(CGCol) * k_, hipMemcpyDeviceToHost, s));
+        SC_HIP(hipStreamSynchronize(s));
+        for (int j = 0; j < k_; ++j)
+            if (!(hst_[j].bnorm2 > 0.0))
+                SC_TRY(lincomb(0, X_ + j * ldx2_, N2_, 0, X_ + j * ldx2_, N2_, 0, nullptr, 0, N2_, 1, 0.0, 0.0, s));
+        return SC_OK;
+    }
+
+    bool any_active() const override {
+        for (int j = 0; j < k_; ++j)
+            if (hst_[j].active) return true;
+        return false;
+    }
+
+    int chunk() const override { return chunk_; }
+    int state_index() const override { return cur_; }
+    hipStream_t stream() const override { return s_; }
+
+    sc_status iterate(int n) override {
+        R* r = (R*)w_.r;
+        R* p = (R*)w_.p;
+        R* q = (R*)w_.q;
+        const dim3 blk(kBlock), grid(g_, k_);
+        hipStream_t s = s_;
+        for (int it = 0; it < n; ++it) {
+            // fused form (Wilson, t-march shape): D pass with <p, A p> partials, D^H pass
+            // finishing r -= alpha A p, then x += alpha p and p = r + beta p
+            int gf = 0;
+            SC_TRY(wilson_cg_fused(op_, mixed_, p, w_.tmp, k_, w_.st[cur_], w_.part_pq, r, op_->n, w_.part_rr,
+                                   kMaxRedBlocks, &gf, s));
+            if (gf > 0) {
+                if (mixed_)
+                    hipLaunchKernelGGL((k_cg_xp<float, R, VEC>), grid, blk, 0, s, (float*)w_.xs, N2_, p, r, N2_, N2_,
+                                       w_.st[cur_], w_.st[1 - cur_], w_.part_pq, w_.part_rr, gf, 1);
+                else
+                    hipLaunchKernelGGL((k_cg_xp<double, R, VEC>), grid, blk, 0, s, X_, ldx2_, p, r, N2_, N2_,
+                                       w_.st[cur_], w_.st[1 - cur_], w_.part_pq, w_.part_rr, gf, 0);
+                SC_LAUNCH_CHECK();
+                cur_ = 1 - cur_;
+                continue;
+            }
+            // q = A p; for A = D^H D the D pass can also leave <p, q> = ||D p||^2
+            int gpq = 0;
+            SC_TRY(op_apply_norm(op_, mixed_, p, op_->n, q, op_->n, k_, w_.tmp, w_.part_pq, kMaxRedBlocks, &gpq, s));
+            if (gpq == 0) {
+                hipLaunchKernelGGL((k_cg_pq<R, VEC>), grid, blk, 0, s, p, q, N2_, N2_, w_.st[cur_], w_.part_pq);
+                SC_LAUNCH_CHECK();
+                gpq = g_;
+            }
+            if (mixed_)
+                hipLaunchKernelGGL((k_cg_xr<float, R, VEC>), grid, blk, 0, s, (float*)w_.xs, N2_, r, p, q, N2_, N2_,
+                                   w_.st[cur_], w_.part_pq, gpq, w_.part_rr);
+            else
+                hipLaunchKernelGGL((k_cg_xr<double, R, VEC>), grid, blk, 0, s, X_, ldx2_, r, p, q, N2_, N2_,
+                                   w_.st[cur_], w_.part_pq, gpq, w_.part_rr);
+            SC_LAUNCH_CHECK();
+            hipLaunchKernelGGL((k_cg_p<R, VEC>), grid, blk, 0, s, p, r, N2_, N2_, w_.st[cur_], w_.st[1 - cur_],
+                               w_.part_rr, g_, mixed_ ? 1 : 0);
+            SC_LAUNCH_CHECK();
+            cur_ = 1 - cur_;
+        }
+        return SC_OK;
+    }
+
+    sc_status check(bool* any_out) override {
+        hipStream_t s = s_;
+        R* r = (R*)w_.r;
+        SC_HIP(hipMemcpyAsync(hst_.data(), w_.st[cur_], sizeof(CGCol) * k_, hipMemcpyDeviceToHost, s));
+        SC_HIP(hipStreamSynchronize(s));
+        bool any = false;
+        std::vector<int> upd;
+        int need = 0;        // iterations the slowest active column still needs, as estimated
+        bool dirty = false;  // host-side state changes to copy back
+        for (int j = 0; j < k_; ++j) {
+            if (hst_[j].active) {
+                if (hst_[j].rho < 0.98 * min_rho_[j]) {
+                    min_rho_[j] = hst_[j].rho;
+                    it_min_[j] = hst_[j].iters;
+                } else if (hst_[j].iters - it_min_[j] >= kStallWindow) {
+                    stop_stalled(j);
+                    dirty = true;
+                    // a recursion that stopped falling may have left the solution
+                    // behind: the column keeps x as of its last reliable update
+                    if (mixed_) SC_TRY(fill<float>((float*)w_.xs + (int64_t)j * N2_, N2_, 0.0f, s));
+                }
+            }
+            any |= hst_[j].active != 0;
+            if (mixed_ && hst_[j].flag != 0 && hst_[j].iters < hst_[j].maxit) upd.push_back(j);
+            if (hst_[j].active) {
+                const int di = hst_[j].iters - chk_it_[j];
+                double est = kChunk;
+                if (chk_it_[j] >= 0 && di > 0 && hst_[j].rho < chk_rho_[j] && hst_[j].rho > hst_[j].tol2) {
+                    const double rate = std::log(hst_[j].rho / chk_rho_[j]) / di;  // < 0
+                    est = std::ceil(std::log(hst_[j].tol2 / hst_[j].rho) / rate);
+                }
+                need = std::max(need, (int)std::min<double>(kChunk, std::max(1.0, est)));
+            }
+            chk_rho_[j] = hst_[j].rho;
+            chk_it_[j] = hst_[j].iters;
+        }
+        chunk_ = need > 0 ? need : kChunk;
+        if (dirty && upd.empty()) {
+            SC_HIP(hipMemcpyAsync(w_.st[cur_], hst_.data(), sizeof(CGCol) * k_, hipMemcpyHostToDevice, s));
+            SC_HIP(hipStreamSynchronize(s));
+        }
+        if (!upd.empty()) {
+            // reliable update of the flagged columns (batched over the list):
+            // x64 += xs; xs = 0; r64 = b - A64 x64; r = r64; then the direction
+            const dim3 blk(kBlock);
+            const int nu = (int)upd.size();
+            const int gr = red_grid(N2_, 4);
+            SC_HIP(hipMemcpyAsync(w_.cols, upd.data(), sizeof(int) * nu, hipMemcpyHostToDevice, s));
+            const bool all = nu == k_;  // the list is then 0..k-1 in order
+            hipLaunchKernelGGL(k_ru_gather, dim3(gr, nu), blk, 0, s, w_.cols, X_, ldx2_, (float*)w_.xs,
+                               all ? nullptr : w_.xg, N2_);
+            SC_LAUNCH_CHECK();
+            if (all) SC_TRY(op_apply(op_, false, X_, ldx_, w_.ax64, op_->n, nu, w_.tmp64, s));
+            else SC_TRY(op_apply(op_, false, w_.xg, op_->n, w_.ax64, op_->n, nu, w_.tmp64, s));
+            hipLaunchKernelGGL(k_ru_resid, dim3(gr, nu), blk, 0, s, w_.cols, B_, ldb2_, w_.ax64, w_.r64, (float*)r,
+                               N2_, w_.part);
+            SC_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_dot_finish, dim3(nu), blk, 0, s, w_.part, gr, w_.rho);
+            SC_LAUNCH_CHECK();
+            SC_HIP(hipMemcpyAsync(hrr_.data(), w_.rho, sizeof(double) * nu, hipMemcpyDeviceToHost, s));
+            SC_HIP(hipStreamSynchronize(s));
+            std::vector<int> dl;
+            std::vector<double> db;
+            for (int c = 0; c < nu; ++c) {
+                const int j = upd[c];
+                CGCol& cc = hst_[j];
+                const double rr = hrr_[c];
+                const bool done = !(rr > cc.tol2);
+                // the true residual should have fallen with the recursive one; if
+                // it has not halved since the best one seen, or it is more than
+                // twice the recursive residual norm (cc.rho is the recursion's
+                // ||r||^2 at this check), the FP64 residual is at its rounding
+                // floor and the kept direction no longer matches it
+                const bool improved = rr < 0.5 * best_true_[j];
+                const bool consistent = rr <= 4.0 * cc.rho;
+                if (improved) {
+                    best_true_[j] = rr;
+                    nstall_[j] = 0;
+                } else if (!done) {
+                    ++nstall_[j];
+                }
+                if (!done && (cc.flag == 1 || !improved || !consistent)) {
+                    // the FP32 recurrence reached tol but the true residual did not,
+                    // or the true residual stopped following it: restart the
+                    // direction from the true residual
+                    dl.push_back(j);
+                    db.push_back(0.0);
+                }
+                // otherwise (flag 2) p was formed from the recursive residual and is
+                // kept; CG continues from the true residual (rho = ||r_true||^2)
+                cc.rho = rr;
+                cc.rho_prev = rr;
+                cc.rmax2 = rr;
+                cc.active = done ? 0 : 1;
+                cc.flag = 0;
+                min_rho_[j] = rr;
+                it_min_[j] = cc.iters;
+                if (!done && nstall_[j] >= kStallUpdates) stop_stalled(j);
+                any |= cc.active != 0;
+            }
+            if (!dl.empty()) {
+                SC_HIP(hipMemcpyAsync(w_.cols, dl.data(), sizeof(int) * dl.size(), hipMemcpyHostToDevice, s));
+                SC_HIP(hipMemcpyAsync(w_.ru_beta, db.data(), sizeof(double) * db.size(), hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(k_ru_dir, dim3(gr, (unsigned)dl.size()), blk, 0, s, w_.cols, w_.ru_beta,
+                                   (float*)w_.p, (const float*)r, N2_);
+                SC_LAUNCH_CHECK();
+            }
+            SC_HIP(hipMemcpyAsync(w_.st[cur_], hst_.data(), sizeof(CGCol) * k_, hipMemcpyHostToDevice, s));
+            SC_HIP(hipStreamSynchronize(s));
+            // the updated columns measure their decay from the true residual on
+            for (int c = 0; c < nu; ++c) {
+                chk_rho_[upd[c]] = hst_[upd[c]].rho;
+                chk_it_[upd[c]] = hst_[upd[c]].iters;
+            }
+        }
+        *any_out = any;
+        return SC_OK;
+    }
+
+    sc_status verify(bool* again_out) override {
+        hipStream_t s = s_;
+        const int vt = mixed_ ? 1 : 0;
+        R* r = (R*)w_.r;
+        R* p = (R*)w_.p;
+        double* r64 = mixed_ ? w_.r64 : (double*)r;
+        if (mixed_) {
+            // fold any remaining FP32 increment into x
+            SC_TRY(lincomb(0, X_, ldx2_, 0, X_, ldx2_, 1, w_.xs, N2_, N2_, k_, 1.0, 1.0, s));
+            SC_TRY(fill<float>((float*)w_.xs, N2_ * k_, 0.0f, s));
+        }
+        // verify on the true residual
+        SC_TRY(true_residual(op_, B_, ldb2_, X_, ldx2_, k_, w_, r64, N2_, w_.rho, s));
+        SC_HIP(hipMemcpyAsync(hrr_.data(), w_.rho, sizeof(double) * k_, hipMemcpyDeviceToHost, s));
+        SC_HIP(hipStreamSynchronize(s));
+        bool again = false;
+        for (int j = 0; j < k_; ++j) {
+            const double bn = hst_[j].bnorm2;
+            relres_[j] = bn > 0.0 ? std::sqrt(hrr_[j] / bn) : 0.0;
+            if (bn > 0.0 && !(relres_[j] <= tol_) && hst_[j].iters < hst_[j].maxit) again = true;
+        }
+        *again_out = false;
+        if (!again || restarts_ >= 5) return SC_OK;
+        ++restarts_;
+        // restart every column from its true residual (converged ones stay inactive)
+        if (mixed_) SC_TRY(lincomb(1, r, N2_, 0, w_.r64, N2_, 0, nullptr, 0, N2_, k_, 1.0, 0.0, s));
+        SC_TRY(lincomb(vt, p, N2_, vt, r, N2_, 0, nullptr, 0, N2_, k_, 1.0, 0.0, s));
+        hipLaunchKernelGGL(k_cg_setup, dim3((k_ + 63) / 64), dim3(64), 0, s, w_.st[cur_], w_.rho, w_.bn, k_, tol_,
+                           maxit_, 0);
+        SC_LAUNCH_CHECK();
+        SC_HIP(hipMemcpyAsync(hst_.data(), w_.st[cur_], sizeof(CGCol) * k_, hipMemcpyDeviceToHost, s));
+        SC_HIP(hipStreamSynchronize(s));
+        *again_out = true;
+        return SC_OK;
+    }
+
+    void results(int* iters, double* relres, sc_status* result) const override {
+        *result = SC_OK;
+        for (int j = 0; j < k_; ++j) {
+            iters[j] = hst_[j].iters;
+            relres[j] = relres_[j];
+            if (!(relres_[j] <= tol_)) *result = SC_NOT_CONVERGED;
+        }
+    }
+
+   private:
+    static constexpr double kInf = std::numeric_limits<double>::infinity();
     // iterations between host checks: at most kChunk, fewer when every active
     // column's residual decay since the previous check says it will reach tol
     // sooner (the check then comes when the last column converges)
-    constexpr int kChunk = 8;
-    int chunk = kChunk;
-    std::vector<double> chk_rho(k, 0.0);
-    std::vector<int> chk_it(k, -1);
-    int cur = 0;  // index of the state copy the next iteration reads
-    // stall detection (see the file header)
-    constexpr double kInf = std::numeric_limits<double>::infinity();
-    std::vector<double> min_rho(k, kInf), best_true(k, kInf);
-    std::vector<int> it_min(k, 0), nstall(k, 0);
-    auto stop_stalled = [&](int j) {
-        hst[j].active = 0;
-        hst[j].flag = 0;
-        hst[j].maxit = hst[j].iters;
-    };
+    static constexpr int kChunk = 8;
 
-    SC_TRY(dot(0, B, ldb2, 0, B, ldb2, N2, k, w.bn, w.part, nullptr, s));
-    // r = b - A x; rho = ||r||^2
-    double* r64 = mixed ? w.r64 : (double*)r;
-    SC_TRY(true_residual(op, B, ldb2, X, ldx2, k, w, r64, N2, w.rho, s));
+    void stop_stalled(int j) {
+        hst_[j].active = 0;
+        hst_[j].flag = 0;
+        hst_[j].maxit = hst_[j].iters;
+    }
+
+    const sc_op* op_;
+    bool mixed_;
+    const double* B_;
+    double* X_;
+    int k_;
+    double tol_;
+    int maxit_;
+    CGWork w_;
+    hipStream_t s_;
+    int64_t N2_ = 0, ldb2_ = 0, ldx2_ = 0, ldx_ = 0;
+    int g_ = 0;
+    int cur_ = 0;  // index of the state copy the next iteration reads
+    int chunk_ = kChunk;
+    int restarts_ = 0;
+    std::vector<CGCol> hst_;
+    std::vector<double> hrr_, chk_rho_, min_rho_, best_true_, relres_;
+    std::vector<int> chk_it_, it_min_, nstall_;
+};
+
+std::unique_ptr<CGRun> cg_make(const sc_op* op, int mixed, const void* B, int64_t ldb, void* X, int64_t ldx, int k,
+                               double tol, int maxit, void* work, size_t work_bytes, hipStream_t s, sc_status* st) {
+    Carver c(work, work_bytes);
+    CGWork w = carve_cg(c, op, k, mixed != 0);
+    *st = SC_OK;
+    if (!c.ok()) {
+        set_error("solve_cg: work buffer too small");
+        *st = SC_ERR_WORKSPACE;
+        return nullptr;
+    }
+    const bool cpl = is_complex(op->dtype);
+    const int64_t N2 = op->n * (cpl ? 2 : 1);
+    const int64_t mul = cpl ? 2 : 1;
+    const double* Bd = (const double*)B;
+    double* Xd = (double*)X;
     if (mixed) {
-        SC_TRY(lincomb(1, r, N2, 0, r64, N2, 0, nullptr, 0, N2, k, 1.0, 0.0, s));
-        SC_TRY(fill<float>((float*)w.xs, N2 * k, 0.0f, s));
+        // packs of 4 floats: columns of r, p, q, xs are N2 floats apart
+        if ((N2 % 4) == 0) return std::make_unique<CGRunT<float, true>>(op, true, Bd, ldb, Xd, ldx, k, tol, maxit, w, s);
+        return std::make_unique<CGRunT<float, false>>(op, true, Bd, ldb, Xd, ldx, k, tol, maxit, w, s);
     }
-    SC_TRY(lincomb(vt, p, N2, vt, r, N2, 0, nullptr, 0, N2, k, 1.0, 0.0, s));
-    hipLaunchKernelGGL(k_cg_setup, dim3((k + 63) / 64), dim3(64), 0, s, w.st[cur], w.rho, w.bn, k, tol, maxit, 1);
-    SC_LAUNCH_CHECK();
-
-    // columns with b = 0 are solved by x = 0
-    SC_HIP(hipMemcpyAsync(hst.data(), w.st[cur], sizeof(CGCol) * k, hipMemcpyDeviceToHost, s));
-    SC_HIP(hipStreamSynchronize(s));
-    for (int j = 0; j < k; ++j)
-        if (!(hst[j].bnorm2 > 0.0)) SC_TRY(lincomb(0, X + j * ldx2, N2, 0, X + j * ldx2, N2, 0, nullptr, 0, N2, 1, 0.0, 0.0, s));
-
-    int restarts = 0;
-    for (;;) {
-        bool any = false;
-        for (int j = 0; j < k; ++j) any |= hst[j].active != 0;
-        while (any) {
-            for (int it = 0; it < chunk; ++it) {
-                // fused form (Wilson, t-march shape): D pass with <p, A p> partials, D^H pass
-                // finishing r -= alpha A p, then x += alpha p and p = r + beta p
-                int gf = 0;
-                SC_TRY(wilson_cg_fused(op, mixed, p, w.tmp, k, w.st[cur], w.part_pq, r, op->n, w.part_rr,
-                                       kMaxRedBlocks, &gf, s));
-                if (gf > 0) {
-                    if (mixed)
-                        hipLaunchKernelGGL((k_cg_xp<float, R, VEC>), grid, blk, 0, s, (float*)w.xs, N2, p, r, N2, N2,
-                                           w.st[cur], w.st[1 - cur], w.part_pq, w.part_rr, gf, 1);
-                    else
-                        hipLaunchKernelGGL((k_cg_xp<double, R, VEC>), grid, blk, 0, s, X, ldx2, p, r, N2, N2,
-                                           w.st[cur], w.st[1 - cur], w.part_pq, w.part_rr, gf, 0);
-                    SC_LAUNCH_CHECK();
-                    cur = 1 - cur;
-                    continue;
-                }
-                // q = A p; for A = D^H D the D pass can also leave <p, q> = ||D p||^2
-                int gpq = 0;
-                SC_TRY(op_apply_norm(op, mixed, p, op->n, q, op->n, k, w.tmp, w.part_pq, kMaxRedBlocks, &gpq, s));
-                if (gpq == 0) {
-                    hipLaunchKernelGGL((k_cg_pq<R, VEC>), grid, blk, 0, s, p, q, N2, N2, w.st[cur], w.part_pq);
-                    SC_LAUNCH_CHECK();
-                    gpq = g;
-                }
-                if (mixed)
-                    hipLaunchKernelGGL((k_cg_xr<float, R, VEC>), grid, blk, 0, s, (float*)w.xs, N2, r, p, q, N2, N2,
-                                       w.st[cur], w.part_pq, gpq, w.part_rr);
-                else
-                    hipLaunchKernelGGL((k_cg_xr<double, R, VEC>), grid, blk, 0, s, X, ldx2, r, p, q, N2, N2,
-                                       w.st[cur], w.part_pq, gpq, w.part_rr);
-                SC_LAUNCH_CHECK();
-                hipLaunchKernelGGL((k_cg_p<R, VEC>), grid, blk, 0, s, p, r, N2, N2, w.st[cur], w.st[1 - cur],
-                                   w.part_rr, g, mixed ? 1 : 0);
-                SC_LAUNCH_CHECK();
-                cur = 1 - cur;
-            }
-            SC_HIP(hipMemcpyAsync(hst.data(), w.st[cur], sizeof(CGCol) * k, hipMemcpyDeviceToHost, s));
-            SC_HIP(hipStreamSynchronize(s));
-            any = false;
-            std::vector<int> upd;
-            int need = 0;  // iterations the slowest active column still needs, as estimated
-            bool dirty = false;  // host-side state changes to copy back
-            for (int j = 0; j < k; ++j) {
-                if (hst[j].active) {
-                    if (hst[j].rho < 0.98 * min_rho[j]) {
-                        min_rho[j] = hst[j].rho;
-                        it_min[j] = hst[j].iters;
-                    } else if (hst[j].iters - it_min[j] >= kStallWindow) {
-                        stop_stalled(j);
-                        dirty = true;
-                        // a recursion that stopped falling may have left the solution
-                        // behind: the column keeps x as of its last reliable update
-                        if (mixed) SC_TRY(fill<float>((float*)w.xs + (int64_t)j * N2, N2, 0.0f, s));
-                    }
-                }
-                any |= hst[j].active != 0;
-                if (mixed && hst[j].flag != 0 && hst[j].iters < hst[j].maxit) upd.push_back(j);
-                if (hst[j].active) {
-                    const int di = hst[j].iters - chk_it[j];
-                    double est = kChunk;
-                    if (chk_it[j] >= 0 && di > 0 && hst[j].rho < chk_rho[j] && hst[j].rho > hst[j].tol2) {
-                        const double rate = std::log(hst[j].rho / chk_rho[j]) / di;  // < 0
-                        est = std::ceil(std::log(hst[j].tol2 / hst[j].rho) / rate);
-                    }
-                    need = std::max(need, (int)std::min<double>(kChunk, std::max(1.0, est)));
-                }
-                chk_rho[j] = hst[j].rho;
-                chk_it[j] = hst[j].iters;
-            }
-            chunk = need > 0 ? need : kChunk;
-            if (dirty && upd.empty()) {
-                SC_HIP(hipMemcpyAsync(w.st[cur], hst.data(), sizeof(CGCol) * k, hipMemcpyHostToDevice, s));
-                SC_HIP(hipStreamSynchronize(s));
-            }
-            if (!upd.empty()) {
-                // reliable update of the flagged columns (batched over the list):
-                // x64 += xs; xs = 0; r64 = b - A64 x64; r = r64; then the direction
-                const int nu = (int)upd.size();
-                const int gr = red_grid(N2, 4);
-                SC_HIP(hipMemcpyAsync(w.cols, upd.data(), sizeof(int) * nu, hipMemcpyHostToDevice, s));
-                const bool all = nu == k;  // the list is then 0..k-1 in order
-                hipLaunchKernelGGL(k_ru_gather, dim3(gr, nu), blk, 0, s, w.cols, X, ldx2, (float*)w.xs,
-                                   all ? nullptr : w.xg, N2);
-                SC_LAUNCH_CHECK();
-                if (all) SC_TRY(op_apply(op, false, X, ldx, w.ax64, op->n, nu, w.tmp64, s));
-                else SC_TRY(op_apply(op, false, w.xg, op->n, w.ax64, op->n, nu, w.tmp64, s));
-                hipLaunchKernelGGL(k_ru_resid, dim3(gr, nu), blk, 0, s, w.cols, B, ldb2, w.ax64, w.r64, (float*)r, N2,
-                                   w.part);
-                SC_LAUNCH_CHECK();
-                hipLaunchKernelGGL(k_dot_finish, dim3(nu), blk, 0, s, w.part, gr, w.rho);
-                SC_LAUNCH_CHECK();
-                SC_HIP(hipMemcpyAsync(hrr.data(), w.rho, sizeof(double) * nu, hipMemcpyDeviceToHost, s));
-                SC_HIP(hipStreamSynchronize(s));
-                std::vector<double> hb(nu);
-                std::vector<int> dl;
-                std::vector<double> db;
-                for (int c = 0; c < nu; ++c) {
-                    const int j = upd[c];
-                    CGCol& cc = hst[j];
-                    const double rr = hrr[c];
-                    const bool done = !(rr > cc.tol2);
-                    // the true residual should have fallen with the recursive one; if
-                    // it has not halved since the best one seen, or it is more than
-                    // twice the recursive residual norm (cc.rho is the recursion's
-                    // ||r||^2 at this check), the FP64 residual is at its rounding
-                    // floor and the kept direction no longer matches it
-                    const bool improved = rr < 0.5 * best_true[j];
-                    const bool consistent = rr <= 4.0 * cc.rho;
-                    if (improved) {
-                        best_true[j] = rr;
-                        nstall[j] = 0;
-                    } else if (!done) {
-                        ++nstall[j];
-                    }
-                    if (!done && (cc.flag == 1 || !improved || !consistent)) {
-                        // the FP32 recurrence reached tol but the true residual did not,
-                        // or the true residual stopped following it: restart the
-                        // direction from the true residual
-                        dl.push_back(j);
-                        db.push_back(0.0);
-                    }
-                    // otherwise (flag 2) p was formed from the recursive residual and is
-                    // kept; CG continues from the true residual (rho = ||r_true||^2)
-                    cc.rho = rr;
-                    cc.rho_prev = rr;
-                    cc.rmax2 = rr;
-                    cc.active = done ? 0 : 1;
-                    cc.flag = 0;
-                    min_rho[j] = rr;
-                    it_min[j] = cc.iters;
-                    if (!done && nstall[j] >= kStallUpdates) stop_stalled(j);
-                    any |= cc.active != 0;
-                }
-                if (!dl.empty()) {
-                    SC_HIP(hipMemcpyAsync(w.cols, dl.data(), sizeof(int) * dl.size(), hipMemcpyHostToDevice, s));
-                    SC_HIP(hipMemcpyAsync(w.ru_beta, db.data(), sizeof(double) * db.size(), hipMemcpyHostToDevice, s));
-                    hipLaunchKernelGGL(k_ru_dir, dim3(gr, (unsigned)dl.size()), blk, 0, s, w.cols, w.ru_beta, (float*)p,
-                                       (const float*)r, N2);
-                    SC_LAUNCH_CHECK();
-                }
-                SC_HIP(hipMemcpyAsync(w.st[cur], hst.data(), sizeof(CGCol) * k, hipMemcpyHostToDevice, s));
-                SC_HIP(hipStreamSynchronize(s));
-                // the updated columns measure their decay from the true residual on
-                for (int c = 0; c < nu; ++c) {
-                    chk_rho[upd[c]] = hst[upd[c]].rho;
-                    chk_it[upd[c]] = hst[upd[c]].iters;
-                }
-            }
-        }
-        if (mixed) {
-            // fold any remaining FP32 increment into x
-            SC_TRY(lincomb(0, X, ldx2, 0, X, ldx2, 1, w.xs, N2, N2, k, 1.0, 1.0, s));
-            SC_TRY(fill<float>((float*)w.xs, N2 * k, 0.0f, s));
-        }
-        // verify on the true residual
-        SC_TRY(true_residual(op, B, ldb2, X, ldx2, k, w, r64, N2, w.rho, s));
-        SC_HIP(hipMemcpyAsync(hrr.data(), w.rho, sizeof(double) * k, hipMemcpyDeviceToHost, s));
-        SC_HIP(hipStreamSynchronize(s));
-        bool again = false;
-        for (int j = 0; j < k; ++j) {
-            const double bn = hst[j].bnorm2;
-            relres[j] = bn > 0.0 ? std::sqrt(hrr[j] / bn) : 0.0;
-            iters[j] = hst[j].iters;
-            if (bn > 0.0 && !(relres[j] <= tol) && hst[j].iters < hst[j].maxit) again = true;
-        }
-        if (!again || restarts >= 5) break;
-        ++restarts;
-        // restart every column from its true residual (converged ones stay inactive)
-        if (mixed) SC_TRY(lincomb(1, r, N2, 0, w.r64, N2, 0, nullptr, 0, N2, k, 1.0, 0.0, s));
-        SC_TRY(lincomb(vt, p, N2, vt, r, N2, 0, nullptr, 0, N2, k, 1.0, 0.0, s));
-        hipLaunchKernelGGL(k_cg_setup, dim3((k + 63) / 64), dim3(64), 0, s, w.st[cur], w.rho, w.bn, k, tol, maxit, 0);
-        SC_LAUNCH_CHECK();
-        SC_HIP(hipMemcpyAsync(hst.data(), w.st[cur], sizeof(CGCol) * k, hipMemcpyDeviceToHost, s));
-        SC_HIP(hipStreamSynchronize(s));
-    }
-    *result = SC_OK;
-    for (int j = 0; j < k; ++j)
-        if (!(relres[j] <= tol)) *result = SC_NOT_CONVERGED;
-    return SC_OK;
+    const bool vec = (N2 % 2) == 0 && ((uintptr_t)X % 16) == 0 && ((ldx * mul) % 2) == 0;
+    if (vec) return std::make_unique<CGRunT<double, true>>(op, false, Bd, ldb, Xd, ldx, k, tol, maxit, w, s);
+    return std::make_unique<CGRunT<double, false>>(op, false, Bd, ldb, Xd, ldx, k, tol, maxit, w, s);
 }
 
 sc_status solve_cg(const sc_op* op, int mixed, const void* B, int64_t ldb, void* X, int64_t ldx, int k, double tol,
                    int maxit, int* iters, double* relres, void* work, size_t work_bytes, hipStream_t s) {
-    Carver c(work, work_bytes);
-    CGWork w = carve_cg(c, op, k, mixed != 0);
-    if (!c.ok()) {
-        set_error("solve_cg: work buffer too small");
-        return SC_ERR_WORKSPACE;
+    sc_status st = SC_OK;
+    std::unique_ptr<CGRun> cg = cg_make(op, mixed, B, ldb, X, ldx, k, tol, maxit, work, work_bytes, s, &st);
+    if (!cg) return st;
+    SC_TRY(cg->start());
+    for (;;) {
+        bool any = cg->any_active();
+        while (any) {
+            SC_TRY(cg->iterate(cg->chunk()));
+            SC_TRY(cg->check(&any));
+        }
+        bool again = false;
+        SC_TRY(cg->verify(&again));
+        if (!again) break;
     }
     sc_status result = SC_OK;
-    const bool cpl = is_complex(op->dtype);
-    const int64_t N2 = op->n * (cpl ? 2 : 1);
-    const int64_t mul = cpl ? 2 : 1;
-    if (mixed) {
-        // packs of 4 floats: columns of r, p, q, xs are N2 floats apart
-        const bool vec = (N2 % 4) == 0;
-        if (vec) SC_TRY((cg_run<float, true>(op, true, (const double*)B, ldb, (double*)X, ldx, k, tol, maxit, iters, relres, w, s, &result)));
-        else SC_TRY((cg_run<float, false>(op, true, (const double*)B, ldb, (double*)X, ldx, k, tol, maxit, iters, relres, w, s, &result)));
-    } else {
-        const bool vec = (N2 % 2) == 0 && ((uintptr_t)X % 16) == 0 && ((ldx * mul) % 2) == 0;
-        if (vec) SC_TRY((cg_run<double, true>(op, false, (const double*)B, ldb, (double*)X, ldx, k, tol, maxit, iters, relres, w, s, &result)));
-        else SC_TRY((cg_run<double, false>(op, false, (const double*)B, ldb, (double*)X, ldx, k, tol, maxit, iters, relres, w, s, &result)));
-    }
+    cg->results(iters, relres, &result);
     if (result == SC_NOT_CONVERGED)
         set_error("solve_cg: some right-hand side is above tol (iteration limit reached or residual stalled)");
     return result;

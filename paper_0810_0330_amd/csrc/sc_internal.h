@@ -2,6 +2,8 @@
 // host drivers.
 #pragma once
 
+#include <memory>
+
 #include "sc_common.h"
 
 enum sc_op_kind { SC_OPK_LAPLACE2D = 0, SC_OPK_DIAG = 1, SC_OPK_WILSON = 2, SC_OPK_WILSON_G5 = 3 };
@@ -160,6 +162,33 @@ sc_status project_impl(int64_t n, const void* V, int64_t ldv, sc_dtype vdt, int 
                        const double* beta, sc_dtype xdt, const void* R0, int64_t ldr, int k, void* X, int64_t ldx,
                        void* work, size_t work_bytes, hipStream_t s);
 size_t cg_workspace(const sc_op* op, int k, bool mixed);
+// The batched CG of solve_cg as a steppable object (cg.hip): start() forms the
+// residuals and column states (one host synchronisation); iterate(n) enqueues
+// n iterations and nothing else, so a fixed n can be captured into a graph;
+// check() reads the column states, applies the stall rules and makes the due
+// reliable updates; verify() checks every column's true residual once none is
+// active and restarts those above tol (again = true).  state_index() is the
+// copy of the double-buffered column state the next iteration reads (an even
+// number of iterations returns to it).
+class CGRun {
+   public:
+    virtual ~CGRun() = default;
+    virtual sc_status start() = 0;
+    virtual bool any_active() const = 0;
+    virtual int chunk() const = 0;
+    virtual int state_index() const = 0;
+    virtual hipStream_t stream() const = 0;
+    virtual sc_status iterate(int n) = 0;
+    virtual sc_status check(bool* any) = 0;
+    virtual sc_status verify(bool* again) = 0;
+    virtual void results(int* iters, double* relres, sc_status* result) const = 0;
+};
+// the CG of solve_cg on the caller's work buffer (null and *st set on error)
+std::unique_ptr<CGRun> cg_make(const sc_op* op, int mixed, const void* B, int64_t ldb, void* X, int64_t ldx, int k,
+                               double tol, int maxit, void* work, size_t work_bytes, hipStream_t s, sc_status* st);
+// one k-column pass through the CG workspace, so that the stencil shape of the
+// CG passes is tuned now (e.g. before systems start running concurrently)
+sc_status cg_pretune(const sc_op* op, int mixed, int k, void* work, size_t work_bytes, hipStream_t s);
 sc_status solve_cg(const sc_op* op, int mixed, const void* B, int64_t ldb, void* X, int64_t ldx, int k, double tol,
                    int maxit, int* iters, double* relres, void* work, size_t work_bytes, hipStream_t s);
 

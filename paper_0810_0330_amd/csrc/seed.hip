@@ -222,14 +222,20 @@ __global__ __launch_bounds__(kBlock) void k_lz_f(R* __restrict__ f, const R* __r
 // For the Wilson normal operator the two stencil passes of a Lanczos step carry
 // the neighbouring vector work, on the direction-split launch shape (a block
 // covers 64 sites, wave w the hops of direction w; partial results meet in
-// LDS):
-//   D pass of step i >= 2 = step 9 of step i - 1 + the pass: beta_{i-1} = ||f||
-//     from the partials (the checks of k_lz_next), v_i = f / beta_{i-1} stored
-//     for the block's sites, and D v_i = (D f) / beta_{i-1};
-//   D^H pass of step i = the pass + the first half of step 5:
-//     f = D^H (D v_i) - beta_{i-1} v_{i-1} and the partials of Re(v_i^H f),
-//     one per 64-site tile.
-// The arithmetic of the recurrence is that of the separate kernels.
+// LDS).  Two launches per step i >= 2:
+//   D pass = step 9 of step i - 1 + the pass: beta_{i-1} = ||f|| from the
+//     partials (the checks of k_lz_next), v_i = f / beta_{i-1} stored for the
+//     block's sites, D v_i = (D f) / beta_{i-1}, and per 64-site tile the
+//     partials of ||D v_i||^2 and of Re(v_i^H v_{i-1});
+//   D^H pass = the pass + step 5: alpha_i = ||D v_i||^2 - beta_{i-1}
+//     Re(v_i^H v_{i-1}) from those partials (with the LU pivot of step 6),
+//     f = D^H (D v_i) - beta_{i-1} v_{i-1} - alpha_i v_i, and per tile the
+//     partials of ||f||^2 for the next D pass.
+// For A = D^H D, v^H A v = ||D v||^2, so this alpha_i is step 5's
+// v_i^H (A v_i - beta_{i-1} v_{i-1}) in exact arithmetic; it is known before
+// the D^H pass, which can then form the final f itself.  Step 1 (no v_0) takes
+// the three-launch form: D^H pass with the partials of Re(v_1^H f), then
+// k_lz_f.
 
 // sum over the 4 direction waves of component j of spin mu, for lane l
 template <typename R>
@@ -250,11 +256,38 @@ __device__ __forceinline__ void dir_stash(R (*red)[24][64], int mu, int l, const
         }
 }
 
+// The partials a fused pass needs, loaded into registers before its hops so
+// that their latency overlaps the hops' own loads: the first kPre * kBlock of
+// the G partials (the whole array up to 2048 tiles), the rest summed later.
+// part_sum adds them in the order of sum_partials, so every block gets the
+// same, deterministic total.
+constexpr int kPre = 8;
+struct PartPre {
+    double v[kPre];
+};
+__device__ __forceinline__ PartPre part_load(const double* __restrict__ part, int G) {
+    PartPre q;
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const int j = (int)threadIdx.x + u * kBlock;
+        q.v[u] = j < G ? part[j] : 0.0;
+    }
+    return q;
+}
+__device__ __forceinline__ double part_sum(const PartPre& q, const double* __restrict__ part, int G, double* sh) {
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) s += q.v[u];
+    for (int j = (int)threadIdx.x + kPre * kBlock; j < G; j += kBlock) s += part[j];
+    return block_sum(s, sh);
+}
+
 template <typename R, typename VT>
 __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const R* __restrict__ f,
-                                                     VT* __restrict__ vnext, const R* __restrict__ U, Geom g, R kappa,
-                                                     R tsign, int ntile, int per_xcd, double* beta, int im1,
-                                                     SeedState* st, const double* part, int G) {
+                                                     VT* __restrict__ vnext, const VT* __restrict__ vprev,
+                                                     const R* __restrict__ U, Geom g, R kappa, R tsign, int ntile,
+                                                     int per_xcd, double* beta, int im1, SeedState* st,
+                                                     const double* part, int G, double* part_a) {
     __shared__ R red[4][24][64];
     __shared__ double sh[kWaves];
     if (st->halt) return;
@@ -272,9 +305,10 @@ __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const 
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
+    const PartPre pf = part_load(part, G);
     if (ok) dir_hops<false, R>(acc, f, U, g, uV, s, mu, tsign);
     dir_stash(red, mu, l, acc);
-    const double bn = sqrt(sum_partials(part, G, sh));  // its barriers also order the stash
+    const double bn = sqrt(part_sum(pf, part, G, sh));  // its barriers also order the stash
     const bool fin = isfinite(bn);
     const bool brk = fin && !(bn > kBreakdownTol * st->amax);
     if (b == 0 && threadIdx.x == 0) {  // block 0 always holds a tile
@@ -301,18 +335,29 @@ __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const 
                     typename vec2<VT>::type{VT(0), VT(0)};
         return;
     }
-    if (!ok) return;
     const R bR = (R)bn;
+    double dacc = 0.0, pacc = 0.0;  // ||D v_i||^2 and Re(v_i^H v_{i-1}) over the lane's 3 components
+    if (ok) {
 #pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-        const cplx<R> h = dir_total(red, mu, cc, l);
-        const size_t cb = 2 * (size_t)((mu * 3 + cc) * uV);
-        const cplx<R> fv = ldc(f + cb, (unsigned)s);
-        const cplx<R> v = {fv.re / bR, fv.im / bR};                              // v_i = f / beta
-        const cplx<R> r = {(fv.re - kappa * h.re) / bR, (fv.im - kappa * h.im) / bR};  // D v_i
-        reinterpret_cast<typename vec2<R>::type*>(tmp + cb)[s] = typename vec2<R>::type{r.re, r.im};
-        reinterpret_cast<typename vec2<VT>::type*>(vnext)[(mu * 3 + cc) * uV + s] =
-            typename vec2<VT>::type{(VT)v.re, (VT)v.im};
+        for (int cc = 0; cc < 3; ++cc) {
+            const cplx<R> h = dir_total(red, mu, cc, l);
+            const size_t cb = 2 * (size_t)((mu * 3 + cc) * uV);
+            const cplx<R> fv = ldc(f + cb, (unsigned)s);
+            const cplx<R> v = {fv.re / bR, fv.im / bR};                              // v_i = f / beta
+            const cplx<R> r = {(fv.re - kappa * h.re) / bR, (fv.im - kappa * h.im) / bR};  // D v_i
+            const typename vec2<VT>::type vs{(VT)v.re, (VT)v.im};
+            const typename vec2<VT>::type pv = reinterpret_cast<const typename vec2<VT>::type*>(vprev)[(mu * 3 + cc) * uV + s];
+            reinterpret_cast<typename vec2<R>::type*>(tmp + cb)[s] = typename vec2<R>::type{r.re, r.im};
+            reinterpret_cast<typename vec2<VT>::type*>(vnext)[(mu * 3 + cc) * uV + s] = vs;
+            dacc += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
+            pacc += (double)vs.x * (double)pv.x + (double)vs.y * (double)pv.y;
+        }
+    }
+    const double dt = block_sum(dacc, sh);
+    const double pt = block_sum(pacc, sh);
+    if (threadIdx.x == 0) {
+        part_a[L] = dt;
+        part_a[ntile + L] = pt;
     }
 }
 
@@ -360,6 +405,76 @@ __global__ __launch_bounds__(kBlock) void k_lz_dhalpha(R* __restrict__ f, const 
     if (threadIdx.x == 0) part[L] = tot;
 }
 
+// D^H pass of step i >= 2: alpha_i from the D pass's partials, the pivot of
+// step 6, and the final f = D^H (D v_i) - beta_{i-1} v_{i-1} - alpha_i v_i with
+// the partials of ||f||^2
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_lz_dhf(R* __restrict__ f, const R* __restrict__ tmp,
+                                                   const R* __restrict__ vi, const R* __restrict__ vprev,
+                                                   const R* __restrict__ U, Geom g, R kappa, R tsign, int ntile,
+                                                   int per_xcd, double* alpha, const double* beta, double* delta,
+                                                   int i, SeedState* st, const double* part_a, double* part_f,
+                                                   int indef) {
+    __shared__ R red[4][24][64];
+    __shared__ double sh[kWaves];
+    if (st->halt) return;
+    const int b = blockIdx.x;
+    const int L = (b % kXcd) * per_xcd + b / kXcd;
+    if (L >= ntile) return;  // uniform over the block
+    const int mu = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int s = L * 64 + l;
+    const bool ok = s < (int)g.V;
+    const unsigned uV = (unsigned)g.V;
+    cplx<R> acc[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
+    const PartPre pd = part_load(part_a, ntile), pp = part_load(part_a + ntile, ntile);
+    if (ok) dir_hops<true, R>(acc, tmp, U, g, uV, s, mu, tsign);
+    dir_stash(red, mu, l, acc);
+    // alpha_i (its barriers also order the stash); every block adds the same
+    // partials in the same order, so every block gets the same alpha
+    const double dn = part_sum(pd, part_a, ntile, sh);
+    const double pr = part_sum(pp, part_a + ntile, ntile, sh);
+    const double bp = beta[i - 1];
+    const double a = dn - bp * pr;
+    const double d = a - bp * bp / delta[i - 1];  // the LU pivot of step 6
+    const bool bad = !isfinite(a) || (!indef && !(d > 0.0));
+    if (b == 0 && threadIdx.x == 0) {  // block 0 always holds a tile
+        alpha[i - 1] = a;
+        delta[i] = d;
+        if (bad) {
+            st->status = isfinite(a) ? SC_ERR_NOT_PD : SC_ERR_NONFINITE;
+            st->halt_step = i;
+            st->m_done = i - 1;
+            st->halt = 1;
+        } else {
+            st->amax = fmax(st->amax, fabs(a));
+        }
+    }
+    if (bad) return;
+    const R bR = (R)bp, aR = (R)a;
+    double facc = 0.0;
+    if (ok) {
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            const cplx<R> h = dir_total(red, mu, cc, l);
+            const size_t cb = 2 * (size_t)((mu * 3 + cc) * uV);
+            const cplx<R> t = ldc(tmp + cb, (unsigned)s);
+            const cplx<R> av = {t.re - kappa * h.re, t.im - kappa * h.im};  // A v_i = D^H (D v_i)
+            const cplx<R> pv = ldc(vprev + cb, (unsigned)s);
+            const cplx<R> v = ldc(vi + cb, (unsigned)s);
+            cplx<R> fv = {av.re - bR * pv.re, av.im - bR * pv.im};
+            fv = {fv.re - aR * v.re, fv.im - aR * v.im};
+            reinterpret_cast<typename vec2<R>::type*>(f + cb)[s] = typename vec2<R>::type{fv.re, fv.im};
+            facc += (double)fv.re * (double)fv.re + (double)fv.im * (double)fv.im;
+        }
+    }
+    const double tot = block_sum(facc, sh);
+    if (threadIdx.x == 0) part_f[L] = tot;
+}
+
 // v /= ||v|| (norm from partials)
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_scale_norm(R* __restrict__ v, int64_t N, const double* part, int G,
@@ -384,8 +499,10 @@ static SeedWork carve_seed(Carver& c, const sc_op* op, int m, bool single) {
     w.r64 = c.take<double>(N2);
     w.ax64 = c.take<double>(N2);
     w.tmp64 = c.take<double>(std::max<int64_t>(tmpn, 1));
-    w.part_a = c.take<double>(std::max<int64_t>(kMaxRedBlocks, (op->n / 12 + 63) / 64));
-    w.part_f = c.take<double>(kMaxRedBlocks);
+    // per 64-site tile: two partials from the fused D pass, one of ||f||^2 from the fused D^H pass
+    const int64_t ntile = (op->n / 12 + 63) / 64;
+    w.part_a = c.take<double>(std::max<int64_t>(kMaxRedBlocks, 2 * ntile));
+    w.part_f = c.take<double>(std::max<int64_t>(kMaxRedBlocks, ntile));
     w.part_v = c.take<double>(kMaxRedBlocks);
     w.delta = c.take<double>((size_t)m + 2);
     w.st = c.take<SeedState>(1);
@@ -449,16 +566,9 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
         R* vi = V + (int64_t)(i - 1) * ldv2;
         R* vprev = i > 1 ? V + (int64_t)(i - 2) * ldv2 : vi;
         R* vnext = V + (int64_t)i * ldv2;
-        if (fused) {
-            // D pass (with step 9 of step i - 1 for i >= 2), then D^H pass with the first half of step 5
-            if (i == 1) {
-                SC_TRY(wilson_pass(op, single, 0, vi, ldv, tmpv, op->n, 1, s));
-            } else {
-                TimerScope ts_(tcls, s, pass_bytes + 24.0 * sizeof(R) * op->vol, 1368.0 * op->vol);
-                SC_TLAUNCH((k_lz_dnext<R, R>), dgrid, blk, 0, s, tmpv, (const R*)f, vi, U, geo, kapR, tsg,
-                                   ntile, per_xcd, beta, i - 1, w.st, w.part_f, gf);
-                SC_LAUNCH_CHECK();
-            }
+        if (fused && i == 1) {
+            // D pass, D^H pass with the partials of Re(v_1^H f), then k_lz_f applies alpha_1
+            SC_TRY(wilson_pass(op, single, 0, vi, ldv, tmpv, op->n, 1, s));
             {
                 TimerScope ts_(tcls, s, pass_bytes + 48.0 * sizeof(R) * op->vol, 1368.0 * op->vol);
                 SC_TLAUNCH((k_lz_dhalpha<R>), dgrid, blk, 0, s, f, (const R*)tmpv, (const R*)vi,
@@ -468,6 +578,24 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
             hipLaunchKernelGGL((k_lz_f<R, VEC>), dim3(g), blk, 0, s, f, vi, N2, alpha, beta, w.delta, i, w.st,
                                w.part_a, ntile, w.part_f, indef);
             SC_LAUNCH_CHECK();
+            gf = g;
+        } else if (fused) {
+            // D pass with step 9 of step i - 1 and the partials of alpha_i, then the
+            // D^H pass with step 5 (alpha_i, the pivot, the final f, its norm partials)
+            {
+                TimerScope ts_(tcls, s, pass_bytes + 48.0 * sizeof(R) * op->vol, 1368.0 * op->vol);
+                SC_TLAUNCH((k_lz_dnext<R, R>), dgrid, blk, 0, s, tmpv, (const R*)f, vi, (const R*)vprev, U, geo,
+                                   kapR, tsg, ntile, per_xcd, beta, i - 1, w.st, w.part_f, gf, w.part_a);
+                SC_LAUNCH_CHECK();
+            }
+            {
+                TimerScope ts_(tcls, s, pass_bytes + 48.0 * sizeof(R) * op->vol, 1416.0 * op->vol);
+                SC_TLAUNCH((k_lz_dhf<R>), dgrid, blk, 0, s, f, (const R*)tmpv, (const R*)vi, (const R*)vprev, U,
+                                   geo, kapR, tsg, ntile, per_xcd, alpha, beta, w.delta, i, w.st, w.part_a, w.part_f,
+                                   indef);
+                SC_LAUNCH_CHECK();
+            }
+            gf = ntile;
         } else {
             // step 5: f = A v_i - beta_{i-1} v_{i-1}; alpha_i; f -= alpha_i v_i
             SC_TRY(op_apply(op, single, vi, ldv, av, op->n, 1, w.tmp, s));
@@ -477,8 +605,8 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
             hipLaunchKernelGGL((k_lz_f<R, VEC>), dim3(g), blk, 0, s, f, vi, N2, alpha, beta, w.delta, i, w.st,
                                w.part_a, g, w.part_f, indef);
             SC_LAUNCH_CHECK();
+            gf = g;
         }
-        gf = g;
         if (freq > 0 && i >= 2 && i % freq == 0) {
             // step 8: [v_i, f] -= V_{i-1} (V_{i-1}^H [v_i, f]); v_i /= ||v_i||; f -= v_i (v_i^H f)
             ColPtrs<const void> wc{};
@@ -501,6 +629,7 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
             SC_TRY(gemm_nn(cpl, single, vi, ldv, op->n, 1, w.G2, 1, single, fo, -1.0, halt, s));
             hipLaunchKernelGGL((k_norm_part<R, VEC>), dim3(g), blk, 0, s, f, N2, w.part_f, halt);
             SC_LAUNCH_CHECK();
+            gf = g;
         }
         // step 9: beta_i = ||f||, v_{i+1} = f / beta_i (the fused form does it in the next D pass)
         if (!fused || i == m) {
