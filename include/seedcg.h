@@ -157,16 +157,19 @@ sc_status sc_wilson_dslash(const sc_op* op, sc_dtype dtype, int which, const voi
  * blocks of 2 and 4 consecutive z-planes, whose z neighbours inside the
  * block are staged in LDS too; where the planes do not fit LDS (4 planes of
  * 2 columns, FP64 beyond 2 planes) or do not divide Z, the launch uses the
- * next smaller plane count.  69..80: FP32 D and D^H passes on lattices with
+ * next smaller plane count.  69..86: FP32 D and D^H passes on lattices with
  * X = Y = 16 (and |kappa| >= 1e-6), for k > 1: one block per xy-plane and
  * column group marching t, x neighbours exchanged between lanes (DPP), y
  * neighbours through LDS as half spinors already multiplied by the source
  * site's link; 69 + 6 * (c - 1) + 3 * o + {0, 1, 2} for c = 1, 2 columns
  * per thread, segments of {4, 8, 16} slices, o = 0: the planes of a segment
- * are consecutive work items, 1: the column groups of a plane are.
+ * are consecutive work items, 1: the column groups of a plane are;
+ * 81 + 3 * (c - 1) + {0, 1, 2}: quads of 4 consecutive planes (2 or 1 when
+ * Z is not a multiple of 4), the planes of one column group consecutive,
+ * then the next group on the same quad.
  * us (host, SC_WILSON_VARIANTS floats): measured microseconds per pass of each
  * candidate (-1 if not run). */
-#define SC_WILSON_VARIANTS 81
+#define SC_WILSON_VARIANTS 87
 sc_status sc_wilson_tune_info(const sc_op* op, sc_dtype dtype, int k, int* variant, float* us);
 
 /* Pin the stencil launch shape for (this op's lattice, dtype, k) instead of
@@ -176,7 +179,7 @@ sc_status sc_wilson_tune_info(const sc_op* op, sc_dtype dtype, int k, int* varia
  * 45..68) on a lattice with X Y != 256. */
 sc_status sc_wilson_tune_set(const sc_op* op, sc_dtype dtype, int k, int variant);
 
-/* Host-only check of the addressing of the DPP-form stencil shapes (69..80),
+/* Host-only check of the addressing of the DPP-form stencil shapes (69..86),
  * whose loads and stores go through buffer descriptors: an access outside
  * its descriptor's record would read zero or be dropped instead of faulting.
  * Walks, on the CPU and with the kernel's own index functions, every access

@@ -145,7 +145,7 @@ def release_workspace():
 
 
 # ----------------------------------------------------------------------------- timing
-WILSON_VARIANTS = 81  # SC_WILSON_VARIANTS: tiled, t-march (1, 2, 4 planes per block), direction-split, DPP
+WILSON_VARIANTS = 87  # SC_WILSON_VARIANTS: tiled, t-march (1, 2, 4 planes per block), direction-split, DPP
 
 TIMER_CLASSES = {0: "wilson_f32_k1", 1: "wilson_f64_k1", 2: "gemm_cn", 3: "gemm_nn", 4: "wilson_f32_kn",
                  5: "wilson_f64_kn"}

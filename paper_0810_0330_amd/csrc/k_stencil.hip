@@ -707,14 +707,16 @@ constexpr int WV_TMARCH = 12;
 constexpr int WV_DIR = WV_TILED + WV_TMARCH;  // the direction-split form
 constexpr int WV_TM2 = WV_DIR + 1;            // t-march, 2 and 4 planes per block
 constexpr int WV_TX = WV_TM2 + 2 * WV_TMARCH;  // one column per thread, x hops by DPP (FP32, X = Y = 16)
-constexpr int WV_NTX = 12;
+constexpr int WV_NTX = 18;
 constexpr int WV_COUNT = WV_TX + WV_NTX;
 static_assert(WV_COUNT == SC_WILSON_VARIANTS, "variant count must match the header");
 
 // The DPP form (wilson_tx.h): ids WV_TX + 6 * (nc - 1) + 3 * order + {0, 1, 2}
 // for nc = 1, 2 columns per thread and segments of {4, 8, 16} time slices,
 // order 0: the planes of a segment are consecutive work items, 1: the column
-// groups of a plane are.  FP32 D and D^H passes only, on
+// groups of a plane are; ids WV_TX + 12 + 3 * (nc - 1) + {0, 1, 2}: order 2,
+// quads of planes with the column groups of a quad consecutive (tx_item).
+// FP32 D and D^H passes only, on
 // lattices with X = Y = 16 (an x-row is a 16-lane DPP row, four y-rows a
 // wave); its accumulator starts at -psi / kappa, so kappa must not be tiny.
 static bool is_tx(int v) { return v >= WV_TX && v < WV_TX + WV_NTX; }
@@ -726,12 +728,19 @@ static int tx_tlen(const sc_op* op, int v) {
     const int i = (v - WV_TX) % 3;
     return std::max(1, std::min(i == 0 ? 4 : (i == 1 ? 8 : 16), op->dims[3]));
 }
-static int tx_nc(int v) { return (v - WV_TX) >= 6 ? 2 : 1; }
+static int tx_nc(int v) {
+    const int i = v - WV_TX;
+    return i < 12 ? (i >= 6 ? 2 : 1) : (i >= 15 ? 2 : 1);
+}
+static int tx_order(int v) {
+    const int i = v - WV_TX;
+    return i < 12 ? ((i % 6) >= 3 ? 1 : 0) : 2;
+}
 static int tx_parts(const sc_op* op, int v) { return op->dims[2] * ((op->dims[3] + tx_tlen(op, v) - 1) / tx_tlen(op, v)); }
 
 // launch geometry of a DPP-form pass (used by the launch and by its range check)
 struct TxGeom {
-    int nc, tlen, nseg, ncg, per_xcd, blocks, cgm;
+    int nc, tlen, nseg, ncg, per_xcd, blocks, order;
 };
 static TxGeom tx_geom(const sc_op* op, int v, int k) {
     TxGeom q;
@@ -741,7 +750,7 @@ static TxGeom tx_geom(const sc_op* op, int v, int k) {
     q.ncg = (k + q.nc - 1) / q.nc;
     q.per_xcd = (q.ncg * op->dims[2] * q.nseg + kXcd - 1) / kXcd;
     q.blocks = q.per_xcd * kXcd;
-    q.cgm = ((v - WV_TX) % 6) >= 3 ? 1 : 0;
+    q.order = tx_order(v);
     return q;
 }
 
@@ -753,7 +762,7 @@ static void tx_launch(const sc_op* op, int v, bool dag, int epi, const float* X,
     const float kap = (float)op->kappa, ts = op->antiperiodic ? -1.0f : 1.0f;
 #define SC_TX(DAG, EPI_, NC_)                                                                                     \
     SC_TLAUNCH((k_wilson_tx<DAG, EPI_, NC_>), grid, blk, 0, s, Y, 2 * ldy, X, 2 * ldx, U, g, kap, ts, k, q.nseg, \
-               q.tlen, q.per_xcd, q.cgm, e)
+               q.tlen, q.per_xcd, q.order, e)
 #define SC_TXE(NC_)                                 \
     if (epi == TM_NORM) SC_TX(false, TM_NORM, NC_); \
     else if (epi == TM_CG) SC_TX(true, TM_CG, NC_); \
@@ -811,7 +820,7 @@ sc_status wilson_tx_check(const int dims[4], int v, int k, int64_t ldx, int64_t 
     for (int b = 0; b < q.blocks; ++b) {
         const int L = (b % kXcd) * q.per_xcd + b / kXcd;
         if (L >= q.ncg * Z * q.nseg) continue;  // the kernel returns
-        const TxItem wi = tx_item(L, q.ncg, Z, q.nseg, q.cgm);
+        const TxItem wi = tx_item(L, q.ncg, Z, q.nseg, q.order);
         const int t0 = wi.seg * q.tlen, t1 = std::min(T, t0 + q.tlen);
         ++n;
         if (wi.cg < 0 || wi.cg >= q.ncg || wi.z < 0 || wi.z >= Z || wi.seg < 0 || wi.seg >= q.nseg || t0 >= T) ++bad;
@@ -1065,7 +1074,8 @@ static void wilson_launch_variant(int v, const sc_op* op, int which, const R* X,
 
 // variants worth timing for this lattice, precision and column count
 static bool variant_applies(const sc_op* op, int v, bool single, int k) {
-    if (is_tx(v)) return single && tx_ok(op) && k > 1 && !(tx_nc(v) == 2 && k == 2 && ((v - WV_TX) % 6) >= 3);
+    // (with one column group the orders 1 and 2 repeat order 0's work on other planes first: skipped)
+    if (is_tx(v)) return single && tx_ok(op) && k > 1 && !(k <= tx_nc(v) && tx_order(v) != 0);
     if (v == WV_DIR) return k <= 4;
     if (is_tmarch(v)) {
         const int i = v < WV_DIR ? v - WV_TILED : (v - WV_TM2) % WV_TMARCH;
@@ -1107,8 +1117,25 @@ int g_tune_mode = -1;  // -1: read SEEDCG_TUNE on first use; 0: defaults only; 1
 
 }  // namespace
 
+// Expected HBM traffic of a shape's work order, lowest first, from the
+// FETCH_SIZE / WRITE_SIZE counters of the 24-column FP32 passes on 16^3 x 32
+// (traffic over algorithmic bytes, class means): the DPP form in quads of
+// planes, then the t-march forms with 2 or 4 planes per block (1.5x), the DPP
+// form with column groups fastest (1.8x), the one-plane t-march forms
+// (1.8-2.2x), the DPP form with planes fastest (2.4x), the direction-split form
+// (one column: 1.3x, few columns), the tiled forms (site order, about 3x).
+static int traffic_rank(int v) {
+    if (is_tx(v)) return tx_order(v) == 2 ? 0 : (tx_order(v) == 1 ? 2 : 4);
+    if (v >= WV_TM2 && v < WV_TX) return 1;
+    if (v >= WV_TILED && v < WV_DIR) return 3;
+    if (v == WV_DIR) return 5;
+    return 6;
+}
+constexpr float kTuneTie = 1.03f;
+
 // Time every variant on the caller's buffers (the output is rewritten by the
-// real launch that follows) and keep the fastest for (lattice, precision, k).
+// real launch that follows) and keep the fastest for (lattice, precision, k),
+// time ties going to the shape with the lower expected traffic.
 // Returns false, with rec holding the default shape and no timings, when a HIP
 // call fails; the caller does not cache that result.
 template <typename R>
@@ -1146,6 +1173,17 @@ static bool tune_variants(const sc_op* op, int which, const R* X, int64_t ldx, R
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    // a time tie (within kTuneTie of the fastest, the spread of repeated
+    // timings) goes to the shape that moves the fewest bytes past L2
+    if (ok) {
+        int pick = rec.best;
+        for (int v = 0; v < WV_COUNT; ++v) {
+            if (rec.us[v] < 0.0f || rec.us[v] > kTuneTie * best) continue;
+            const int rv = traffic_rank(v), rp = traffic_rank(pick);
+            if (rv < rp || (rv == rp && rec.us[v] < rec.us[pick])) pick = v;
+        }
+        rec.best = pick;
+    }
     if (!ok) {
         rec.best = dflt;
         for (int v = 0; v < WV_COUNT; ++v) rec.us[v] = -1.0f;

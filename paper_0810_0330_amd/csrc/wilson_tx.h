@@ -20,10 +20,9 @@
 //     carried in registers.
 // One column per thread keeps a lane's state (accumulator, carried half
 // spinor, one hop's operands) within 128 VGPRs, so four waves share a SIMD.
-// Work items (column, plane, segment) are ordered with
-// the column fastest (cgminor: the 24 columns of a plane share its links in
-// one XCD's L2) or with the plane fastest (a segment's planes share their z
-// neighbours).
+// Work items (column group, plane, segment) are ordered in one of three ways
+// (tx_item): planes fastest, column groups fastest, or quads of planes with
+// the column groups of a quad consecutive.
 //
 // Empty asm statements with a memory clobber fence the sections of a slice:
 // they keep the compiler from hoisting every load of the slice to its top,
@@ -62,17 +61,35 @@ constexpr int kTxPlane = 256;             // sites of an xy-plane (X = Y = 16)
 constexpr unsigned kTxSpinorBytes = 96u;  // per site of a spinor column: 12 complex64
 constexpr unsigned kTxLinkBytes = 288u;   // per site of the links: 4 x 9 complex64
 
-// work item L -> (column group, z-plane, t-segment)
+// work item L -> (column group, z-plane, t-segment), in one of three orders:
+//   0: the planes of a segment consecutive (z fastest, then segment, then
+//      column group): z neighbours shared in L2, links read once per group;
+//   1: the column groups of a plane consecutive (then z, then segment): links
+//      shared in L2 by all groups, z neighbours read again by each plane;
+//   2: quads of Q = 4 consecutive planes (2 or 1 when Z is not a multiple of
+//      4): the Q planes of one column group consecutive, then the next group on
+//      the same quad, then the next quad, then the next segment.  The z
+//      neighbours inside a quad and the quad's links are shared in L2; only
+//      the two planes bordering the quad come from outside it.
 struct TxItem {
     int cg, z, seg;
 };
-__host__ __device__ inline TxItem tx_item(int L, int ncg, int Z, int nseg, int cgminor) {
+__host__ __device__ inline int tx_quad(int Z) { return Z % 4 == 0 ? 4 : (Z % 2 == 0 ? 2 : 1); }
+__host__ __device__ inline TxItem tx_item(int L, int ncg, int Z, int nseg, int order) {
     TxItem w;
-    if (cgminor) {
+    if (order == 1) {
         w.cg = L % ncg;
         const int r = L / ncg;
         w.z = r % Z;
         w.seg = r / Z;
+    } else if (order == 2) {
+        const int Q = tx_quad(Z);
+        const int per_seg = Z * ncg;
+        w.seg = L / per_seg;
+        const int r = L % per_seg;
+        const int quad = r / (Q * ncg), r2 = r % (Q * ncg);
+        w.cg = r2 / Q;
+        w.z = quad * Q + r2 % Q;
     } else {
         w.z = L % Z;
         const int r = L / Z;
@@ -151,7 +168,7 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
                                                                      const float* __restrict__ in, int64_t ldi,
                                                                      const float* __restrict__ U, Geom g, float kappa,
                                                                      float tsign, int k, int nseg, int tlen,
-                                                                     int per_xcd, int cgminor, TmEpi e) {
+                                                                     int per_xcd, int order, TmEpi e) {
     using C = cplx<float>;
     // per lane and column: P psi for the -y neighbour (colours 0..2), U^H P psi for the +y one
     __shared__ float4 ys[NC][6][kBlock];
@@ -160,7 +177,7 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
     const int L = (b % kXcd) * per_xcd + b / kXcd;
     const int ncg = (k + NC - 1) / NC;  // column groups
     if (L >= ncg * g.Z * nseg) return;  // uniform over the block
-    const TxItem wi = tx_item(L, ncg, g.Z, nseg, cgminor);
+    const TxItem wi = tx_item(L, ncg, g.Z, nseg, order);
     const int cg = wi.cg, z = wi.z, seg = wi.seg;
     // the group's columns; a column past k (a partial last group) repeats the
     // last one and stores nothing, as does a column not active in e.st

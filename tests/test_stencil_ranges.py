@@ -1,4 +1,4 @@
-"""Host-side range check of the DPP-form stencil shapes (variants 69..80).
+"""Host-side range check of the DPP-form stencil shapes (variants 69..86).
 
 Their loads and stores go through buffer descriptors, which turn an access
 outside the descriptor's record into a zero read or a dropped store instead of
@@ -18,7 +18,7 @@ import pytest
 
 from paper_0810_0330_amd import api
 
-VARIANTS = range(69, 81)
+VARIANTS = range(69, 87)
 LATTICES = [(16, 16, 16, 16), (16, 16, 16, 32), (16, 16, 4, 8), (16, 16, 1, 1), (16, 16, 3, 7), (16, 16, 5, 18)]
 
 
