@@ -358,17 +358,22 @@ def compare_seeding(args, w):
     print(json.dumps(res), flush=True)
 
 
-def workload(args):
+def workload_by_key(key):
     from paper_0810_0330_amd import synth
-    if args.workload == "wilson_16x3x32":
+    if key == "wilson_16x3x32":
         w = synth.wilson_16x3x32()
-    elif args.workload == "wilson_8x4":
+    elif key == "wilson_8x4":
         w = synth.wilson_8x4(m=150)
         w.precision = "mixed"
-    elif args.workload == "diag_5000":
+    elif key == "diag_5000":
         w = synth.diag_5000()
     else:
         w = synth.laplace_32x32()
+    return w
+
+
+def workload(args):
+    w = workload_by_key(args.workload)
     if args.m is not None:
         w.m = args.m
     if args.freq is not None:
@@ -404,25 +409,24 @@ def measured_traffic(cls, k, variant, dims):
     return None
 
 
-def cpu_baseline(w, inp, counts):
-    """Time the FP64 oracle as it stands on a bounded sample of the workload and scale it to the whole solve.
+def _oracle_unit_times(key, threads, nlz=8, nvec=64):
+    """Unit times of the FP64 oracle's parts on the workload, BLAS limited to `threads`.
 
-    Sample (about 10 s on the 16^3 x 32 lattice): the oracle's seed phase for
-    8 Lanczos steps on right-hand side 1 (each step: one A-apply, its vector
-    work and the incremental x^1 update), its CG on right-hand side 2 for 10
-    and for 2 iterations (the difference prices one CG iteration), 2 plain
-    A-applies, and 64 of its length-n vector updates.  The full oracle solve is
-    priced with this run's counts: the seed steps, the CG iterations, two
-    residuals per right-hand side, and one vector update per stored basis
-    vector touched by the reorthogonalizations and by the incremental seeding
-    of the other right-hand sides (steps 4 and 7).
+    Builds the workload's inputs itself so that it can run in a fresh worker
+    process.  Parts: one seed-phase Lanczos step (one A-apply, its vector work
+    and the incremental x^1 update), one CG iteration (CG for 10 minus CG for 2
+    iterations, over 8), one A-apply, one length-n vector update.
     """
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     from oracle import operators as ops
     from oracle.cg import cg
     from oracle.seed import seed_lanczos
+    from paper_0810_0330_amd import synth
 
+    w = workload_by_key(key)
+    inp = synth.make_inputs(w)
     if w.op == "laplace2d":
         op = ops.Laplace2DOp(*w.dims)
     elif w.op == "diag":
@@ -430,42 +434,95 @@ def cpu_baseline(w, inp, counts):
     else:
         op = ops.WilsonNormalOp(inp["U"], w.kappa)
     B = inp["B"]
-    nlz = 8
-    t0 = time.perf_counter()
-    seed_lanczos(op, B[:, :1], m=nlz, freq=0)
-    t_step = (time.perf_counter() - t0) / nlz
-    t0 = time.perf_counter()
-    cg(op, B[:, 1], tol=1e-300, maxit=10)
-    t10 = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    cg(op, B[:, 1], tol=1e-300, maxit=2)
-    t2 = time.perf_counter() - t0
-    t_iter = max(t10 - t2, 0.0) / 8
-    t0 = time.perf_counter()
-    for _ in range(2):
-        op(B[:, 0])
-    t_apply = (time.perf_counter() - t0) / 2
-    v = B[:, 1].astype(np.complex128 if w.op == "wilson" else np.float64)
-    y = v.copy()
-    nvec = 64
-    t0 = time.perf_counter()
-    for _ in range(nvec):
-        c = np.vdot(v, y)
-        y = y - (c / (np.vdot(v, v) + 1.0)) * v
-    t_vec = (time.perf_counter() - t0) / nvec
-    t_total = (counts["seed_steps"] * t_step + counts["cg_iters"] * t_iter + counts["residuals"] * t_apply
-               + counts["vector_passes"] * t_vec)
+    with threadpool_limits(limits=threads):
+        t0 = time.perf_counter()
+        seed_lanczos(op, B[:, :1], m=nlz, freq=0)
+        t_step = (time.perf_counter() - t0) / nlz
+        t0 = time.perf_counter()
+        cg(op, B[:, 1], tol=1e-300, maxit=10)
+        t10 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        cg(op, B[:, 1], tol=1e-300, maxit=2)
+        t_iter = max(t10 - (time.perf_counter() - t0), 0.0) / 8
+        t0 = time.perf_counter()
+        for _ in range(2):
+            op(B[:, 0])
+        t_apply = (time.perf_counter() - t0) / 2
+        v = B[:, 1].astype(np.complex128 if w.op == "wilson" else np.float64)
+        y = v.copy()
+        t0 = time.perf_counter()
+        for _ in range(nvec):
+            c = np.vdot(v, y)
+            y = y - (c / (np.vdot(v, v) + 1.0)) * v
+        t_vec = (time.perf_counter() - t0) / nvec
+    return {"t_step": t_step, "t_iter": t_iter, "t_apply": t_apply, "t_vec": t_vec}
+
+
+def _host_info():
+    """CPU model, logical CPU counts and the NumPy/BLAS build of the host."""
+    import numpy as np
+
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    try:
+        blas = np.show_config(mode="dicts")["Build Dependencies"]["blas"]
+        blas = f"{blas.get('name')} {blas.get('version')}"
+    except Exception:  # noqa: BLE001 - build info is descriptive only
+        blas = None
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "numpy": np.__version__, "blas": blas}
+
+
+def cpu_baseline(key, w, counts):
+    """Time the FP64 oracle as it stands on a bounded sample of the workload and scale it to the whole solve.
+
+    Sample (about 10 s per process on the 16^3 x 32 lattice): the oracle's
+    seed phase for 8 Lanczos steps on right-hand side 1, its CG on right-hand
+    side 2 for 10 and for 2 iterations (the difference prices one CG
+    iteration), 2 plain A-applies, and 64 of its length-n vector updates.  The
+    full oracle solve is priced with this run's counts: the seed steps, the CG
+    iterations, two residuals per right-hand side, and one vector update per
+    stored basis vector touched by the reorthogonalizations and by the
+    incremental seeding of the other right-hand sides.
+
+    Two runs: one process with BLAS on one thread, and one process per host
+    CPU (at most 16) running the same sample at once, each on one thread; the
+    all-core figure is the throughput of that many independent copies of the
+    workload solved side by side, each at its measured (contended) speed.  The
+    oracle is sequential code, so this is how it uses a many-core host.
+    """
+    import multiprocessing as mp
+
+    def total(u):
+        return (counts["seed_steps"] * u["t_step"] + counts["cg_iters"] * u["t_iter"]
+                + counts["residuals"] * u["t_apply"] + counts["vector_passes"] * u["t_vec"])
+
+    one = _oracle_unit_times(key, 1)
+    v1 = w.nrhs / total(one)
+    procs = min(len(os.sched_getaffinity(0)), 16)
+    with mp.get_context("spawn").Pool(procs) as pool:
+        many = pool.starmap(_oracle_unit_times, [(key, 1)] * procs)
+    v_all = sum(w.nrhs / total(u) for u in many)
+    slow = sum(u["t_iter"] for u in many) / len(many) / max(one["t_iter"], 1e-12)
     return {
-        "value": w.nrhs / t_total,
+        "value": v_all,
         "unit": "RHS/s",
-        "cores": 1,
+        "cores": procs,
         "kind": "oracle",
-        "sample": (f"oracle seed phase {nlz} Lanczos steps ({t_step * 1e3:.0f} ms each), oracle CG 10 and 2 "
-                   f"iterations ({t_iter * 1e3:.0f} ms per iteration), {2} A-applies ({t_apply * 1e3:.0f} ms each), "
-                   f"{nvec} vector updates ({t_vec * 1e3:.2f} ms each) on the benchmark lattice; scaled by this "
-                   f"run's counts: {counts['seed_steps']} seed steps, {counts['cg_iters']} CG iterations, "
-                   f"{counts['residuals']} residuals, {counts['vector_passes']} basis-vector passes "
-                   f"(extrapolated; the numpy oracle runs on one thread)"),
+        "value_1_thread": v1,
+        "host": _host_info(),
+        "sample": (f"oracle seed phase 8 Lanczos steps ({one['t_step'] * 1e3:.0f} ms each), oracle CG 10 and 2 "
+                   f"iterations ({one['t_iter'] * 1e3:.0f} ms per iteration), 2 A-applies "
+                   f"({one['t_apply'] * 1e3:.0f} ms each), 64 vector updates ({one['t_vec'] * 1e3:.2f} ms each) "
+                   f"on the benchmark lattice, on one thread; the same sample in {procs} processes at once (one "
+                   f"thread each, CG iteration {slow:.2f}x slower under contention) gives the all-core value as "
+                   f"{procs} independent copies of the workload; scaled by this run's counts: "
+                   f"{counts['seed_steps']} seed steps, {counts['cg_iters']} CG iterations, {counts['residuals']} "
+                   f"residuals, {counts['vector_passes']} basis-vector passes (extrapolated)"),
     }
 
 
@@ -562,6 +619,39 @@ def main():
         plain = {"rhs_per_s": w.nrhs / tp, "ms": tp * 1e3, "iters": pits, "dtype": "f64"}
         log(f"[bench] plain FP64 CG: {tp * 1e3:.1f} ms, {plain['rhs_per_s']:.1f} RHS/s, iters {pits}")
 
+    # ---- unseeded batched CG of the same right-hand sides, same precision and kernels: every column
+    # from zero in one multi-column CG (what the seed phase and projection are measured against)
+    unseeded = None
+    if not args.no_plain:
+        api.solve_cg(op, B, w.tol, mixed=mixed)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            _, uits, urel = api.solve_cg(op, B, w.tol, mixed=mixed)
+        torch.cuda.synchronize()
+        tu = (time.perf_counter() - t) / args.steps
+        assert max(urel) <= w.tol
+        unseeded = {"rhs_per_s": round(w.nrhs / tu, 3), "ms": round(tu * 1e3, 3), "iters": uits,
+                    "dtype": "f32+f64" if mixed else "f64"}
+        log(f"[bench] unseeded batched CG: {tu * 1e3:.1f} ms, {w.nrhs / tu:.1f} RHS/s, iters {uits}")
+
+    # ---- error of sampled columns against the FP64 oracle's tight solutions (stored values written by
+    # tests/golden/make_oracle_golden.py from the oracle alone, on these same seeded inputs)
+    oracle_err = None
+    gpath = os.path.join(ROOT, "tests", "golden", "oracle_c3.json")
+    if w.op == "wilson" and os.path.exists(gpath):
+        g = json.load(open(gpath))
+        if g["workload"] == w.name:
+            idx = np.array(g["sample_index"])
+            errs = {}
+            for j, xs in zip(g["x_cols"], g["x_sample"]):
+                x = api.unpack_field(out["X"][j:j + 1].cpu().numpy())[0][idx]
+                xo = np.array([complex(a, b) for a, b in xs])
+                errs[str(j)] = float(np.linalg.norm(x - xo) / np.linalg.norm(xo))
+            oracle_err = {"columns": errs, "entries_per_column": len(idx), "oracle_tol": g["x_tol"],
+                          "measure": "||x - x_oracle|| / ||x_oracle|| over the sampled entries"}
+            log(f"[bench] error vs FP64 oracle (sampled): {errs}")
+
     # ---- roofline of the dominant kernel class.  Stencil launches are a uniform
     # 1-in-`timer_every` sample of their class and contraction launches are all
     # timed, so a class's total time is estimated as sampled time x its rate.
@@ -611,7 +701,7 @@ def main():
         counts = {"seed_steps": n_seed, "cg_iters": cg_its, "residuals": 2 * w.nrhs,
                   "vector_passes": reorth_vecs + 2 * n_seed * (w.nrhs - 1)}
         t = time.perf_counter()
-        cpu = cpu_baseline(w, inp, counts)
+        cpu = cpu_baseline(args.workload, w, counts)
         log(f"[bench] cpu baseline ({time.perf_counter() - t:.1f} s): {cpu['value']:.4f} RHS/s")
 
     res = {
@@ -633,6 +723,9 @@ def main():
         "max_relres": max(relres),
         "plain_cg": plain,
         "speedup_vs_plain": round(value / plain["rhs_per_s"], 3) if plain else None,
+        "unseeded_batched_cg": unseeded,
+        "speedup_vs_unseeded_batched": round(value / unseeded["rhs_per_s"], 3) if unseeded else None,
+        "error_vs_oracle": oracle_err,
         "roofline": roof,
         "kernels": kernels,
         "stencil_tuning": tuning,
