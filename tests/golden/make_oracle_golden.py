@@ -27,6 +27,11 @@ Sections and the file each writes (tests/golden/oracle_<section>.json):
            512 sampled entries with their norms.
   c3all    the same lattice: the mixed emulation's plain-CG count (from zero,
            tol 1e-8) of every one of the 24 columns (4 worker processes).
+  c3seed   the same lattice: the mixed emulation's single-seeded solve of all
+           24 columns with m = 200, freq = 100 (counts per column), and the
+           orthogonality of its complex64 basis, max |(V^H V - I)[i, j]| over
+           j <= i, for the columns just before and just after the two
+           reorthogonalization events (0-based 98..100 and 198..200).
 """
 import json
 import os
@@ -167,7 +172,34 @@ def c3all():
     return {"workload": w.name, "tol": w.tol, "mixed_cg_iters": its}
 
 
-SECTIONS = {"mixed8": mixed8, "tmarch": tmarch, "grad12": grad12, "c3": c3, "c3all": c3all}
+def basis_orthogonality(V, rows):
+    """max |(V^H V - I)[i, j]| over j <= i for each 0-based column i of the basis V (n x m+1)."""
+    out = {}
+    for i in rows:
+        vi = V[:, i].astype(np.complex128)
+        g = V[:, : i + 1].astype(np.complex128).conj().T @ vi
+        g[i] -= 1.0
+        out[str(i)] = float(np.abs(g).max())
+    return out
+
+
+def c3seed():
+    w = synth.wilson_16x3x32()
+    inp = synth.make_inputs(w)
+    op = ops.WilsonNormalOp(inp["U"], w.kappa)
+    m, freq = 200, 100
+    t = time.time()
+    res = mixed.seeded_solve_mixed(op, op.single(), inp["B"], m, freq, w.tol)
+    _say("c3seed mixed seeded iters", res["iters"], f"{time.time() - t:.0f} s")
+    rows = [98, 99, 100, 198, 199, 200]
+    orth = basis_orthogonality(res["seed"].V, rows)
+    _say("c3seed basis orthogonality", orth)
+    return {"workload": w.name, "m": m, "freq": freq, "tol": w.tol, "seeded_iters": res["iters"],
+            "cg_iters": res["cg_iters"], "m_done": res["seed"].m_done, "basis_orth_rows": rows,
+            "basis_orth": orth}
+
+
+SECTIONS = {"mixed8": mixed8, "tmarch": tmarch, "grad12": grad12, "c3": c3, "c3all": c3all, "c3seed": c3seed}
 
 if __name__ == "__main__":
     for name in sys.argv[1:]:
