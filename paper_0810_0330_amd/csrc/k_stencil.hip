@@ -664,7 +664,10 @@ __global__ __launch_bounds__(kBlock) void k_wilson_dir(R* __restrict__ out, int6
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
-    if (ok) dir_hops<DAG, R>(acc, src, U, g, uV, s, mu, tsign);
+    if (ok) {  // the x hops by DPP when a lane row is an x-row (X = 16)
+        if (mu == 0 && g.X == 16) dir_hops_x16<DAG, R>(acc, src, U, uV, s);
+        else dir_hops<DAG, R>(acc, src, U, g, uV, s, mu, tsign);
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll

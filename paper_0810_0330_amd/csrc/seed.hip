@@ -306,7 +306,10 @@ __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const 
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
     const PartPre pf = part_load(part, G);
-    if (ok) dir_hops<false, R>(acc, f, U, g, uV, s, mu, tsign);
+    if (ok) {  // the x hops by DPP when a lane row is an x-row (X = 16)
+        if (mu == 0 && g.X == 16) dir_hops_x16<false, R>(acc, f, U, uV, s);
+        else dir_hops<false, R>(acc, f, U, g, uV, s, mu, tsign);
+    }
     dir_stash(red, mu, l, acc);
     const double bn = sqrt(part_sum(pf, part, G, sh));  // its barriers also order the stash
     const bool fin = isfinite(bn);
@@ -382,7 +385,10 @@ __global__ __launch_bounds__(kBlock) void k_lz_dhalpha(R* __restrict__ f, const 
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
-    if (ok) dir_hops<true, R>(acc, tmp, U, g, uV, s, mu, tsign);
+    if (ok) {  // the x hops by DPP when a lane row is an x-row (X = 16)
+        if (mu == 0 && g.X == 16) dir_hops_x16<true, R>(acc, tmp, U, uV, s);
+        else dir_hops<true, R>(acc, tmp, U, g, uV, s, mu, tsign);
+    }
     dir_stash(red, mu, l, acc);
     __syncthreads();
     const R bp = (R)(i > 1 ? beta[i - 1] : 0.0);
@@ -431,7 +437,10 @@ __global__ __launch_bounds__(kBlock) void k_lz_dhf(R* __restrict__ f, const R* _
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
     const PartPre pd = part_load(part_a, ntile), pp = part_load(part_a + ntile, ntile);
-    if (ok) dir_hops<true, R>(acc, tmp, U, g, uV, s, mu, tsign);
+    if (ok) {  // the x hops by DPP when a lane row is an x-row (X = 16)
+        if (mu == 0 && g.X == 16) dir_hops_x16<true, R>(acc, tmp, U, uV, s);
+        else dir_hops<true, R>(acc, tmp, U, g, uV, s, mu, tsign);
+    }
     dir_stash(red, mu, l, acc);
     // alpha_i (its barriers also order the stash); every block adds the same
     // partials in the same order, so every block gets the same alpha

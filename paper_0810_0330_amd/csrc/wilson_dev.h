@@ -203,6 +203,63 @@ __device__ __forceinline__ void neighbours(const Geom& g, int s, int mu, R tsign
     }
 }
 
+// The value held by the lane one x-step up (x + 1) or down (x - 1) in this
+// lane's row of 16 lanes, by DPP row rotation: for row_ror:n lane i reads lane
+// (i - n) mod 16, so row_ror:15 gives x + 1 and row_ror:1 gives x - 1, wrapping
+// exactly as the periodic x boundary does when a row holds one x-row of a
+// lattice with X = 16.  FP64 values move as two 32-bit halves.
+__device__ __forceinline__ float dpp_from_xp(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x12F, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float dpp_from_xm(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x121, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double dpp_from_xp(double v) {
+    int2 b = __builtin_bit_cast(int2, v);
+    b.x = __builtin_amdgcn_update_dpp(0, b.x, 0x12F, 0xF, 0xF, false);
+    b.y = __builtin_amdgcn_update_dpp(0, b.y, 0x12F, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, b);
+}
+__device__ __forceinline__ double dpp_from_xm(double v) {
+    int2 b = __builtin_bit_cast(int2, v);
+    b.x = __builtin_amdgcn_update_dpp(0, b.x, 0x121, 0xF, 0xF, false);
+    b.y = __builtin_amdgcn_update_dpp(0, b.y, 0x121, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, b);
+}
+
+// The two x hops of site s when the wave's lanes hold whole x-rows of a
+// lattice with X = 16 (lane l = site s mod 64, x = l mod 16): the lane loads
+// only its own spinor and link, projects its spinor for both hops and forms
+// U_x(s)^H P psi(s) itself; the forward hop takes the projection of lane x + 1
+// and the backward hop the product of lane x - 1 through DPP.  Each quantity
+// is the one the loading form computes from the neighbour's data, so the
+// result is the same.
+template <bool DAG, typename R>
+__device__ __forceinline__ void dir_hops_x16(cplx<R> acc[4][3], const R* __restrict__ src, const R* __restrict__ U,
+                                             unsigned uV, int s) {
+    constexpr int SF = DAG ? 1 : -1;
+    constexpr int SB = -SF;
+    cplx<R> u[3][3], psi[4][3];
+    load_link(U, uV, 0, (unsigned)s, u);
+    load_spinor(src, uV, (unsigned)s, psi);
+    cplx<R> h0[3], h1[3], g0[3], g1[3], c0[3], c1[3];
+    project<0, SF>(psi, h0, h1);  // what lane x - 1 needs for its forward hop
+    project<0, SB>(psi, g0, g1);
+    su3_mul<true>(u, g0, c0);     // what lane x + 1 needs for its backward hop
+    su3_mul<true>(u, g1, c1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        h0[c] = {dpp_from_xp(h0[c].re), dpp_from_xp(h0[c].im)};
+        h1[c] = {dpp_from_xp(h1[c].re), dpp_from_xp(h1[c].im)};
+        c0[c] = {dpp_from_xm(c0[c].re), dpp_from_xm(c0[c].im)};
+        c1[c] = {dpp_from_xm(c1[c].re), dpp_from_xm(c1[c].im)};
+    }
+    hop_acc<0, SB>(acc, c0, c1);  // backward hop, from x - 1
+    su3_mul<false>(u, h0, c0);
+    su3_mul<false>(u, h1, c1);
+    hop_acc<0, SF>(acc, c0, c1);  // forward hop, from x + 1
+}
+
 // acc += the forward and backward hops of direction mu at site s (one
 // direction of the hopping term; mu wave-uniform)
 template <bool DAG, typename R>

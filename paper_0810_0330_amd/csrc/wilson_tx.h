@@ -42,20 +42,10 @@
 
 namespace sc {
 
-// The value of the lane one x-step up (x + 1 mod 16) or down (x - 1 mod 16) in
-// this lane's row of 16: DPP row rotation, lane i reads lane (i - n) mod 16 for
-// row_ror:n.
-__device__ __forceinline__ float dpp_from_xp(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x12F, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float dpp_from_xm(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x121, 0xF, 0xF, false));
-}
-
 #define SC_TX_FENCE() asm volatile("" ::: "memory")
 
 // ---- the kernel's index arithmetic, shared with the host-side range check
-// (tx_check_ranges in k_stencil.hip walks every access of a launch with these
+// (wilson_tx_check in k_stencil.hip walks every access of a launch with these
 // functions and compares it with its descriptor's record size)
 constexpr int kTxPlane = 256;             // sites of an xy-plane (X = Y = 16)
 constexpr unsigned kTxSpinorBytes = 96u;  // per site of a spinor column: 12 complex64

@@ -576,6 +576,29 @@ def test_shortest_seeds(m):
                     assert abs(a - b) <= 2, (m, mixed, out["iters"], oits)
 
 
+def test_seed_alpha_beta_on_x16_lattice():
+    # on lattices with X = 16 the fused Lanczos passes take the x hops through
+    # the lanes of an x-row (DPP) instead of loading the neighbours: the
+    # recurrence coefficients against the oracle's, FP64 and complex64 basis
+    dims = (16, 16, 2, 3)
+    _say("seed alpha/beta on", dims)
+    U = synth.su3_links(dims, synth.rng(16, 0))
+    op = api.Op.wilson(dims, torch.from_numpy(api.pack_links(U)).to(DEV), 0.12)
+    oop = ops.WilsonNormalOp(U, 0.12)
+    b = synth.z4_noise(oop.n, 1, synth.rng(16, 1))
+    m = 25
+    ref = o_seed(oop, b, m=m, freq=1)
+    for vdt, bar in ((torch.complex128, 1e-11), (torch.complex64, 1e-5)):  # FP32 rounding through 25 steps
+        basis = api.seed_lanczos(op, _to_lib(b)[0], m, 1, v_dtype=vdt)
+        assert basis.m_done == m
+        a = basis.alpha.cpu().numpy()
+        bb = basis.beta.cpu().numpy()
+        ea = np.abs(a - ref.alpha[:m]).max() / np.abs(ref.alpha[:m]).max()
+        eb = np.abs(bb - ref.beta[: m + 1]).max() / np.abs(ref.beta[: m + 1]).max()
+        _say("  ", vdt, "alpha err %.2e beta err %.2e" % (ea, eb))
+        assert ea <= bar and eb <= bar, (vdt, ea, eb)
+
+
 def test_seeded_solve_periodic_time():
     # periodic (not antiperiodic) time boundary through the whole method, on a
     # t-march lattice (xy-plane of 256 sites) and on a tiled one, FP64 and mixed
