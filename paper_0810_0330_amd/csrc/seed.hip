@@ -225,10 +225,10 @@ __global__ __launch_bounds__(kBlock) void k_lz_f(R* __restrict__ f, const R* __r
 // LDS).  Two launches per step i >= 2:
 //   D pass = step 9 of step i - 1 + the pass: beta_{i-1} = ||f|| from the
 //     partials (the checks of k_lz_next), v_i = f / beta_{i-1} stored for the
-//     block's sites, D v_i = (D f) / beta_{i-1}, and per 64-site tile the
-//     partials of ||D v_i||^2 and of Re(v_i^H v_{i-1});
-//   D^H pass = the pass + step 5: alpha_i = ||D v_i||^2 - beta_{i-1}
-//     Re(v_i^H v_{i-1}) from those partials (with the LU pivot of step 6),
+//     block's sites, D v_i = (D f) / beta_{i-1}, and per 64-site tile its
+//     share of alpha_i = ||D v_i||^2 - beta_{i-1} Re(v_i^H v_{i-1});
+//   D^H pass = the pass + step 5: alpha_i as the sum of those shares (with
+//     the LU pivot of step 6),
 //     f = D^H (D v_i) - beta_{i-1} v_{i-1} - alpha_i v_i, and per tile the
 //     partials of ||f||^2 for the next D pass.
 // For A = D^H D, v^H A v = ||D v||^2, so this alpha_i is step 5's
@@ -262,23 +262,26 @@ __device__ __forceinline__ void dir_stash(R (*red)[24][64], int mu, int l, const
 // part_sum adds them in the order of sum_partials, so every block gets the
 // same, deterministic total.
 constexpr int kPre = 8;
+template <int P = kPre>
 struct PartPre {
-    double v[kPre];
+    double v[P];
 };
-__device__ __forceinline__ PartPre part_load(const double* __restrict__ part, int G) {
-    PartPre q;
+template <int P = kPre>
+__device__ __forceinline__ PartPre<P> part_load(const double* __restrict__ part, int G) {
+    PartPre<P> q;
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
+    for (int u = 0; u < P; ++u) {
         const int j = (int)threadIdx.x + u * kBlock;
         q.v[u] = j < G ? part[j] : 0.0;
     }
     return q;
 }
-__device__ __forceinline__ double part_sum(const PartPre& q, const double* __restrict__ part, int G, double* sh) {
+template <int P>
+__device__ __forceinline__ double part_sum(const PartPre<P>& q, const double* __restrict__ part, int G, double* sh) {
     double s = 0.0;
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) s += q.v[u];
-    for (int j = (int)threadIdx.x + kPre * kBlock; j < G; j += kBlock) s += part[j];
+    for (int u = 0; u < P; ++u) s += q.v[u];
+    for (int j = (int)threadIdx.x + P * kBlock; j < G; j += kBlock) s += part[j];
     return block_sum(s, sh);
 }
 
@@ -305,7 +308,18 @@ __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const 
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
-    const PartPre pf = part_load(part, G);
+    const PartPre<> pf = part_load(part, G);
+    // the epilogue's own-site operands (f and v_{i-1} at the lane's 3
+    // components), loaded with the partials so that the epilogue after the
+    // barriers below waits on no memory
+    cplx<R> fo[3];
+    typename vec2<VT>::type po[3];
+    if (ok)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            fo[cc] = ldc(f + 2 * (size_t)((mu * 3 + cc) * uV), (unsigned)s);
+            po[cc] = reinterpret_cast<const typename vec2<VT>::type*>(vprev)[(mu * 3 + cc) * uV + s];
+        }
     if (ok) {  // the x hops by DPP when a lane row is an x-row (X = 16)
         if (mu == 0 && g.X == 16) dir_hops_x16<false, R>(acc, f, U, uV, s);
         else dir_hops<false, R>(acc, f, U, g, uV, s, mu, tsign);
@@ -345,11 +359,11 @@ __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const 
         for (int cc = 0; cc < 3; ++cc) {
             const cplx<R> h = dir_total(red, mu, cc, l);
             const size_t cb = 2 * (size_t)((mu * 3 + cc) * uV);
-            const cplx<R> fv = ldc(f + cb, (unsigned)s);
+            const cplx<R> fv = fo[cc];
             const cplx<R> v = {fv.re / bR, fv.im / bR};                              // v_i = f / beta
             const cplx<R> r = {(fv.re - kappa * h.re) / bR, (fv.im - kappa * h.im) / bR};  // D v_i
             const typename vec2<VT>::type vs{(VT)v.re, (VT)v.im};
-            const typename vec2<VT>::type pv = reinterpret_cast<const typename vec2<VT>::type*>(vprev)[(mu * 3 + cc) * uV + s];
+            const typename vec2<VT>::type pv = po[cc];
             reinterpret_cast<typename vec2<R>::type*>(tmp + cb)[s] = typename vec2<R>::type{r.re, r.im};
             reinterpret_cast<typename vec2<VT>::type*>(vnext)[(mu * 3 + cc) * uV + s] = vs;
             dacc += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
@@ -358,10 +372,8 @@ __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const 
     }
     const double dt = block_sum(dacc, sh);
     const double pt = block_sum(pacc, sh);
-    if (threadIdx.x == 0) {
-        part_a[L] = dt;
-        part_a[ntile + L] = pt;
-    }
+    // the tile's share of alpha_i = ||D v_i||^2 - beta_{i-1} Re(v_i^H v_{i-1})
+    if (threadIdx.x == 0) part_a[L] = dt - bn * pt;
 }
 
 template <typename R>
@@ -436,18 +448,34 @@ __global__ __launch_bounds__(kBlock) void k_lz_dhf(R* __restrict__ f, const R* _
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
-    const PartPre pd = part_load(part_a, ntile), pp = part_load(part_a + ntile, ntile);
+    // 6 of the (up to) 8 partials per thread: the registers of the other 2
+    // hold the epilogue's operands
+    const PartPre<6> pa = part_load<6>(part_a, ntile);
+    // the epilogue's own-site operands at the lane's 3 components, loaded with
+    // the partials so that the epilogue after the barriers below waits on no
+    // memory: D v_i - beta_{i-1} v_{i-1} (beta_{i-1} is known; the D pass
+    // stored it) and v_i
+    const double bp = beta[i - 1];
+    const R bR = (R)bp;
+    cplx<R> wo[3], vo[3];
+    if (ok)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            const size_t cb = 2 * (size_t)((mu * 3 + cc) * uV);
+            const cplx<R> t = ldc(tmp + cb, (unsigned)s);
+            const cplx<R> pv = ldc(vprev + cb, (unsigned)s);
+            wo[cc] = {t.re - bR * pv.re, t.im - bR * pv.im};
+            vo[cc] = ldc(vi + cb, (unsigned)s);
+        }
     if (ok) {  // the x hops by DPP when a lane row is an x-row (X = 16)
         if (mu == 0 && g.X == 16) dir_hops_x16<true, R>(acc, tmp, U, uV, s);
         else dir_hops<true, R>(acc, tmp, U, g, uV, s, mu, tsign);
     }
     dir_stash(red, mu, l, acc);
-    // alpha_i (its barriers also order the stash); every block adds the same
-    // partials in the same order, so every block gets the same alpha
-    const double dn = part_sum(pd, part_a, ntile, sh);
-    const double pr = part_sum(pp, part_a + ntile, ntile, sh);
-    const double bp = beta[i - 1];
-    const double a = dn - bp * pr;
+    // alpha_i from the D pass's per-tile shares (its barriers also order the
+    // stash); every block adds the same partials in the same order, so every
+    // block gets the same alpha
+    const double a = part_sum(pa, part_a, ntile, sh);
     const double d = a - bp * bp / delta[i - 1];  // the LU pivot of step 6
     const bool bad = !isfinite(a) || (!indef && !(d > 0.0));
     if (b == 0 && threadIdx.x == 0) {  // block 0 always holds a tile
@@ -463,19 +491,16 @@ __global__ __launch_bounds__(kBlock) void k_lz_dhf(R* __restrict__ f, const R* _
         }
     }
     if (bad) return;
-    const R bR = (R)bp, aR = (R)a;
+    const R aR = (R)a;
     double facc = 0.0;
     if (ok) {
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
             const cplx<R> h = dir_total(red, mu, cc, l);
             const size_t cb = 2 * (size_t)((mu * 3 + cc) * uV);
-            const cplx<R> t = ldc(tmp + cb, (unsigned)s);
-            const cplx<R> av = {t.re - kappa * h.re, t.im - kappa * h.im};  // A v_i = D^H (D v_i)
-            const cplx<R> pv = ldc(vprev + cb, (unsigned)s);
-            const cplx<R> v = ldc(vi + cb, (unsigned)s);
-            cplx<R> fv = {av.re - bR * pv.re, av.im - bR * pv.im};
-            fv = {fv.re - aR * v.re, fv.im - aR * v.im};
+            const cplx<R> v = vo[cc];
+            // f = A v_i - beta_{i-1} v_{i-1} - alpha_i v_i, A v_i = D^H (D v_i) = D v_i - kappa H (D v_i)
+            const cplx<R> fv = {wo[cc].re - kappa * h.re - aR * v.re, wo[cc].im - kappa * h.im - aR * v.im};
             reinterpret_cast<typename vec2<R>::type*>(f + cb)[s] = typename vec2<R>::type{fv.re, fv.im};
             facc += (double)fv.re * (double)fv.re + (double)fv.im * (double)fv.im;
         }
@@ -508,9 +533,9 @@ static SeedWork carve_seed(Carver& c, const sc_op* op, int m, bool single) {
     w.r64 = c.take<double>(N2);
     w.ax64 = c.take<double>(N2);
     w.tmp64 = c.take<double>(std::max<int64_t>(tmpn, 1));
-    // per 64-site tile: two partials from the fused D pass, one of ||f||^2 from the fused D^H pass
+    // per 64-site tile: its share of alpha from the fused D pass, of ||f||^2 from the fused D^H pass
     const int64_t ntile = (op->n / 12 + 63) / 64;
-    w.part_a = c.take<double>(std::max<int64_t>(kMaxRedBlocks, 2 * ntile));
+    w.part_a = c.take<double>(std::max<int64_t>(kMaxRedBlocks, ntile));
     w.part_f = c.take<double>(std::max<int64_t>(kMaxRedBlocks, ntile));
     w.part_v = c.take<double>(kMaxRedBlocks);
     w.delta = c.take<double>((size_t)m + 2);
