@@ -72,10 +72,32 @@ constexpr int kWaves = kBlock / 64;  // 64-wide wavefronts
 constexpr int kXcd = 8;
 constexpr int kMaxRedBlocks = 512;   // split-reduction width cap
 
+// v plus the value that DPP control CTRL moves into this lane, in the rows of
+// RMASK (plus 0 in the others): one DPP move per 32-bit half, no LDS round trip
+template <int CTRL, int RMASK>
+__device__ __forceinline__ double dpp_add(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, RMASK, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, RMASK, 0xF, false);
+    return v + __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wave (all lanes active); every lane gets the
+// total.  Pairs, quads, groups of 8 and rows of 16 by DPP lane permutations
+// (every lane of a row then holds the row's sum), the four rows by the two row
+// broadcasts (lane 63 then holds the total), read back from lane 63.  A fixed
+// tree, so the result is deterministic.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v = dpp_add<0x141, 0xF>(v);  // row_half_mirror
+    v = dpp_add<0x140, 0xF>(v);  // row_mirror
+    v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 63);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
 // Sum over the block; every thread gets the total.  Deterministic: fixed tree.

@@ -352,28 +352,27 @@ __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const 
                     typename vec2<VT>::type{VT(0), VT(0)};
         return;
     }
-    const R bR = (R)bn;
-    double dacc = 0.0, pacc = 0.0;  // ||D v_i||^2 and Re(v_i^H v_{i-1}) over the lane's 3 components
+    const R rb = (R)(1.0 / bn);  // v_i = f / beta as f times 1 / beta (FP64 reciprocal, rounded once)
+    // the lane's share of alpha_i = ||D v_i||^2 - beta_{i-1} Re(v_i^H v_{i-1}) over its 3 components
+    double aacc = 0.0;
     if (ok) {
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
             const cplx<R> h = dir_total(red, mu, cc, l);
             const size_t cb = 2 * (size_t)((mu * 3 + cc) * uV);
             const cplx<R> fv = fo[cc];
-            const cplx<R> v = {fv.re / bR, fv.im / bR};                              // v_i = f / beta
-            const cplx<R> r = {(fv.re - kappa * h.re) / bR, (fv.im - kappa * h.im) / bR};  // D v_i
+            const cplx<R> v = {fv.re * rb, fv.im * rb};                              // v_i
+            const cplx<R> r = {(fv.re - kappa * h.re) * rb, (fv.im - kappa * h.im) * rb};  // D v_i
             const typename vec2<VT>::type vs{(VT)v.re, (VT)v.im};
             const typename vec2<VT>::type pv = po[cc];
             reinterpret_cast<typename vec2<R>::type*>(tmp + cb)[s] = typename vec2<R>::type{r.re, r.im};
             reinterpret_cast<typename vec2<VT>::type*>(vnext)[(mu * 3 + cc) * uV + s] = vs;
-            dacc += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
-            pacc += (double)vs.x * (double)pv.x + (double)vs.y * (double)pv.y;
+            aacc += (double)r.re * (double)r.re + (double)r.im * (double)r.im -
+                    bn * ((double)vs.x * (double)pv.x + (double)vs.y * (double)pv.y);
         }
     }
-    const double dt = block_sum(dacc, sh);
-    const double pt = block_sum(pacc, sh);
-    // the tile's share of alpha_i = ||D v_i||^2 - beta_{i-1} Re(v_i^H v_{i-1})
-    if (threadIdx.x == 0) part_a[L] = dt - bn * pt;
+    const double at = block_sum(aacc, sh);
+    if (threadIdx.x == 0) part_a[L] = at;
 }
 
 template <typename R>
