@@ -676,6 +676,26 @@ def main():
                 "avg_launch_us": kd["avg_us"], "bytes_per_launch": kd["bytes_per_launch"],
                 "timed_launches": kd["launches"], "sample_every": 1 if dom.startswith("gemm") else args.timer_every}
 
+    # measured copy bandwidth of the device (the runtime's device-to-device copy of 24 complex64 columns of
+    # the lattice, 302 MB each way), for the stencil rate as a fraction of what a plain copy reaches
+    if roof is not None and roof["bound"] == "hbm":
+        nb = 24 * 12 * int(np.prod(w.dims)) * 8 if w.op == "wilson" else 256 << 20
+        cx = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
+        cy = torch.empty_like(cx)
+        cy.copy_(cx)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            cy.copy_(cx)
+        e1.record()
+        e1.synchronize()
+        copy_gbs = 2 * nb * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        roof["copy_GBps"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
+        del cx, cy
+        for kd_ in kernels.values():
+            kd_["frac_of_hbm_peak"] = round(kd_["GBps"] / HBM_PEAK_GBS, 4)
+
     if roof is not None and w.op == "wilson" and roof["kernel"].startswith("wilson_f32"):
         kk = 1 if roof["kernel"].endswith("_k1") else w.nrhs
         v, _ = op.tune_info(kk, single=True)
