@@ -368,7 +368,11 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
             }
         }
         SC_TX_FENCE();
-        // +t with the next slice, which becomes current
+        // +t with the next slice, which becomes current, and the epilogue, one
+        // column after the other: a column's r (TM_CG) is loaded together with
+        // its next slice, so the epilogue's loads are waited for together with
+        // the +t hop's instead of after it, and the registers of one column's r
+        // are those its finished accumulator frees
         const bool tlast = t == g.T - 1;
         const unsigned sn = (unsigned)tx_tnext_site((int)s, t, g.T, g.Z);
         // the boundary sign as a multiply, not a branch: a branch here splits
@@ -379,6 +383,13 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
             tx_link(Ub, uV, 3, tx_opaque(s), u);  // U_t(s) again
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
+                C q[4][3];
+                if constexpr (EPI == TM_CG) {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int cc = 0; cc < 3; ++cc) q[a][cc] = tx_ld(dst[c], tx_boff(s), tx_soff(a * 3 + cc, uV));
+                }
                 tx_spinor(src[c], uV, sn, cur[c]);  // cur is dead since the t section: the next slice
                 C h0[3], h1[3], c0[3], c1[3];
                 project<3, SF>(cur[c], h0, h1);
@@ -390,29 +401,22 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
                 su3_mul<false>(u, h0, c0);
                 su3_mul<false>(u, h1, c1);
                 hop_acc<3, SF>(acc[c], c0, c1);
-            }
-        }
-        SC_TX_FENCE();
-        // out = psi - kappa H psi = -kappa acc, or r -= alpha out
+                // out = psi - kappa H psi = -kappa acc, or r -= alpha out
+                float sq = 0.0f;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            float sq = 0.0f;
+                for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    C r = {-kappa * acc[c][a][cc].re, -kappa * acc[c][a][cc].im};
-                    const unsigned soff = tx_soff(a * 3 + cc, uV);
-                    if constexpr (EPI == TM_CG) {
-                        const C q = tx_ld(dst[c], tx_boff(s), soff);
-                        r = {q.re - alpha[c] * r.re, q.im - alpha[c] * r.im};
+                    for (int cc = 0; cc < 3; ++cc) {
+                        C r = {-kappa * acc[c][a][cc].re, -kappa * acc[c][a][cc].im};
+                        if constexpr (EPI == TM_CG) r = {q[a][cc].re - alpha[c] * r.re, q[a][cc].im - alpha[c] * r.im};
+                        tx_st(dst[c], tx_boff(s), tx_soff(a * 3 + cc, uV), r);
+                        sq = __builtin_fmaf(r.re, r.re, sq);
+                        sq = __builtin_fmaf(r.im, r.im, sq);
                     }
-                    tx_st(dst[c], tx_boff(s), soff, r);
-                    sq = __builtin_fmaf(r.re, r.re, sq);
-                    sq = __builtin_fmaf(r.im, r.im, sq);
-                }
-            // |.|^2 of the site in FP32 (12 components), summed over sites in FP64
-            if constexpr (EPI != TM_PLAIN) nacc[c] += (double)sq;
+                // |.|^2 of the site in FP32 (12 components), summed over sites in FP64
+                if constexpr (EPI != TM_PLAIN) nacc[c] += (double)sq;
+                SC_TX_FENCE();  // the next column's loads stay after this column's epilogue
+            }
         }
     }
     if constexpr (EPI != TM_PLAIN) {
