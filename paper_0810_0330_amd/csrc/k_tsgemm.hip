@@ -445,14 +445,26 @@ __global__ __launch_bounds__(kBlock) void k_cn_reduce(const double* __restrict__
     __shared__ double sh[kWaves][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t o = blockIdx.x * (int64_t)64 + lane;
-    double s = 0.0;
+    // wave wv adds chunks wv, wv + 4, ...: chunk wv + 4 (8 j + u) into
+    // accumulator u, so eight loads are in flight at a time (a row chunk count
+    // in the hundreds would otherwise be a chain of dependent loads); the
+    // accumulators are then added in a fixed order
+    double acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
     if (o < nout) {
-        if (cplx) {
-            for (int c = wv; c < nchunk; c += kWaves) s += part[(int64_t)c * nout + o];
-        } else {  // partials keep (re, im) pairs; the real result is the re part
-            for (int c = wv; c < nchunk; c += kWaves) s += part[2 * ((int64_t)c * nout + o)];
-        }
+        // partials keep (re, im) pairs for a real contraction; its result is the re part
+        const int64_t stride = cplx ? nout : 2 * nout;
+        const double* base = part + (cplx ? o : 2 * o);
+        int c = wv;
+        for (; c + 7 * kWaves < nchunk; c += 8 * kWaves)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += base[(int64_t)(c + u * kWaves) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (c + u * kWaves < nchunk) acc[u] += base[(int64_t)(c + u * kWaves) * stride];
     }
+    const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     sh[wv][lane] = s;
     __syncthreads();
     if (wv == 0 && o < nout) G[o] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
