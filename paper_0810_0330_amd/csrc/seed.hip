@@ -276,9 +276,13 @@ __device__ __forceinline__ PartPre<P> part_load(const double* __restrict__ part,
     }
     return q;
 }
+// The sum starts at -0.0, which the first addition absorbs exactly (x + -0.0 =
+// x): with 0.0 the compiler moves that first addition into the conditional
+// load of the first partial and waits for it there, before any other load of
+// the kernel is issued.
 template <int P>
 __device__ __forceinline__ double part_sum(const PartPre<P>& q, const double* __restrict__ part, int G, double* sh) {
-    double s = 0.0;
+    double s = -0.0;
 #pragma unroll
     for (int u = 0; u < P; ++u) s += q.v[u];
     for (int j = (int)threadIdx.x + P * kBlock; j < G; j += kBlock) s += part[j];
@@ -293,10 +297,14 @@ __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const 
                                                      const double* part, int G, double* part_a) {
     __shared__ R red[4][24][64];
     __shared__ double sh[kWaves];
-    if (st->halt) return;
     const int b = blockIdx.x;
     const int L = (b % kXcd) * per_xcd + b / kXcd;
     if (L >= ntile) return;  // uniform over the block
+    // the state is read here and acted on after every load of the pass has
+    // been issued (the loads are in range whatever it says), so that its
+    // latency is not one more round trip on the block's chain
+    const int halted = st->halt;
+    const double amax = st->amax;
     const int mu = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int s = L * 64 + l;
     const bool ok = s < (int)g.V;
@@ -324,10 +332,11 @@ __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const 
         if (mu == 0 && g.X == 16) dir_hops_x16<false, R>(acc, f, U, uV, s);
         else dir_hops<false, R>(acc, f, U, g, uV, s, mu, tsign);
     }
+    if (halted) return;  // uniform over the grid: an earlier step stopped the phase
     dir_stash(red, mu, l, acc);
     const double bn = sqrt(part_sum(pf, part, G, sh));  // its barriers also order the stash
     const bool fin = isfinite(bn);
-    const bool brk = fin && !(bn > kBreakdownTol * st->amax);
+    const bool brk = fin && !(bn > kBreakdownTol * amax);
     if (b == 0 && threadIdx.x == 0) {  // block 0 always holds a tile
         beta[im1] = bn;
         if (!fin) {
@@ -434,10 +443,12 @@ __global__ __launch_bounds__(kBlock) void k_lz_dhf(R* __restrict__ f, const R* _
                                                    int indef) {
     __shared__ R red[4][24][64];
     __shared__ double sh[kWaves];
-    if (st->halt) return;
     const int b = blockIdx.x;
     const int L = (b % kXcd) * per_xcd + b / kXcd;
     if (L >= ntile) return;  // uniform over the block
+    // read here, acted on after the pass's loads are issued (as in k_lz_dnext)
+    const int halted = st->halt;
+    const double dprev = delta[i - 1];
     const int mu = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int s = L * 64 + l;
     const bool ok = s < (int)g.V;
@@ -470,12 +481,13 @@ __global__ __launch_bounds__(kBlock) void k_lz_dhf(R* __restrict__ f, const R* _
         if (mu == 0 && g.X == 16) dir_hops_x16<true, R>(acc, tmp, U, uV, s);
         else dir_hops<true, R>(acc, tmp, U, g, uV, s, mu, tsign);
     }
+    if (halted) return;  // uniform over the grid: an earlier step stopped the phase
     dir_stash(red, mu, l, acc);
     // alpha_i from the D pass's per-tile shares (its barriers also order the
     // stash); every block adds the same partials in the same order, so every
     // block gets the same alpha
     const double a = part_sum(pa, part_a, ntile, sh);
-    const double d = a - bp * bp / delta[i - 1];  // the LU pivot of step 6
+    const double d = a - bp * bp / dprev;  // the LU pivot of step 6
     const bool bad = !isfinite(a) || (!indef && !(d > 0.0));
     if (b == 0 && threadIdx.x == 0) {  // block 0 always holds a tile
         alpha[i - 1] = a;
