@@ -226,12 +226,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_xp(XT* __restrict__ x, int64_t ld
     const int64_t stride = (int64_t)gridDim.x * kBlock * W;
     for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * W; i0 < N; i0 += stride) {
         if (VEC && sizeof(XT) == sizeof(R) && i0 + W <= N) {
+            // r is loaded with x and p (cont is uniform over the block), so an
+            // iteration waits on memory once, not once for x, p and again for r
             Pack<R> xv = ldp((R*)xc, i0), pv = ldp(pc, i0);
+            Pack<R> rv;
+            if (cont) rv = ldp(rc, i0);
 #pragma unroll
             for (int e = 0; e < W; ++e) xv.v[e] = xv.v[e] + aR * pv.v[e];
             stp((R*)xc, i0, xv);
             if (cont) {
-                const Pack<R> rv = ldp(rc, i0);
 #pragma unroll
                 for (int e = 0; e < W; ++e) pv.v[e] = rv.v[e] + b * pv.v[e];
                 stp(pc, i0, pv);

@@ -261,20 +261,33 @@ __global__ __launch_bounds__(kBlock) void k_nn_mfma(const VR* __restrict__ V, in
 #pragma unroll
         for (int v = 0; v < 4; ++v) lds.qs[wv * 16 + (lane >> 4) + 4 * v][t * 16 + (lane & 15)] = accq[t][v];
     __syncthreads();
+    // every X element this lane updates is loaded (at clamped rows and
+    // columns, so unconditionally) before any is stored: the output columns
+    // are distinct, so no store changes a value loaded here, and the loads are
+    // one round trip instead of one per element
+    XR* xp[NT];
+    XR xo[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int c = min(t * 16 + (lane & 15), 2 * N - 1);
+        const bool re = c < N;
+        xp[t] = (XR*)X.p[re ? c : c - N] + (re ? 0 : 1);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) xo[t][v] = xp[t][2 * min(row0 + wv * 16 + (lane >> 4) + 4 * v, n - 1)];
+    }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int c = t * 16 + (lane & 15);
         if (c >= 2 * N) continue;
         const bool re = c < N;
         const int j = re ? c : c - N;
-        XR* x = (XR*)X.p[j] + (re ? 0 : 1);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int rl = wv * 16 + (lane >> 4) + 4 * v;
             const int64_t r = row0 + rl;
             if (r < n) {
                 const double d = re ? accp[t][v] - lds.qs[rl][N + c] : accp[t][v] + lds.qs[rl][j];
-                x[2 * r] = (XR)((double)x[2 * r] + scale * d);
+                xp[t][2 * r] = (XR)((double)xo[t][v] + scale * d);
             }
         }
     }
@@ -685,18 +698,28 @@ __global__ __launch_bounds__(kBlock) void k_nn_small(const VR* __restrict__ V, i
             for (int t = 0; t < kNnRPT; ++t) vb[t] = vn[t];
         }
     }
+    // every X element of the thread's rows is loaded (at the clamped rows, so
+    // unconditionally) before any is stored: the output columns are distinct,
+    // so no store changes a value loaded here, and the loads are one round
+    // trip instead of one per row and column
+    XR* x0 = (XR*)X.p[0];
+    XR* x1 = (XR*)X.p[N > 1 ? 1 : 0];  // column 0 again when there is one (loaded, not stored)
+    cplx<XR> xa[kNnRPT], xb[kNnRPT];
+#pragma unroll
+    for (int t = 0; t < kNnRPT; ++t) {
+        xa[t] = ld2(x0, rr[t]);
+        xb[t] = ld2(x1, rr[t]);
+    }
 #pragma unroll
     for (int t = 0; t < kNnRPT; ++t) {
         const int64_t r = r0 + (int64_t)t * kBlock;
         if (r >= n) continue;
-        XR* x0 = (XR*)X.p[0];
-        cplx<XR> c = ld2(x0, r);
+        cplx<XR> c = xa[t];
         c.re = (XR)((double)c.re + scale * a0r[t]);
         c.im = (XR)((double)c.im + scale * a0i[t]);
         st2(x0, r, c);
         if (N > 1) {
-            XR* x1 = (XR*)X.p[1];
-            cplx<XR> d = ld2(x1, r);
+            cplx<XR> d = xb[t];
             d.re = (XR)((double)d.re + scale * a1r[t]);
             d.im = (XR)((double)d.im + scale * a1i[t]);
             st2(x1, r, d);
