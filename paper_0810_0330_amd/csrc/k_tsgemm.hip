@@ -94,6 +94,15 @@ __global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, in
     }
     cplx<VR> pv[EV];
     cplx<double> pw[EW];
+    // the W column each of the thread's W elements comes from is the same in
+    // every stage: its pointer is read once here, not (with a wait) in every
+    // stage's fetch
+    const WR* wcol[EW];
+#pragma unroll
+    for (int q = 0; q < EW; ++q) {
+        const int jj = (threadIdx.x + q * kBlock) / KR;
+        wcol[q] = (const WR*)W.p[jj < N ? jj : 0];
+    }
     // element e of a stage: V row e % KR of column e / KR; W row e % KR of complex column e / KR
     auto fetch = [&](int64_t rb) {
 #pragma unroll
@@ -110,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_cn_mfma(const VR* __restrict__ V, in
             const int jj = e / KR;
             cplx<double> w{0.0, 0.0};
             if (r < r1 && jj < N) {
-                const cplx<WR> c = ld2((const WR*)W.p[jj], r);
+                const cplx<WR> c = ld2(wcol[q], r);
                 w = {(double)c.re, (double)c.im};
             }
             pw[q] = w;
