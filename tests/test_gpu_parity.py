@@ -23,6 +23,7 @@ Tolerances:
     are i.i.d. (Gaussian) in that case; a run with m inside the horizon is
     held to +-2 of the single oracle run.
 """
+import ctypes
 import json
 import os
 
@@ -597,6 +598,72 @@ def test_seed_alpha_beta_on_x16_lattice():
         eb = np.abs(bb - ref.beta[: m + 1]).max() / np.abs(ref.beta[: m + 1]).max()
         _say("  ", vdt, "alpha err %.2e beta err %.2e" % (ea, eb))
         assert ea <= bar and eb <= bar, (vdt, ea, eb)
+
+
+def _seed_sentinel(op, b1, m, freq, vdt, sent=12345.0):
+    """sc_seed_lanczos with alpha, beta and V filled with a sentinel beforehand,
+    so that what the phase wrote after it stopped shows."""
+    b1 = b1.to(op.dtype).reshape(-1).contiguous()
+    x1 = torch.zeros_like(b1)
+    V = torch.full((m + 1, op.n), complex(sent, -sent), dtype=vdt, device=DEV)
+    alpha = torch.full((m,), sent, dtype=torch.float64, device=DEV)
+    beta = torch.full((m + 1,), sent, dtype=torch.float64, device=DEV)
+    nb = api._SZ()
+    api._check(api.lib().sc_workspace_size(op.handle, api.SC_CALL_SEED, 1, m, api._DT_OF[vdt], ctypes.byref(nb)))
+    w = api._work(nb.value, op.device)
+    md = api._INT()
+    st = api.lib().sc_seed_lanczos(op.handle, api._ptr(b1), api._ptr(x1), m, freq, api._ptr(V), op.n,
+                                   api._DT_OF[vdt], api._ptr(alpha), api._ptr(beta), ctypes.byref(md),
+                                   api._ptr(w), w.numel(), api._stream())
+    torch.cuda.synchronize()
+    return st, md.value, x1.cpu().numpy(), V.cpu().numpy(), alpha.cpu().numpy(), beta.cpu().numpy()
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (16, 2, 2, 8)])
+def test_fused_wilson_seed_halts(dims):
+    # the fused Wilson Lanczos passes stop the phase themselves (breakdown,
+    # non-finite alpha or beta) and write nothing once it has stopped: alpha,
+    # beta and the basis are filled with a sentinel beforehand.  X = 16 takes
+    # the x hops through the lanes of an x-row.
+    sent = 12345.0
+    b = synth.point_sources(dims, [(0, 0)])  # unit delta at the origin
+    m = 6
+    # kappa = 0: A = 1, so alpha_1 = 1 and f = v_1 - v_1 = 0 exactly in both
+    # precisions; the D pass of step 2 finds beta_1 = 0: m_done = 1, v_2 = 0, x^1 = b
+    U = synth.su3_links(dims, synth.rng(21, 0))
+    op = api.Op.wilson(dims, torch.from_numpy(api.pack_links(U)).to(DEV), 0.0)
+    for vdt in (torch.complex128, torch.complex64):
+        for freq in (0, 1):
+            _say("fused seed halt: breakdown", dims, vdt, "freq", freq)
+            st, md, x1, V, al, be = _seed_sentinel(op, _to_lib(b)[0], m, freq, vdt, sent)
+            assert st == 2 and md == 1, (st, md)
+            assert al[0] == 1.0 and be[0] == 1.0 and be[1] == 0.0
+            assert np.all(al[1:] == sent) and np.all(be[2:] == sent)
+            assert np.all(V[1] == 0) and np.all(V[2:] == complex(sent, -sent))
+            np.testing.assert_array_equal(_to_nat(torch.from_numpy(x1[None]))[:, 0], b[:, 0])
+    # the t-link at (x, t) = (1, 1) scaled up: v_1 and D v_1 are zero at both
+    # of its ends, v_2 is not (A reaches the sites two hops off the origin
+    # that are not on a straight line), so step 2 overflows.  FP64 (scale
+    # 1e200): alpha_2 = ||D v_2||^2 - ... is not finite, which the D^H pass of
+    # step 2 finds.  FP32 (scale 1e25, links rounded to FP32): alpha_2 is
+    # finite in FP64 but not in FP32, so f_2 and beta_2 are not finite, which
+    # the D pass of step 3 finds.  Either way m_done = 1 and x^1 stays x0 = 0.
+    for vdt, scale in ((torch.complex128, 1e200), (torch.complex64, 1e25)):
+        Ub = U.copy()
+        Ub[3, 1, 0, 0, 1] *= scale  # links are (mu, T, Z, Y, X, 3, 3), mu = 3 is t
+        opb = api.Op.wilson(dims, torch.from_numpy(api.pack_links(Ub)).to(DEV), 0.12)
+        _say("fused seed halt: overflow", dims, vdt)
+        st, md, x1, V, al, be = _seed_sentinel(opb, _to_lib(b)[0], m, 1, vdt, sent)
+        assert st == -4 and md == 1, (st, md)
+        assert np.all(np.isfinite(al[:1])) and np.all(np.isfinite(be[:2])) and np.all(np.isfinite(V[:2]))
+        assert np.all(x1 == 0)
+        if vdt == torch.complex128:
+            assert not np.isfinite(al[1]) and np.all(al[2:] == sent) and np.all(be[2:] == sent)
+            assert np.all(V[2:] == complex(sent, -sent))
+        else:
+            assert np.isfinite(al[1]) and not np.isfinite(be[2])
+            assert np.all(al[2:] == sent) and np.all(be[3:] == sent)
+            assert np.all(V[2] == 0) and np.all(V[3:] == complex(sent, -sent))
 
 
 def test_seeded_solve_periodic_time():
