@@ -112,6 +112,23 @@ sc_status sc_op_wilson_normal(const int dims[4], const void* U64_dev, const void
 sc_status sc_op_wilson_g5(const int dims[4], const void* U64_dev, const void* U32_dev, double kappa,
                           int t_antiperiodic, sc_op** out);
 
+/* Checks on the GPU whether every link of a Wilson operator (either kind) is
+ * in SU(3): the largest over the links of the entrywise moduli of
+ * U U^H - 1 and of |det U - 1|, in FP64 from U64_dev, is returned in
+ * *deviation (host, may be NULL; +inf if a link holds a value that is not
+ * finite).  When it is at most 1e-9 and the op has U32_dev, the op's
+ * single-precision passes from then on read rows 0 and 1 of each link and
+ * rebuild row 2 as the complex conjugate of their cross product (which holds
+ * for unitary matrices of determinant 1): 12 instead of 18 reals per link,
+ * equal to the stored row up to FP32 rounding.  *rebuild (host, may be NULL)
+ * is 1 then and 0 otherwise, and 0 until this is called.  The links must not
+ * change afterwards to values outside SU(3) unless this is called again.
+ * Not part of the method: a smaller form of the data it reads.  Runs on
+ * `stream`, allocates 8 bytes of device memory for the duration of the call
+ * and synchronizes the stream once.  Errors: SC_ERR_ARG for an op that is
+ * not a Wilson operator; SC_ERR_HIP. */
+sc_status sc_op_wilson_check_su3(sc_op* op, void* stream, double* deviation, int* rebuild);
+
 sc_status sc_op_destroy(sc_op* op);
 
 /* Vector length n and the op's full-precision dtype (SC_R64 or SC_C128). */

@@ -51,6 +51,7 @@ _PROTOS = {
     "sc_indefinite_solve": [_P, _P, _I64, _P, _I64, _INT, _INT, _INT, _DBL, _INT, ctypes.POINTER(_INT),
                             ctypes.POINTER(_DBL), ctypes.POINTER(_INT), _P, _SZ, _P],
     "sc_op_destroy": [_P],
+    "sc_op_wilson_check_su3": [_P, _P, ctypes.POINTER(_DBL), ctypes.POINTER(_INT)],
     "sc_op_info": [_P, ctypes.POINTER(_I64), ctypes.POINTER(_INT)],
     "sc_op_apply": [_P, _INT, _P, _I64, _P, _I64, _INT, _P, _SZ, _P],
     "sc_wilson_dslash": [_P, _INT, _INT, _P, _I64, _P, _I64, _INT, _P],
@@ -211,6 +212,18 @@ class Op:
         self.sc_dtype = dt.value
         self.dtype = _TORCH_DT[dt.value]
         self.single_dtype = torch.complex64 if dt.value == SC_C128 else torch.float32
+        self.su3_deviation = None  # Wilson: largest deviation of a link from SU(3), once checked
+        self.rebuild = False       # Wilson: FP32 passes read 2 rows of each link and rebuild the third
+
+    def check_su3(self):
+        """Check the links for SU(3) on the GPU (on the current stream); when they pass and the op
+        has FP32 links, its FP32 passes rebuild each link's third row.  Returns the deviation."""
+        dev = _DBL()
+        rb = _INT()
+        _check(lib().sc_op_wilson_check_su3(self._h, _stream(), ctypes.byref(dev), ctypes.byref(rb)))
+        self.su3_deviation = dev.value
+        self.rebuild = bool(rb.value)
+        return dev.value
 
     @property
     def handle(self):
@@ -240,8 +253,10 @@ class Op:
         return cls(h, [d], d.device, "diag")
 
     @classmethod
-    def wilson(cls, dims, U, kappa, antiperiodic=True, single=True):
-        """A = D^H D.  dims = (X, Y, Z, T); U: links in the library layout (pack_links), complex128 on the GPU."""
+    def wilson(cls, dims, U, kappa, antiperiodic=True, single=True, rebuild=True):
+        """A = D^H D.  dims = (X, Y, Z, T); U: links in the library layout (pack_links), complex128 on the GPU.
+        single: keep an FP32 copy of the links for the single-precision passes; rebuild: check the links
+        for SU(3) so that those passes may read two rows of each link and rebuild the third."""
         _require_gpu(U)
         U64 = U.to(torch.complex128).contiguous()
         U32 = U64.to(torch.complex64) if single else None
@@ -249,11 +264,14 @@ class Op:
         h = _P()
         _check(lib().sc_op_wilson_normal(d, _ptr(U64), _ptr(U32) if U32 is not None else None, float(kappa),
                                          1 if antiperiodic else 0, ctypes.byref(h)))
-        return cls(h, [U64, U32], U64.device, "wilson", dims=tuple(dims), kappa=float(kappa),
-                   antiperiodic=antiperiodic)
+        op = cls(h, [U64, U32], U64.device, "wilson", dims=tuple(dims), kappa=float(kappa),
+                 antiperiodic=antiperiodic)
+        if single and rebuild:
+            op.check_su3()
+        return op
 
     @classmethod
-    def wilson_g5(cls, dims, U, kappa, antiperiodic=True, single=False):
+    def wilson_g5(cls, dims, U, kappa, antiperiodic=True, single=False, rebuild=True):
         """Q = gamma_5 D (Hermitian indefinite; D x = b is Q x = gamma_5 b).  Arguments as wilson()."""
         _require_gpu(U)
         U64 = U.to(torch.complex128).contiguous()
@@ -262,8 +280,11 @@ class Op:
         h = _P()
         _check(lib().sc_op_wilson_g5(d, _ptr(U64), _ptr(U32) if U32 is not None else None, float(kappa),
                                      1 if antiperiodic else 0, ctypes.byref(h)))
-        return cls(h, [U64, U32], U64.device, "wilson_g5", dims=tuple(dims), kappa=float(kappa),
-                   antiperiodic=antiperiodic)
+        op = cls(h, [U64, U32], U64.device, "wilson_g5", dims=tuple(dims), kappa=float(kappa),
+                 antiperiodic=antiperiodic)
+        if single and rebuild:
+            op.check_su3()
+        return op
 
     def _vec(self, X, dtype):
         if X.dim() == 1:

@@ -168,6 +168,13 @@ sc_status sc_op_wilson_g5(const int dims[4], const void* U64_dev, const void* U3
     SC_GUARD_END
 }
 
+sc_status sc_op_wilson_check_su3(sc_op* op, void* stream, double* deviation, int* rebuild) {
+    SC_GUARD_BEGIN
+    SC_ARG(op && has_links(op), "op is NULL or not a Wilson operator");
+    return wilson_check_su3(op, (hipStream_t)stream, deviation, rebuild);
+    SC_GUARD_END
+}
+
 sc_status sc_op_destroy(sc_op* op) {
     SC_GUARD_BEGIN
     if (op) batch_forget_op(op);

@@ -107,6 +107,7 @@ GraphKey make_key(int nsys, const sc_batch_system* sys, const void* work, hipStr
         put(&op->U32, sizeof op->U32);
         put(&op->kappa, sizeof op->kappa);
         put(&op->antiperiodic, sizeof op->antiperiodic);
+        put(&op->su3, sizeof op->su3);
         // the stencil shape the seed phase's one-column passes were tuned to
         int variant = -1;
         if (has_links(op)) {

@@ -645,7 +645,7 @@ __global__ __launch_bounds__(kBlock * NZ) void k_wilson_tm(R* __restrict__ out, 
 // spin component w of the result.  Four times the waves of the one-site-per-
 // thread form, each with a chain of two dependent hops instead of eight: for
 // launches too small to hide memory latency otherwise.
-template <typename R, bool DAG, int MODE>
+template <typename R, bool DAG, int MODE, bool REC>
 __global__ __launch_bounds__(kBlock) void k_wilson_dir(R* __restrict__ out, int64_t ldo, const R* __restrict__ in,
                                                        int64_t ldi, const R* __restrict__ U, Geom g, R kappa,
                                                        R tsign, int k, int ntile, int per_xcd) {
@@ -665,8 +665,8 @@ __global__ __launch_bounds__(kBlock) void k_wilson_dir(R* __restrict__ out, int6
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
     if (ok) {  // the x hops by DPP when a lane row is an x-row (X = 16)
-        if (mu == 0 && g.X == 16) dir_hops_x16<DAG, R>(acc, src, U, uV, s);
-        else dir_hops<DAG, R>(acc, src, U, g, uV, s, mu, tsign);
+        if (mu == 0 && g.X == 16) dir_hops_x16<DAG, R, REC>(acc, src, U, uV, s);
+        else dir_hops<DAG, R, REC>(acc, src, U, g, uV, s, mu, tsign);
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -763,9 +763,16 @@ static void tx_launch(const sc_op* op, int v, bool dag, int epi, const float* X,
     const TxGeom q = tx_geom(op, v, k);
     const dim3 grid((unsigned)q.blocks), blk(kBlock);
     const float kap = (float)op->kappa, ts = op->antiperiodic ? -1.0f : 1.0f;
-#define SC_TX(DAG, EPI_, NC_)                                                                                     \
-    SC_TLAUNCH((k_wilson_tx<DAG, EPI_, NC_>), grid, blk, 0, s, Y, 2 * ldy, X, 2 * ldx, U, g, kap, ts, k, q.nseg, \
-               q.tlen, q.per_xcd, q.order, e)
+    // SU(3) links: rows 0 and 1 of each link read, row 2 rebuilt
+#define SC_TX(DAG, EPI_, NC_)                                                                                         \
+    do {                                                                                                              \
+        if (op->su3)                                                                                                  \
+            SC_TLAUNCH((k_wilson_tx<DAG, EPI_, NC_, true>), grid, blk, 0, s, Y, 2 * ldy, X, 2 * ldx, U, g, kap, ts, \
+                       k, q.nseg, q.tlen, q.per_xcd, q.order, e);                                                     \
+        else                                                                                                          \
+            SC_TLAUNCH((k_wilson_tx<DAG, EPI_, NC_, false>), grid, blk, 0, s, Y, 2 * ldy, X, 2 * ldx, U, g, kap,    \
+                       ts, k, q.nseg, q.tlen, q.per_xcd, q.order, e);                                                 \
+    } while (0)
 #define SC_TXE(NC_)                                 \
     if (epi == TM_NORM) SC_TX(false, TM_NORM, NC_); \
     else if (epi == TM_CG) SC_TX(true, TM_CG, NC_); \
@@ -955,9 +962,16 @@ static void wilson_launch_dir(const sc_op* op, int which, const R* X, int64_t ld
     dim3 grid((unsigned)(per_xcd * kXcd));
     const R kap = (R)op->kappa;
     const R ts = op->antiperiodic ? R(-1) : R(1);
-#define SC_WD(DAG, MODE)                                                                                         \
-    SC_TLAUNCH((k_wilson_dir<R, DAG, MODE>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X, 2 * ldx, U, g, kap, \
-                       ts, k, ntile, per_xcd);
+    // SU(3) links in a single-precision pass: rows 0 and 1 read, row 2 rebuilt
+    constexpr bool kRec = sizeof(R) == 4;
+    const bool rec = kRec && op->su3;
+#define SC_WD(DAG, MODE)                                                                                           \
+    if (rec)                                                                                                       \
+        SC_TLAUNCH((k_wilson_dir<R, DAG, MODE, kRec>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X, 2 * ldx, U, g,  \
+                   kap, ts, k, ntile, per_xcd);                                                                    \
+    else                                                                                                           \
+        SC_TLAUNCH((k_wilson_dir<R, DAG, MODE, false>), grid, dim3(kBlock), 0, s, Y, 2 * ldy, X, 2 * ldx, U, g, \
+                   kap, ts, k, ntile, per_xcd);
     switch (which) {
         case 0: SC_WD(false, 0) break;
         case 1: SC_WD(true, 0) break;
@@ -1102,10 +1116,12 @@ namespace {
 struct TuneKey {
     int dims[4];
     int single, k;
+    int rec;  // single-precision passes rebuilding row 2 of SU(3) links (they move fewer bytes)
     bool operator<(const TuneKey& o) const {
         for (int i = 0; i < 4; ++i)
             if (dims[i] != o.dims[i]) return dims[i] < o.dims[i];
         if (single != o.single) return single < o.single;
+        if (rec != o.rec) return rec < o.rec;
         return k < o.k;
     }
 };
@@ -1197,7 +1213,8 @@ static bool tune_variants(const sc_op* op, int which, const R* X, int64_t ldx, R
 template <typename R>
 static int choose_variant(const sc_op* op, int which, const R* X, int64_t ldx, R* Y, int64_t ldy, int k, const R* U,
                           hipStream_t s) {
-    TuneKey key{{op->dims[0], op->dims[1], op->dims[2], op->dims[3]}, sizeof(R) == 4 ? 1 : 0, k};
+    TuneKey key{{op->dims[0], op->dims[1], op->dims[2], op->dims[3]}, sizeof(R) == 4 ? 1 : 0, k,
+                (sizeof(R) == 4 && op->su3) ? 1 : 0};
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
     if (it != g_tune.end()) return it->second.best;
@@ -1223,7 +1240,7 @@ sc_status wilson_tune_pin(const sc_op* op, bool single, int k, int variant) {
         set_error("wilson_tune_set: the DPP shapes need FP32, X = Y = 16 and |kappa| >= 1e-6");
         return SC_ERR_ARG;
     }
-    TuneKey key{{op->dims[0], op->dims[1], op->dims[2], op->dims[3]}, single ? 1 : 0, k};
+    TuneKey key{{op->dims[0], op->dims[1], op->dims[2], op->dims[3]}, single ? 1 : 0, k, (single && op->su3) ? 1 : 0};
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (variant < 0) {
         g_tune.erase(key);
@@ -1237,7 +1254,7 @@ sc_status wilson_tune_pin(const sc_op* op, bool single, int k, int variant) {
 }
 
 sc_status wilson_tune_query(const sc_op* op, bool single, int k, int* variant, float* us) {
-    TuneKey key{{op->dims[0], op->dims[1], op->dims[2], op->dims[3]}, single ? 1 : 0, k};
+    TuneKey key{{op->dims[0], op->dims[1], op->dims[2], op->dims[3]}, single ? 1 : 0, k, (single && op->su3) ? 1 : 0};
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
     if (it == g_tune.end()) {

@@ -23,6 +23,9 @@ struct sc_op {
     const void* U32 = nullptr;
     double kappa = 0.0;
     int antiperiodic = 1;
+    // every link of U64 is in SU(3) to within 1e-9 (checked at creation): the
+    // single-precision passes read rows 0 and 1 of a link and rebuild row 2
+    int su3 = 0;
     // distinct for every op the process creates (an op allocated at a freed
     // op's address is still a different op to the caches keyed on it)
     uint64_t gen = 0;
@@ -85,6 +88,10 @@ sc_status wilson_pass(const sc_op* op, bool single, int which, const void* X, in
 // autotuned stencil launch shape for (op lattice, precision, k): variant id
 // (-1 if not tuned yet) and the measured microseconds of each candidate
 sc_status wilson_tune_query(const sc_op* op, bool single, int k, int* variant, float* us);
+// SU(3) check of a Wilson operator's links (links.hip): sets op->su3 when every
+// link of U64 is in SU(3) to within kSu3Tol and the op has U32
+constexpr double kSu3Tol = 1e-9;
+sc_status wilson_check_su3(sc_op* op, hipStream_t s, double* deviation, int* rebuild);
 // pin a variant for (lattice, precision, k); variant < 0 forgets the choice
 sc_status wilson_tune_pin(const sc_op* op, bool single, int k, int variant);
 // host-side walk of every buffer access of a DPP-form stencil launch (no GPU)

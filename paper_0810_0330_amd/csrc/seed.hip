@@ -289,7 +289,7 @@ __device__ __forceinline__ double part_sum(const PartPre<P>& q, const double* __
     return block_sum(s, sh);
 }
 
-template <typename R, typename VT>
+template <typename R, typename VT, bool REC>
 __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const R* __restrict__ f,
                                                      VT* __restrict__ vnext, const VT* __restrict__ vprev,
                                                      const R* __restrict__ U, Geom g, R kappa, R tsign, int ntile,
@@ -329,8 +329,8 @@ __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const 
             po[cc] = reinterpret_cast<const typename vec2<VT>::type*>(vprev)[(mu * 3 + cc) * uV + s];
         }
     if (ok) {  // the x hops by DPP when a lane row is an x-row (X = 16)
-        if (mu == 0 && g.X == 16) dir_hops_x16<false, R>(acc, f, U, uV, s);
-        else dir_hops<false, R>(acc, f, U, g, uV, s, mu, tsign);
+        if (mu == 0 && g.X == 16) dir_hops_x16<false, R, REC>(acc, f, U, uV, s);
+        else dir_hops<false, R, REC>(acc, f, U, g, uV, s, mu, tsign);
     }
     if (halted) return;  // uniform over the grid: an earlier step stopped the phase
     dir_stash(red, mu, l, acc);
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_dnext(R* __restrict__ tmp, const 
     if (threadIdx.x == 0) part_a[L] = at;
 }
 
-template <typename R>
+template <typename R, bool REC>
 __global__ __launch_bounds__(kBlock) void k_lz_dhalpha(R* __restrict__ f, const R* __restrict__ tmp,
                                                        const R* __restrict__ vi, const R* __restrict__ vprev,
                                                        const R* __restrict__ U, Geom g, R kappa, R tsign, int ntile,
@@ -406,8 +406,8 @@ __global__ __launch_bounds__(kBlock) void k_lz_dhalpha(R* __restrict__ f, const 
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) acc[a][cc] = {R(0), R(0)};
     if (ok) {  // the x hops by DPP when a lane row is an x-row (X = 16)
-        if (mu == 0 && g.X == 16) dir_hops_x16<true, R>(acc, tmp, U, uV, s);
-        else dir_hops<true, R>(acc, tmp, U, g, uV, s, mu, tsign);
+        if (mu == 0 && g.X == 16) dir_hops_x16<true, R, REC>(acc, tmp, U, uV, s);
+        else dir_hops<true, R, REC>(acc, tmp, U, g, uV, s, mu, tsign);
     }
     dir_stash(red, mu, l, acc);
     __syncthreads();
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_dhalpha(R* __restrict__ f, const 
 // D^H pass of step i >= 2: alpha_i from the D pass's partials, the pivot of
 // step 6, and the final f = D^H (D v_i) - beta_{i-1} v_{i-1} - alpha_i v_i with
 // the partials of ||f||^2
-template <typename R>
+template <typename R, bool REC>
 __global__ __launch_bounds__(kBlock) void k_lz_dhf(R* __restrict__ f, const R* __restrict__ tmp,
                                                    const R* __restrict__ vi, const R* __restrict__ vprev,
                                                    const R* __restrict__ U, Geom g, R kappa, R tsign, int ntile,
@@ -478,8 +478,8 @@ __global__ __launch_bounds__(kBlock) void k_lz_dhf(R* __restrict__ f, const R* _
             vo[cc] = ldc(vi + cb, (unsigned)s);
         }
     if (ok) {  // the x hops by DPP when a lane row is an x-row (X = 16)
-        if (mu == 0 && g.X == 16) dir_hops_x16<true, R>(acc, tmp, U, uV, s);
-        else dir_hops<true, R>(acc, tmp, U, g, uV, s, mu, tsign);
+        if (mu == 0 && g.X == 16) dir_hops_x16<true, R, REC>(acc, tmp, U, uV, s);
+        else dir_hops<true, R, REC>(acc, tmp, U, g, uV, s, mu, tsign);
     }
     if (halted) return;  // uniform over the grid: an earlier step stopped the phase
     dir_stash(red, mu, l, acc);
@@ -604,6 +604,11 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
     const R tsg = op->antiperiodic ? R(-1) : R(1);
     const double pass_bytes = (48.0 + 72.0) * sizeof(R) * (double)op->vol;
     const int tcls = single ? TC_WILSON_F32 : TC_WILSON_F64;
+    // links in SU(3) and a single-precision pass: the fused kernels read rows
+    // 0 and 1 of each link and rebuild row 2 (kRec is false for FP64, which
+    // always reads the whole link)
+    const bool rec = single && op->su3;
+    constexpr bool kRec = sizeof(R) == 4;
     R* tmpv = (R*)w.tmp;
     int gf = g;  // partials of ||f||^2 left by the previous step
 
@@ -616,8 +621,12 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
             SC_TRY(wilson_pass(op, single, 0, vi, ldv, tmpv, op->n, 1, s));
             {
                 TimerScope ts_(tcls, s, pass_bytes + 48.0 * sizeof(R) * op->vol, 1368.0 * op->vol);
-                SC_TLAUNCH((k_lz_dhalpha<R>), dgrid, blk, 0, s, f, (const R*)tmpv, (const R*)vi,
-                                   (const R*)vprev, U, geo, kapR, tsg, ntile, per_xcd, beta, i, w.st, w.part_a);
+#define SC_LZ_DHALPHA(REC_)                                                                               \
+    SC_TLAUNCH((k_lz_dhalpha<R, REC_>), dgrid, blk, 0, s, f, (const R*)tmpv, (const R*)vi, (const R*)vprev, U, \
+               geo, kapR, tsg, ntile, per_xcd, beta, i, w.st, w.part_a)
+                if (rec) SC_LZ_DHALPHA(kRec);
+                else SC_LZ_DHALPHA(false);
+#undef SC_LZ_DHALPHA
                 SC_LAUNCH_CHECK();
             }
             hipLaunchKernelGGL((k_lz_f<R, VEC>), dim3(g), blk, 0, s, f, vi, N2, alpha, beta, w.delta, i, w.st,
@@ -629,15 +638,22 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
             // D^H pass with step 5 (alpha_i, the pivot, the final f, its norm partials)
             {
                 TimerScope ts_(tcls, s, pass_bytes + 48.0 * sizeof(R) * op->vol, 1368.0 * op->vol);
-                SC_TLAUNCH((k_lz_dnext<R, R>), dgrid, blk, 0, s, tmpv, (const R*)f, vi, (const R*)vprev, U, geo,
-                                   kapR, tsg, ntile, per_xcd, beta, i - 1, w.st, w.part_f, gf, w.part_a);
+#define SC_LZ_DNEXT(REC_)                                                                                    \
+    SC_TLAUNCH((k_lz_dnext<R, R, REC_>), dgrid, blk, 0, s, tmpv, (const R*)f, vi, (const R*)vprev, U, geo, kapR, \
+               tsg, ntile, per_xcd, beta, i - 1, w.st, w.part_f, gf, w.part_a)
+                if (rec) SC_LZ_DNEXT(kRec);
+                else SC_LZ_DNEXT(false);
+#undef SC_LZ_DNEXT
                 SC_LAUNCH_CHECK();
             }
             {
                 TimerScope ts_(tcls, s, pass_bytes + 48.0 * sizeof(R) * op->vol, 1416.0 * op->vol);
-                SC_TLAUNCH((k_lz_dhf<R>), dgrid, blk, 0, s, f, (const R*)tmpv, (const R*)vi, (const R*)vprev, U,
-                                   geo, kapR, tsg, ntile, per_xcd, alpha, beta, w.delta, i, w.st, w.part_a, w.part_f,
-                                   indef);
+#define SC_LZ_DHF(REC_)                                                                                      \
+    SC_TLAUNCH((k_lz_dhf<R, REC_>), dgrid, blk, 0, s, f, (const R*)tmpv, (const R*)vi, (const R*)vprev, U, geo, \
+               kapR, tsg, ntile, per_xcd, alpha, beta, w.delta, i, w.st, w.part_a, w.part_f, indef)
+                if (rec) SC_LZ_DHF(kRec);
+                else SC_LZ_DHF(false);
+#undef SC_LZ_DHF
                 SC_LAUNCH_CHECK();
             }
             gf = ntile;

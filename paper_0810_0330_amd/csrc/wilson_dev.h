@@ -157,12 +157,29 @@ __device__ __forceinline__ void load_spinor(const R* __restrict__ f, unsigned V,
         for (int c = 0; c < 3; ++c) psi[s][c] = ldc(f + 2 * (size_t)((s * 3 + c) * V), site);
 }
 
+// Row 2 of a matrix of SU(3) from rows 0 and 1: for a unitary matrix of
+// determinant 1 it is the complex conjugate of their cross product.
 template <typename R>
+__device__ __forceinline__ void su3_row2(cplx<R> u[3][3]) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+        const cplx<R> p = u[0][b1], q = u[1][b2], r = u[0][b2], w = u[1][b1];
+        const R re = (p.re * q.re - p.im * q.im) - (r.re * w.re - r.im * w.im);
+        const R im = (p.re * q.im + p.im * q.re) - (r.re * w.im + r.im * w.re);
+        u[2][b] = {re, -im};
+    }
+}
+
+// The link U_mu(site).  REC (links known to be in SU(3)): rows 0 and 1 are
+// read and row 2 is rebuilt from them, 12 of the 18 reals of the link.
+template <typename R, bool REC = false>
 __device__ __forceinline__ void load_link(const R* __restrict__ U, unsigned V, int mu, unsigned site, cplx<R> u[3][3]) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < (REC ? 2 : 3); ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) u[a][b] = ldc(U + 2 * (size_t)(((mu * 3 + a) * 3 + b) * V), site);
+    if constexpr (REC) su3_row2(u);
 }
 
 
@@ -234,13 +251,13 @@ __device__ __forceinline__ double dpp_from_xm(double v) {
 // and the backward hop the product of lane x - 1 through DPP.  Each quantity
 // is the one the loading form computes from the neighbour's data, so the
 // result is the same.
-template <bool DAG, typename R>
+template <bool DAG, typename R, bool REC = false>
 __device__ __forceinline__ void dir_hops_x16(cplx<R> acc[4][3], const R* __restrict__ src, const R* __restrict__ U,
                                              unsigned uV, int s) {
     constexpr int SF = DAG ? 1 : -1;
     constexpr int SB = -SF;
     cplx<R> u[3][3], psi[4][3];
-    load_link(U, uV, 0, (unsigned)s, u);
+    load_link<R, REC>(U, uV, 0, (unsigned)s, u);
     load_spinor(src, uV, (unsigned)s, psi);
     cplx<R> h0[3], h1[3], g0[3], g1[3], c0[3], c1[3];
     project<0, SF>(psi, h0, h1);  // what lane x - 1 needs for its forward hop
@@ -262,7 +279,7 @@ __device__ __forceinline__ void dir_hops_x16(cplx<R> acc[4][3], const R* __restr
 
 // acc += the forward and backward hops of direction mu at site s (one
 // direction of the hopping term; mu wave-uniform)
-template <bool DAG, typename R>
+template <bool DAG, typename R, bool REC = false>
 __device__ __forceinline__ void dir_hops(cplx<R> acc[4][3], const R* __restrict__ src, const R* __restrict__ U,
                                          const Geom& g, unsigned uV, int s, int mu, R tsign) {
     constexpr int SF = DAG ? 1 : -1;
@@ -271,7 +288,7 @@ __device__ __forceinline__ void dir_hops(cplx<R> acc[4][3], const R* __restrict_
     R bfp, bfm;
     neighbours<R>(g, s, mu, tsign, np, nm, bfp, bfm);
     cplx<R> u[3][3], psi[4][3];
-    load_link(U, uV, mu, (unsigned)s, u);
+    load_link<R, REC>(U, uV, mu, (unsigned)s, u);
     load_spinor(src, uV, (unsigned)np, psi);
     switch (mu) {
         case 0: hop<0, SF, false>(acc, psi, u, bfp); break;
@@ -279,7 +296,7 @@ __device__ __forceinline__ void dir_hops(cplx<R> acc[4][3], const R* __restrict_
         case 2: hop<2, SF, false>(acc, psi, u, bfp); break;
         default: hop<3, SF, false>(acc, psi, u, bfp); break;
     }
-    load_link(U, uV, mu, (unsigned)nm, u);
+    load_link<R, REC>(U, uV, mu, (unsigned)nm, u);
     load_spinor(src, uV, (unsigned)nm, psi);
     switch (mu) {
         case 0: hop<0, SB, true>(acc, psi, u, bfm); break;

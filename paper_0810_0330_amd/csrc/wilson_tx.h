@@ -145,15 +145,18 @@ __device__ __forceinline__ unsigned tx_opaque(unsigned x) {
     asm volatile("" : "+v"(x));
     return x;
 }
+// REC (links in SU(3)): rows 0 and 1 are read, row 2 rebuilt from them
+template <bool REC>
 __device__ __forceinline__ void tx_link(const TxBuf& U, unsigned V, int mu, unsigned site, cplx<float> u[3][3]) {
     const unsigned boff = tx_boff(site);
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < (REC ? 2 : 3); ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) u[a][b] = tx_ld(U, boff, tx_soff((mu * 3 + a) * 3 + b, V));
+    if constexpr (REC) su3_row2(u);
 }
 
-template <bool DAG, int EPI, int NC>
+template <bool DAG, int EPI, int NC, bool REC>
 __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __restrict__ out, int64_t ldo,
                                                                      const float* __restrict__ in, int64_t ldi,
                                                                      const float* __restrict__ U, Geom g, float kappa,
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
         const unsigned sm = (unsigned)tx_site(p, z, tm, g.Z);
         const float bf = t0 == 0 ? tsign : 1.0f;
         C u[3][3];
-        tx_link(Ub, uV, 3, sm, u);
+        tx_link<REC>(Ub, uV, 3, sm, u);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             C psi[4][3], h0[3], h1[3];
@@ -259,7 +262,7 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
         // y, source side: the halves the +-y neighbours need, into LDS
         {
             C u[3][3];
-            tx_link(Ub, uV, 1, s, u);
+            tx_link<REC>(Ub, uV, 1, s, u);
             __syncthreads();  // the previous slice's reads of ys are done
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
         // x: both hops through the lanes of this row
         {
             C u[3][3];
-            tx_link(Ub, uV, 0, s, u);
+            tx_link<REC>(Ub, uV, 0, s, u);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 C h0[3], h1[3], g0[3], g1[3], c0[3], c1[3];
@@ -304,7 +307,7 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
         // t: the -t hop of the next slice, formed from this one (the last use of cur)
         {
             C u[3][3];
-            tx_link(Ub, uV, 3, s, u);
+            tx_link<REC>(Ub, uV, 3, s, u);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 C h0[3], h1[3];
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
         // z: the neighbouring planes from global memory
         {
             C u[3][3];
-            tx_link(Ub, uV, 2, s, u);
+            tx_link<REC>(Ub, uV, 2, s, u);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 C psi[4][3], h0[3], h1[3], c0[3], c1[3];
@@ -332,7 +335,7 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
         {
             C u[3][3];
             const unsigned sm = (unsigned)((int)s + zoff_m);
-            tx_link(Ub, uV, 2, sm, u);
+            tx_link<REC>(Ub, uV, 2, sm, u);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 C psi[4][3], h0[3], h1[3], c0[3], c1[3];
@@ -348,7 +351,7 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
         {
             C u[3][3];
             __syncthreads();  // every lane's halves are in ys
-            tx_link(Ub, uV, 1, tx_opaque(s), u);  // U_y(s) again
+            tx_link<REC>(Ub, uV, 1, tx_opaque(s), u);  // U_y(s) again
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 C h0[3], h1[3], c0[3], c1[3];
@@ -380,7 +383,7 @@ __global__ __launch_bounds__(kBlock, NC == 1 ? 4 : 3) void k_wilson_tx(float* __
         const float bf = tlast ? tsign : 1.0f;
         {
             C u[3][3];
-            tx_link(Ub, uV, 3, tx_opaque(s), u);  // U_t(s) again
+            tx_link<REC>(Ub, uV, 3, tx_opaque(s), u);  // U_t(s) again
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 C q[4][3];

@@ -53,6 +53,14 @@ def test_op_argument_errors(lib):
     assert b"aligned" in lib.sc_last_error()
     assert lib.sc_op_wilson_normal(dims, ctypes.c_void_p(256), None, ctypes.c_double(float("nan")), 1,
                                    ctypes.byref(out)) == -1
+    # the SU(3) check of the links: a Wilson operator only (refused on the host)
+    dev = ctypes.c_double()
+    rb = ctypes.c_int()
+    assert lib.sc_op_wilson_check_su3(None, None, ctypes.byref(dev), ctypes.byref(rb)) == -1
+    assert lib.sc_op_laplace2d(4, 4, ctypes.byref(out)) == 0
+    assert lib.sc_op_wilson_check_su3(out, None, ctypes.byref(dev), ctypes.byref(rb)) == -1
+    assert b"Wilson" in lib.sc_last_error()
+    assert lib.sc_op_destroy(out) == 0
 
 
 def test_op_create_info_destroy_on_host(lib):

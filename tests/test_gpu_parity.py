@@ -170,10 +170,11 @@ def test_wilson_passes(dims):
     assert _rel(yn, refn) < 1e-13
 
 
-@pytest.mark.parametrize("dims,k", [((3, 5, 4, 6), 1), ((3, 5, 4, 6), 3), ((3, 5, 4, 6), 5), ((3, 5, 4, 6), 9),
-                                    ((16, 16, 8, 9), 1), ((16, 16, 8, 9), 5), ((16, 16, 6, 5), 3),
-                                    ((16, 16, 3, 4), 2)])
-def test_wilson_every_launch_shape(dims, k):
+@pytest.mark.parametrize("dims,k,scale", [((3, 5, 4, 6), 1, 1.0), ((3, 5, 4, 6), 3, 1.0), ((3, 5, 4, 6), 5, 1.0),
+                                          ((3, 5, 4, 6), 9, 1.0), ((16, 16, 8, 9), 1, 1.0), ((16, 16, 8, 9), 5, 1.0),
+                                          ((16, 16, 6, 5), 3, 1.0), ((16, 16, 3, 4), 2, 1.0),
+                                          ((3, 5, 4, 6), 3, 0.9), ((16, 16, 8, 9), 5, 0.9)])
+def test_wilson_every_launch_shape(dims, k, scale):
     # each stencil variant the autotuner may pick, pinned in turn, and k
     # columns (k = 5 and 9 leave partial column chunks): on a ragged lattice
     # (volume not a multiple of the 256-site tile), and on one whose time
@@ -182,9 +183,13 @@ def test_wilson_every_launch_shape(dims, k):
     # last time segment is partial; Z = 6 and 3: blocks of 4 and of 2 planes
     # do not divide Z, so those shapes take smaller plane groups); outputs
     # start as NaN so that a work item the launch skips cannot pass on stale
-    # memory
-    _say("wilson launch shapes", dims, "k", k)
-    U, op = _wilson(dims, cfg=8)
+    # memory.  SU(3) links (scale 1): the FP32 passes read two rows of each
+    # link and rebuild the third; links scaled by 0.9 are not in SU(3), so
+    # those passes read whole links.
+    _say("wilson launch shapes", dims, "k", k, "link scale", scale)
+    U = synth.su3_links(dims, synth.rng(8, 0)) * scale
+    op = api.Op.wilson(dims, torch.from_numpy(api.pack_links(U)).to(DEV), 0.12)
+    assert op.rebuild == (scale == 1.0), (op.su3_deviation, op.rebuild)
     x = synth.complex_gaussian(op.n, k, synth.rng(5, 2))
     X = _to_lib(x)
     fields = [x[:, j].reshape(dims[::-1] + (4, 3)) for j in range(k)]
@@ -577,14 +582,18 @@ def test_shortest_seeds(m):
                     assert abs(a - b) <= 2, (m, mixed, out["iters"], oits)
 
 
-def test_seed_alpha_beta_on_x16_lattice():
+@pytest.mark.parametrize("scale", [1.0, 0.9])
+def test_seed_alpha_beta_on_x16_lattice(scale):
     # on lattices with X = 16 the fused Lanczos passes take the x hops through
     # the lanes of an x-row (DPP) instead of loading the neighbours: the
-    # recurrence coefficients against the oracle's, FP64 and complex64 basis
+    # recurrence coefficients against the oracle's, FP64 and complex64 basis.
+    # SU(3) links (scale 1): the FP32 passes rebuild each link's third row;
+    # links scaled by 0.9: they read whole links.
     dims = (16, 16, 2, 3)
-    _say("seed alpha/beta on", dims)
-    U = synth.su3_links(dims, synth.rng(16, 0))
+    _say("seed alpha/beta on", dims, "link scale", scale)
+    U = synth.su3_links(dims, synth.rng(16, 0)) * scale
     op = api.Op.wilson(dims, torch.from_numpy(api.pack_links(U)).to(DEV), 0.12)
+    assert op.rebuild == (scale == 1.0)
     oop = ops.WilsonNormalOp(U, 0.12)
     b = synth.z4_noise(oop.n, 1, synth.rng(16, 1))
     m = 25
@@ -598,6 +607,37 @@ def test_seed_alpha_beta_on_x16_lattice():
         eb = np.abs(bb - ref.beta[: m + 1]).max() / np.abs(ref.beta[: m + 1]).max()
         _say("  ", vdt, "alpha err %.2e beta err %.2e" % (ea, eb))
         assert ea <= bar and eb <= bar, (vdt, ea, eb)
+
+
+def test_su3_check():
+    # the device check of the links against SU(3): its deviation against the
+    # same measure in numpy, and whether the FP32 passes rebuild row 2
+    dims = (4, 4, 4, 6)
+    U = synth.su3_links(dims, synth.rng(17, 0))
+
+    def dev_np(W):
+        I = np.eye(3)
+        uu = np.abs(W @ np.conj(np.swapaxes(W, -1, -2)) - I).max()
+        return max(uu, np.abs(np.linalg.det(W) - 1).max())
+
+    ph = np.exp(0.2j)  # a U(3) phase: unitary, det = exp(0.6 i)
+    Ub = U.copy()
+    Ub[1, 3, 2, 1, 0] *= ph
+    Un = U.copy()
+    Un[2, 0, 0, 0, 0, 1, 1] = np.nan
+    for name, W, single, want in [("su3", U, True, True), ("su3, no FP32 copy", U, False, False),
+                                  ("scaled 0.9", U * 0.9, True, False), ("one U(3) link", Ub, True, False),
+                                  ("a NaN", Un, True, False)]:
+        _say("su3 check:", name)
+        op = api.Op.wilson(dims, torch.from_numpy(api.pack_links(W)).to(DEV), 0.12, single=single, rebuild=False)
+        assert not op.rebuild
+        dev = op.check_su3()
+        assert op.rebuild == want, (name, dev)
+        if name == "a NaN":
+            assert dev == float("inf")
+        else:
+            ref = dev_np(W)
+            assert abs(dev - ref) <= 1e-13 + 1e-12 * ref, (name, dev, ref)
 
 
 def _seed_sentinel(op, b1, m, freq, vdt, sent=12345.0):
