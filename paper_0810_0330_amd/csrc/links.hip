@@ -2,8 +2,9 @@
 // which a link's third row is the complex conjugate of the cross product of
 // its first two, so that the single-precision passes may read two rows of each
 // link and rebuild the third (12 of the 18 reals of a link).
+#include <algorithm>
 #include <cmath>
-#include <cstring>
+#include <vector>
 
 #include "sc_internal.h"
 
@@ -15,14 +16,9 @@ constexpr int kLinkBlock = 256;
 
 // Largest over the 4V links of the entrywise moduli of U U^H - 1 and of
 // |det U - 1|, in FP64; +inf when a link holds a value that is not finite.
-// Each block reduces in LDS and folds its maximum into *out with a 64-bit
-// unsigned max on the value's bits (the order of non-negative doubles, +inf
-// included).
-__global__ __launch_bounds__(kLinkBlock) void k_su3_dev(const double* __restrict__ U, int64_t V,
-                                                        unsigned long long* out) {
-    __shared__ unsigned long long bm;
-    if (threadIdx.x == 0) bm = 0ull;
-    __syncthreads();
+// One maximum per block (an LDS tree), taken over the blocks on the host.
+__global__ __launch_bounds__(kLinkBlock) void k_su3_dev(const double* __restrict__ U, int64_t V, double* out) {
+    __shared__ double sm[kLinkBlock];
     double dev = 0.0;
     bool bad = false;
     const int64_t nl = 4 * V;
@@ -58,32 +54,32 @@ __global__ __launch_bounds__(kLinkBlock) void k_su3_dev(const double* __restrict
         bad |= isnan(m);
         dev = fmax(dev, m);
     }
-    if (bad || !isfinite(dev)) dev = INFINITY;
-    atomicMax(&bm, (unsigned long long)__double_as_longlong(dev));
+    sm[threadIdx.x] = (bad || !isfinite(dev)) ? INFINITY : dev;
     __syncthreads();
-    if (threadIdx.x == 0) atomicMax(out, bm);
+    for (int h = kLinkBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
 }
 
 }  // namespace
 
 sc_status wilson_check_su3(sc_op* op, hipStream_t s, double* deviation, int* rebuild) {
     const int64_t nl = 4 * op->vol;
-    const int grid = (int)std::min<int64_t>((nl + kLinkBlock - 1) / kLinkBlock, 4096);
-    unsigned long long* d = nullptr;
-    SC_HIP(hipMalloc((void**)&d, sizeof(unsigned long long)));
-    unsigned long long h = 0;
-    hipError_t e = hipMemsetAsync(d, 0, sizeof h, s);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_su3_dev, dim3(grid), dim3(kLinkBlock), 0, s, (const double*)op->U64, op->vol, d);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, s);
+    const int grid = (int)std::min<int64_t>((nl + kLinkBlock - 1) / kLinkBlock, 1024);
+    double* d = nullptr;
+    SC_HIP(hipMalloc((void**)&d, grid * sizeof(double)));
+    std::vector<double> h(grid, 0.0);
+    hipLaunchKernelGGL(k_su3_dev, dim3(grid), dim3(kLinkBlock), 0, s, (const double*)op->U64, op->vol, d);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, grid * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     const hipError_t ef = hipFree(d);
     SC_HIP(e);
     SC_HIP(ef);
-    double dev;
-    std::memcpy(&dev, &h, sizeof dev);
+    double dev = 0.0;
+    for (double v : h) dev = std::max(dev, v);  // no NaN: the kernel maps non-finite values to +inf
     op->su3 = (op->U32 && dev <= kSu3Tol) ? 1 : 0;
     if (deviation) *deviation = dev;
     if (rebuild) *rebuild = op->su3;
