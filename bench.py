@@ -697,6 +697,15 @@ def main():
             kd_["frac_of_hbm_peak"] = round(kd_["GBps"] / HBM_PEAK_GBS, 4)
 
     if roof is not None and w.op == "wilson" and roof["kernel"].startswith("wilson_f32"):
+        # links in SU(3): the FP32 passes read 12 of the 18 reals of each link; the algorithmic bytes above
+        # count whole links (72 reals per site), so also state them for two-row links (48 reals per site)
+        roof["links"] = "two rows read, third rebuilt (SU(3) check passed)" if op.rebuild else "whole"
+        if op.rebuild:
+            per_site = roof["bytes_per_launch"] / float(np.prod(w.dims))
+            two_row = roof["bytes_per_launch"] - 24 * 4 * float(np.prod(w.dims))
+            roof["bytes_per_launch_two_row_links"] = two_row
+            roof["frac_two_row_links"] = round(roof["frac"] * two_row / roof["bytes_per_launch"], 4)
+            roof["bytes_per_site"] = round(per_site, 1)
         kk = 1 if roof["kernel"].endswith("_k1") else w.nrhs
         v, _ = op.tune_info(kk, single=True)
         t = measured_traffic(roof["kernel"], kk, v, w.dims)
