@@ -125,8 +125,9 @@ sc_status sc_op_wilson_g5(const int dims[4], const void* U64_dev, const void* U3
  * change afterwards to values outside SU(3) unless this is called again.
  * Not part of the method: a smaller form of the data it reads.  Runs on
  * `stream`, allocates at most 8 KB of device memory for the duration of the call
- * and synchronizes the stream once.  Errors: SC_ERR_ARG for an op that is
- * not a Wilson operator; SC_ERR_HIP. */
+ * and synchronizes the stream once; it changes the op, so no other call may
+ * use the op meanwhile.  Errors: SC_ERR_ARG for an op that is not a Wilson
+ * operator; SC_ERR_HIP. */
 sc_status sc_op_wilson_check_su3(sc_op* op, void* stream, double* deviation, int* rebuild);
 
 sc_status sc_op_destroy(sc_op* op);
