@@ -83,38 +83,45 @@ std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;  // most recent last
 constexpr size_t kGraphCache = 32;  // seed graphs and per-system CG chunk graphs
 
+void key_put(GraphKey& k, const void* p, size_t n) {
+    const char* c = (const char*)p;
+    k.bytes.insert(k.bytes.end(), c, c + n);
+}
+
+// what a captured seed phase bakes in of its operator: the op's contents and
+// the stencil shape its one-column passes were tuned to
+void key_put_op(GraphKey& k, const sc_op* op, bool single) {
+    auto put = [&](const void* p, size_t n) { key_put(k, p, n); };
+    put(&op, sizeof op);
+    put(&op->gen, sizeof op->gen);
+    put(&op->kind, sizeof op->kind);
+    put(&op->n, sizeof op->n);
+    put(&op->dtype, sizeof op->dtype);
+    put(&op->nx, sizeof op->nx);
+    put(&op->ny, sizeof op->ny);
+    put(&op->d, sizeof op->d);
+    put(op->dims, sizeof op->dims);
+    put(&op->U64, sizeof op->U64);
+    put(&op->U32, sizeof op->U32);
+    put(&op->kappa, sizeof op->kappa);
+    put(&op->antiperiodic, sizeof op->antiperiodic);
+    put(&op->su3, sizeof op->su3);
+    int variant = -1;
+    if (has_links(op)) {
+        float us[SC_WILSON_VARIANTS];
+        (void)wilson_tune_query(op, single, 1, &variant, us);
+    }
+    put(&variant, sizeof variant);
+}
+
 GraphKey make_key(int nsys, const sc_batch_system* sys, const void* work, hipStream_t s) {
     GraphKey k;
-    auto put = [&](const void* p, size_t n) {
-        const char* c = (const char*)p;
-        k.bytes.insert(k.bytes.end(), c, c + n);
-    };
+    auto put = [&](const void* p, size_t n) { key_put(k, p, n); };
     put(&nsys, sizeof nsys);
     put(&work, sizeof work);
     put(&s, sizeof s);
     for (int i = 0; i < nsys; ++i) {
-        const sc_op* op = sys[i].op;
-        put(&op, sizeof op);
-        put(&op->gen, sizeof op->gen);
-        put(&op->kind, sizeof op->kind);
-        put(&op->n, sizeof op->n);
-        put(&op->dtype, sizeof op->dtype);
-        put(&op->nx, sizeof op->nx);
-        put(&op->ny, sizeof op->ny);
-        put(&op->d, sizeof op->d);
-        put(op->dims, sizeof op->dims);
-        put(&op->U64, sizeof op->U64);
-        put(&op->U32, sizeof op->U32);
-        put(&op->kappa, sizeof op->kappa);
-        put(&op->antiperiodic, sizeof op->antiperiodic);
-        put(&op->su3, sizeof op->su3);
-        // the stencil shape the seed phase's one-column passes were tuned to
-        int variant = -1;
-        if (has_links(op)) {
-            float us[SC_WILSON_VARIANTS];
-            (void)wilson_tune_query(op, sys[i].mixed != 0, 1, &variant, us);
-        }
-        put(&variant, sizeof variant);
+        key_put_op(k, sys[i].op, sys[i].mixed != 0);
         put(&sys[i].B_dev, sizeof sys[i].B_dev);
         put(&sys[i].ldb, sizeof sys[i].ldb);
         put(&sys[i].X_dev, sizeof sys[i].X_dev);
@@ -232,6 +239,76 @@ void batch_forget_op(const sc_op* op) {
             ++j;
         }
     }
+}
+
+// One system's seed phase (seed_enqueue_any) replayed on `s` from a cached
+// graph, captured on a private stream the first time these arguments come
+// (the caller's stream may be the null stream, which cannot capture).  The
+// key holds everything the captured launches bake in.  While `s` is itself
+// being captured the phase is launched directly into that capture.  The
+// operator's stencil shapes must be tuned beforehand (seed_pretune).
+sc_status seed_enqueue_cached(const sc_op* op, const void* b1, void* x1, int m, int freq, void* V, int64_t ldv,
+                              sc_dtype vdt, double* alpha, double* beta, const SeedWork& w, hipStream_t s,
+                              bool single) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    SC_HIP(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) return seed_enqueue_any(op, b1, x1, m, freq, V, ldv, vdt, alpha, beta, w, s);
+    GraphKey key;
+    const int tag = -1;  // batch keys start with their system count, >= 1
+    key_put(key, &tag, sizeof tag);
+    key_put(key, &s, sizeof s);
+    key_put_op(key, op, single);
+    for (const void* p : {b1, (const void*)x1, (const void*)V, (const void*)alpha, (const void*)beta})
+        key_put(key, &p, sizeof p);
+    key_put(key, &ldv, sizeof ldv);
+    key_put(key, &vdt, sizeof vdt);
+    key_put(key, &m, sizeof m);
+    key_put(key, &freq, sizeof freq);
+    key_put(key, &w, sizeof w);  // the workspace's carved pointers
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (size_t j = 0; j < g_graphs.size(); ++j)
+            if (g_graphs[j].key == key) {
+                exec = g_graphs[j].exec;
+                GraphEntry e = g_graphs[j];
+                g_graphs.erase(g_graphs.begin() + j);
+                g_graphs.push_back(e);
+                break;
+            }
+    }
+    if (!exec) {
+        hipStream_t cap = nullptr;
+        SC_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        sc_status st = SC_OK;
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            st = seed_enqueue_any(op, b1, x1, m, freq, V, ldv, vdt, alpha, beta, w, cap);
+            e = hipStreamEndCapture(cap, &graph);
+        }
+        (void)hipStreamDestroy(cap);
+        if (st != SC_OK || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            if (st != SC_OK) return st;
+            set_error(std::string("seed phase capture failed: ") + hipGetErrorString(e));
+            return SC_ERR_HIP;
+        }
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            set_error(std::string("seed phase graph instantiation failed: ") + hipGetErrorString(e));
+            return SC_ERR_HIP;
+        }
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        if (g_graphs.size() >= kGraphCache) {
+            (void)hipGraphExecDestroy(g_graphs.front().exec);
+            g_graphs.erase(g_graphs.begin());
+        }
+        g_graphs.push_back({key, exec, {op->gen}});
+    }
+    SC_HIP(hipGraphLaunch(exec, s));
+    return SC_OK;
 }
 
 size_t batch_workspace(int nsys, const sc_batch_system* sys) {

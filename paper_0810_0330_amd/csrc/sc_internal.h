@@ -202,6 +202,11 @@ sc_status solve_cg(const sc_op* op, int mixed, const void* B, int64_t ldb, void*
 // ---------------------------------------------------------------- batches (batch.hip)
 // drop every cached batch graph that was recorded for this op (called when the op is destroyed)
 void batch_forget_op(const sc_op* op);
+// seed_enqueue_any replayed from a cached graph (batch.hip); for small systems,
+// whose seed phase is a chain of short launches
+sc_status seed_enqueue_cached(const sc_op* op, const void* b1, void* x1, int m, int freq, void* V, int64_t ldv,
+                              sc_dtype vdt, double* alpha, double* beta, const SeedWork& w, hipStream_t s,
+                              bool single);
 
 // ---------------------------------------------------------------- multiple seeding (multiseed.hip)
 size_t multiseed_workspace(const sc_op* op, int k);

@@ -583,9 +583,13 @@ static sc_status seed_enqueue(const sc_op* op, const void* b1, void* x1, int m, 
     hipLaunchKernelGGL(k_seed_init, dim3(1), dim3(1), 0, s, w.st);
     SC_LAUNCH_CHECK();
 
-    // step 1: r0 = b1 - A x0 (FP64)
-    SC_TRY(op_apply(op, false, x1, op->n, w.ax64, op->n, 1, w.tmp64, s));
-    SC_TRY(lincomb(0, w.r64, N2, 0, b1, N2, 0, w.ax64, N2, N2, 1, 1.0, -1.0, s));
+    // step 1: r0 = b1 - A x0 (FP64); x1 == nullptr stands for x0 = 0, which is then not read
+    if (x1) {
+        SC_TRY(op_apply(op, false, x1, op->n, w.ax64, op->n, 1, w.tmp64, s));
+        SC_TRY(lincomb(0, w.r64, N2, 0, b1, N2, 0, w.ax64, N2, N2, 1, 1.0, -1.0, s));
+    } else {
+        SC_TRY(lincomb(0, w.r64, N2, 0, b1, N2, 0, b1, N2, N2, 1, 1.0, 0.0, s));
+    }
     // step 2: beta_0 = ||r0||, v_1 = r0 / beta_0
     hipLaunchKernelGGL((k_norm_part<double, VEC>), dim3(g), blk, 0, s, w.r64, N2, w.part_f, nullptr);
     SC_LAUNCH_CHECK();

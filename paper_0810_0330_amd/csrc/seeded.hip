@@ -19,6 +19,11 @@ namespace {
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Systems whose vectors hold at most this many reals run their seed phase from
+// a cached graph: each Lanczos step is then a chain of launches of a few
+// microseconds of work, and the launches, not the kernels, set its time.
+constexpr int64_t kSeedGraphMax = int64_t(1) << 20;
+
 struct SeededPlan {
     size_t v_off, a_off, b_off, seed_off, seed_bytes, g_off, y_off, part_off, trid_off, cg_off, cg_bytes, total;
     int ngroups;
@@ -125,7 +130,14 @@ sc_status seeded_solve(const sc_op* op, int mixed, const void* B, int64_t ldb, v
         }
         return SC_OK;
     };
-    SC_TRY(seed_enqueue_any(op, B, X, m, freq, V, op->n, p.vdt, alpha, beta, sw, s));
+    // a small system's seed phase is a chain of short launches: replay it from a
+    // cached graph (its kernels are then not seen by the in-library timer).  X
+    // is zero here, so the phase gets x0 = 0 without a pointer to X, which
+    // would tie the graph to the caller's output buffer.
+    if (N2 <= kSeedGraphMax)
+        SC_TRY(seed_enqueue_cached(op, B, nullptr, m, freq, V, op->n, p.vdt, alpha, beta, sw, s, mixed != 0));
+    else
+        SC_TRY(seed_enqueue_any(op, B, X, m, freq, V, op->n, p.vdt, alpha, beta, sw, s));
     sc_status seed_status = SC_OK;
     SC_TRY(seed_finalize_any(op, X, V, op->n, p.vdt, alpha, beta, m_done, sw, s, &seed_status, false));
     if (seed_status == SC_ERR_NOT_PD || seed_status == SC_ERR_NONFINITE) {
