@@ -164,6 +164,7 @@ GraphKey make_cg_key(const sc_batch_system& b, const void* cg_work, int cur) {
     put(&op->U32, sizeof op->U32);
     put(&op->kappa, sizeof op->kappa);
     put(&op->antiperiodic, sizeof op->antiperiodic);
+    put(&op->su3, sizeof op->su3);  // the FP32 passes' link form
     int variant = -1;
     if (has_links(op)) {
         float us[SC_WILSON_VARIANTS];

@@ -156,3 +156,41 @@ def test_batch_graph_cache_follows_the_operator():
         del op, r, alone
         gc.collect()
     assert np.abs(outs[0] - outs[1]).max() > 1e-3 * np.abs(outs[0]).max()
+
+
+def test_graph_caches_follow_the_link_form():
+    # the cached graphs (the one-call driver's seed phase, the batch's seed
+    # phases and CG chunks) bake in whether the FP32 passes rebuild row 2 of
+    # the links: after the op's links are scaled in place (no longer SU(3)) and
+    # checked again, every path must give what a fresh op on the scaled links
+    # gives, bit for bit
+    print("graph caches and the link form", flush=True)
+    dims = (4, 4, 4, 4)
+    U = synth.su3_links(dims, synth.rng(23, 0))
+    Bw = _lib(synth.point_sources(dims, synth.ALL_SPIN_COLOUR[:3]))
+    op = api.Op.wilson(dims, torch.from_numpy(api.pack_links(U)).to(DEV), 0.12)
+    assert op.rebuild
+
+    def run(o):
+        one = api.single_seed_solve(o, Bw, 40, 1, 1e-9, mixed=True)
+        bat = api.batch_solve([{"op": o, "B": Bw, "m": 40, "freq": 10, "tol": 1e-9, "mixed": True}])[0]
+        torch.cuda.synchronize()
+        return one, bat
+
+    run(op)  # records the graphs with two-row link reads
+    U64, U32 = op._keep
+    U64.mul_(0.9)
+    U32.copy_(U64.to(torch.complex64))
+    op.check_su3()
+    assert not op.rebuild
+    one, bat = run(op)
+    fresh = api.Op.wilson(dims, torch.from_numpy(api.pack_links(U * 0.9)).to(DEV), 0.12)
+    assert not fresh.rebuild
+    one_f, bat_f = run(fresh)
+    assert one["iters"] == one_f["iters"] and torch.equal(one["X"], one_f["X"])
+    assert bat["iters"] == bat_f["iters"] and torch.equal(bat["X"], bat_f["X"])
+    oop = ops.WilsonNormalOp(U * 0.9, 0.12)
+    X = api.unpack_field(one["X"].cpu().numpy()).T
+    B = synth.point_sources(dims, synth.ALL_SPIN_COLOUR[:3])
+    for j in range(3):
+        assert np.linalg.norm(B[:, j] - oop(X[:, j])) / np.linalg.norm(B[:, j]) <= 1e-9
